@@ -1,0 +1,233 @@
+/*
+ * inpaint.h -- C ABI of libinpaint.so: exemplar-based object removal
+ * (Criminisi-style best-first patch filling) on AMD Instinct MI355X (gfx950).
+ *
+ * The method (paper, Section 3): a source image S has a target region (hole)
+ * Omega to fill; Phi = S - Omega is the known region.  Each iteration
+ *   1. finds the fill front dOmega (hole pixels next to known pixels),
+ *   2. scores each front pixel p with the priority P(p) = C(p) * D(p)
+ *      (confidence term times data term, Eq. 1 and Eq. 2) and takes the
+ *      maximum,
+ *   3. searches the source region for the patch that minimises the sum of
+ *      squared RGB differences to the known pixels of the patch around p
+ *      (findBestPatch, Eq. 3 and Eq. 4),
+ *   4. copies that patch's pixels into the hole pixels of p's patch, which
+ *      take p's confidence,
+ * until the hole is empty.  The search may be restricted to a window around
+ * the hole (search factor alpha, Section 5.3, Eq. 6).
+ *
+ * Conventions for every call:
+ *   - Every function returns an int32_t status (INPAINT_OK, INPAINT_DONE or a
+ *     negative error).  Outputs are written only on success.  No C++
+ *     exception crosses the ABI.
+ *   - Pixel (x, y) has raster index y * width + x.  Rectangles are half-open
+ *     [x0, x1) x [y0, y1).
+ *   - A patch has radius r (1 <= r <= 8) and side P = 2r + 1.
+ *   - Device memory passed in (workspaces) is owned by the caller and must
+ *     outlive the object using it; host buffers are only read or written
+ *     during the call.
+ *   - All device work of a context is enqueued on the hipStream_t given at
+ *     creation.  Calls documented as synchronising wait for that stream.
+ *   - A context or batch must not be used by two threads at once; distinct
+ *     contexts may be used concurrently from different threads.
+ *   - INPAINT_DEVICE is sticky: after a device error the context only
+ *     accepts inpaint_destroy and inpaint_last_error.
+ *
+ * Exact-arithmetic contract: exemplar indices, SSDs and output images are
+ * bit-exact integers; priorities are IEEE binary64 computed in one fixed
+ * operation order with no fused multiply-add, so the fill order is
+ * reproducible on any IEEE machine that follows the same order.
+ */
+#ifndef INPAINT_H
+#define INPAINT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define INPAINT_OK                0
+#define INPAINT_DONE              1   /* not an error: the hole is empty      */
+#define INPAINT_INVALID_ARGUMENT (-1)
+#define INPAINT_NO_CANDIDATE     (-2) /* no valid source centre in the rect   */
+#define INPAINT_OUT_OF_MEMORY    (-3) /* workspace too small / host alloc     */
+#define INPAINT_DEVICE           (-4) /* HIP error; the context is unusable   */
+
+/* ------------------------------------------------------------- parameters */
+#define INPAINT_SEARCH_FULL  0   /* every valid centre of the image          */
+#define INPAINT_SEARCH_ALPHA 1   /* window around the hole, Eq. 6            */
+#define INPAINT_SEARCH_RECT  2   /* caller-given rectangle of centres        */
+
+#define INPAINT_PATH_AUTO 0
+#define INPAINT_PATH_SIMT 1      /* integer dot-product SSD on the VALU      */
+#define INPAINT_PATH_MFMA 2      /* int8 matrix-core cross term (exact)      */
+
+typedef struct {
+    const uint8_t *data;   /* host pixels, row-major, 8 bits per channel     */
+    int32_t width;
+    int32_t height;
+    int32_t stride_bytes;  /* bytes between rows (>= width * channels)       */
+    int32_t channels;      /* 3 (RGB) or 4 (RGBA/RGBX; the 4th is ignored)  */
+} inpaint_image;
+
+typedef struct {
+    int32_t x0, y0, x1, y1;   /* half-open, in candidate-centre coordinates */
+} inpaint_rect;
+
+typedef struct {
+    int32_t patch_radius;  /* r, 1..8; the paper's patch size P = 2r + 1     */
+    int32_t search_mode;   /* INPAINT_SEARCH_*                               */
+    int32_t alpha_num;     /* search factor alpha = alpha_num / alpha_den,  */
+    int32_t alpha_den;     /*   used by INPAINT_SEARCH_ALPHA (alpha >= 0)   */
+    inpaint_rect rect;     /* used by INPAINT_SEARCH_RECT; clipped to image */
+    int32_t path;          /* INPAINT_PATH_*                                 */
+    int32_t graph_iters;   /* inpaint_run: 0 = plain form (two launches per  */
+                           /*   iteration, host checks termination after    */
+                           /*   each); N > 0 = replay a captured hipGraph of */
+                           /*   N iterations, host checks after each replay */
+    int32_t log_capacity;  /* device log records kept (>= 0); -1 = one per   */
+                           /*   hole pixel, which covers any run            */
+    int32_t tile_rows;     /* search tile: candidate rows per thread (0 =   */
+                           /*   default; 4, 8 or 16)                        */
+    int32_t reserved[4];   /* must be zero                                   */
+} inpaint_params;
+
+/* One fill iteration (64 bytes). */
+typedef struct {
+    int64_t target_index;  /* front pixel p^ that was filled                 */
+    int64_t source_index;  /* centre q^ of the copied source patch           */
+    uint32_t ssd;          /* d(Psi_p^, Psi_q^), Eq. 4                        */
+    int32_t known_k;       /* known pixels in the target patch               */
+    int32_t n_filled;      /* hole pixels filled                             */
+    int32_t reserved;
+    double priority;       /* P(p^) = C(p^) D(p^)                             */
+    double confidence;     /* C(p^)                                          */
+    double data_term;      /* D(p^)                                          */
+    int64_t remaining;     /* hole pixels left after this iteration          */
+} inpaint_step_info;
+
+typedef struct inpaint_ctx inpaint_ctx;
+typedef struct inpaint_batch inpaint_batch;
+
+/* ----------------------------------------------------------- single image */
+
+/* Device bytes one job of width x height with params *p needs; this is also
+ * its footprint for admission in a serving loop.  INVALID_ARGUMENT for sizes
+ * below the patch or a bad radius. */
+int32_t inpaint_workspace_bytes(int32_t width, int32_t height, const inpaint_params *p,
+                                uint64_t *bytes);
+
+/* Initialisation stage (Section 4.2): uploads the image and the mask
+ * (nonzero = pixel of the object to remove, i.e. the hole Omega_0) into the
+ * caller's device workspace, zeroes the hole pixels, builds the gray image,
+ * the confidence map (1 on the known region, 0 in the hole), the validity map
+ * of source centres (whole patch inside the image and inside the ORIGINAL
+ * known region) and the initial priorities, and selects the first target.
+ * The host buffers may be freed on return.  d_workspace must be 256-byte
+ * aligned, at least inpaint_workspace_bytes large, and stay allocated until
+ * inpaint_destroy.  hip_stream is a hipStream_t (NULL = default stream).
+ * Synchronises.  Errors: INVALID_ARGUMENT (bad sizes or params, empty hole,
+ * no known pixel, no valid source centre in the search rectangle),
+ * OUT_OF_MEMORY (workspace too small), DEVICE. */
+int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t mask_stride,
+                       const inpaint_params *p, void *d_workspace, uint64_t ws_bytes,
+                       void *hip_stream, inpaint_ctx **out);
+
+/* findBestPatch (Alg. 1, Eq. 3-4) as a pure query on the current state: the
+ * centre q in search_rect (clipped to the image) whose whole patch of radius
+ * patch_radius lies in the image and the original known region, minimising
+ * the SSD over R, G, B of the target patch's known pixels; ties go to the
+ * lowest raster index.  Does not change the state.  Synchronises.
+ * Errors: INVALID_ARGUMENT (target outside the image, radius out of 1..8,
+ * x0 > x1 or y0 > y1), NO_CANDIDATE (no valid centre in the rect). */
+int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t target_x, int32_t target_y,
+                              int32_t patch_radius, inpaint_rect search_rect,
+                              int64_t *source_index, uint32_t *ssd);
+
+/* One iteration (front, priority, search, copy) with the context's search
+ * rectangle.  Fills *info (may be NULL).  Returns INPAINT_DONE without work
+ * if the hole is already empty.  Synchronises. */
+int32_t inpaint_step(inpaint_ctx *ctx, inpaint_step_info *info);
+
+/* Iterates until the hole is empty or max_iters iterations (max_iters < 0:
+ * no limit) have run, in the form chosen by params.graph_iters.  Writes the
+ * number of iterations run to *iters_done and, when log is not NULL, the
+ * first min(log_cap, iterations, log capacity) records of this call.  Returns
+ * INPAINT_DONE when the hole is empty, INPAINT_OK when stopped by max_iters.
+ * Synchronises. */
+int32_t inpaint_run(inpaint_ctx *ctx, int64_t max_iters, int64_t *iters_done,
+                    inpaint_step_info *log, int64_t log_cap);
+
+/* Records [first, first + count) of the device log (records are numbered from
+ * the context's first iteration).  INVALID_ARGUMENT if outside what the log
+ * holds.  Synchronises. */
+int32_t inpaint_read_log(inpaint_ctx *ctx, int64_t first, int64_t count, inpaint_step_info *out);
+
+/* Copies the current RGB image to host rows of `stride` bytes (3 bytes per
+ * pixel).  Synchronises. */
+int32_t inpaint_read_image(inpaint_ctx *ctx, uint8_t *rgb, int32_t stride);
+
+/* Copies the current hole (1 = still to fill) and confidence maps, each
+ * width*height row-major; either pointer may be NULL.  Synchronises. */
+int32_t inpaint_read_state(inpaint_ctx *ctx, uint8_t *mask, double *conf);
+
+/* Hole pixels still to fill.  Synchronises. */
+int32_t inpaint_remaining(inpaint_ctx *ctx, int64_t *remaining);
+
+/* The context's search rectangle after clipping (alpha windows resolved) and
+ * the number of valid source centres in it, i.e. patch evaluations per
+ * search.  No device work. */
+int32_t inpaint_search_info(const inpaint_ctx *ctx, inpaint_rect *rect, int64_t *candidates);
+
+/* Releases the context (not the caller's workspace).  Waits for its work. */
+int32_t inpaint_destroy(inpaint_ctx *ctx);
+
+const char *inpaint_status_string(int32_t status);
+/* Last error message of ctx ("" if none); valid until the next call on ctx.
+ * With ctx == NULL, the last error of a failed inpaint_create on this
+ * thread. */
+const char *inpaint_last_error(const inpaint_ctx *ctx);
+
+/* ------------------------------------------------------------------ batch */
+
+/* Many images advanced together: each batch iteration runs, for every
+ * attached unfinished image, one fill iteration.  The search runs as a
+ * persistent kernel pulling (image, tile) items from a static work list; the
+ * per-image front/priority/copy step runs one work-group per image.  G
+ * iterations are captured once into a hipGraph and replayed. */
+typedef struct {
+    int32_t capacity;        /* maximum attached contexts (slots), >= 1     */
+    int32_t graph_iters;     /* G: iterations per replay, >= 1              */
+    int32_t autotune;        /* 1 = time tile shapes and the persistent grid */
+                             /*   on first use, 0 = defaults                */
+    int32_t reserved;
+    const char *tune_cache;  /* JSON file caching autotuned choices, or NULL */
+} inpaint_batch_params;
+
+/* Allocates the batch's small device tables (slot table, work list) with
+ * hipMalloc.  hip_stream as for inpaint_create. */
+int32_t inpaint_batch_create(const inpaint_batch_params *bp, void *hip_stream,
+                             inpaint_batch **out);
+
+/* Attaches a created context to a free slot (returned in *slot, may be
+ * NULL).  Legal only between inpaint_batch_step calls.  The context must use
+ * the batch's stream or a stream the caller orders with it.
+ * INVALID_ARGUMENT when full or already attached. */
+int32_t inpaint_batch_attach(inpaint_batch *b, inpaint_ctx *ctx, int32_t *slot);
+
+/* Detaches a context (finished or not); its state stays readable. */
+int32_t inpaint_batch_detach(inpaint_batch *b, inpaint_ctx *ctx);
+
+/* Runs G iterations for every attached image and writes the number of
+ * attached images still unfinished to *active.  Synchronises once. */
+int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active);
+
+int32_t inpaint_batch_destroy(inpaint_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INPAINT_H */

@@ -1,0 +1,117 @@
+// Device-side state of one removal job and the kernel entry points of
+// libinpaint.so.  Included by the HIP kernel sources and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "inpaint.h"
+
+namespace inpaint {
+
+constexpr int kMaxRadius = 8;
+constexpr int kMaxPatch = 2 * kMaxRadius + 1;          // 17
+constexpr int kMaxOffsets = kMaxPatch * kMaxPatch;     // 289
+constexpr int kMaskWords = (kMaxOffsets + 31) / 32;    // 10
+constexpr int kBlock = 32;                             // priority block side
+constexpr int kTileW = 64;                             // search tile width (one wave)
+constexpr int kSearchWaves = 4;                        // waves per search work-group
+constexpr int kCommitThreads = 1024;
+
+// Target patch as the search kernels read it.  Offset o = (dx, dy) has slot
+// (dy + r) * P + (dx + r).  tpix holds the target's RGBX word (X = 0) where
+// the pixel is known and 0 elsewhere; bit `slot` of mbits is 1 where known.
+struct alignas(256) TargetStage {
+    int32_t tx, ty, r, k;
+    uint32_t t2;                 // sum over known pixels of R^2 + G^2 + B^2
+    uint32_t pad0[3];
+    uint32_t mbits[16];
+    uint32_t tpix[kMaxOffsets + 15];
+};
+
+// One fill-iteration record, same layout as inpaint_step_info.
+struct StepRec {
+    int64_t target_index, source_index;
+    uint32_t ssd;
+    int32_t known_k, n_filled, reserved;
+    double priority, confidence, data_term;
+    int64_t remaining;
+};
+static_assert(sizeof(StepRec) == sizeof(inpaint_step_info), "record layout");
+
+struct alignas(256) IterState {
+    int64_t remaining;   // hole pixels left
+    int64_t iter;        // iterations committed so far
+    int64_t iter_limit;  // commits stop (without finishing) at this count
+    int32_t done;        // 1 once the hole is empty
+    int32_t error;       // INPAINT_* error seen on the device, 0 if none
+    int32_t pending;     // 1 while a target is staged awaiting its search
+    int32_t pad0;
+    int64_t p_idx;       // staged target pixel
+    double C, D, Pr;     // its confidence, data term and priority
+    StepRec last;        // record of the last committed iteration
+};
+
+// Per-block maximum of the priority keys: larger key wins, ties go to the
+// lower raster index.  key = bit pattern of the (non-negative) priority for
+// front pixels, -1 elsewhere.
+struct BlockBest {
+    int64_t key;
+    int64_t idx;
+};
+
+struct InitInfo {
+    int64_t hole_count;
+    int32_t bx0, by0, bx1, by1;  // bounding box of the hole, half-open
+    int64_t valid_count;         // valid source centres in the search rect
+};
+
+// Everything a kernel needs about one job.  Passed by value to the
+// single-image kernels and stored in the slot table for batched ones.
+struct JobDev {
+    uint32_t *img;       // RGBX, W*H
+    uint8_t *gray;       // W*H
+    uint8_t *hole;       // W*H, 1 = still to fill
+    uint8_t *vrad;       // W*H, largest r <= 8 with a valid patch at the centre
+    double *conf;        // W*H
+    int64_t *pkey;       // W*H priority keys
+    BlockBest *blk;      // ceil(W/32)*ceil(H/32)
+    uint64_t *partials;  // one (ssd << 32 | index) per search tile
+    TargetStage *tgt;    // staged target of the fill loop
+    TargetStage *qtgt;   // staged target of inpaint_find_exemplar
+    IterState *st;
+    StepRec *log;
+    InitInfo *info;
+    int32_t W, H, r, log_cap;
+    int32_t rx0, ry0, rx1, ry1;   // search rect of centres (clipped)
+    int32_t pbx0, pby0, pbx1, pby1;  // priority block range (block units)
+    int32_t nbw;                  // blocks per image row
+    int32_t tile_rows;            // candidate rows per thread in the search
+    int32_t ntx, nty;             // search tiles over the rect
+    double norm1, norm2;          // 255 * |n| for |n|^2 = 1 and 2
+};
+
+// (image slot, tile) work item of the batched persistent search.
+struct WorkItem {
+    int32_t slot;
+    int32_t tile;
+};
+
+// ---- launchers (defined in the .hip files) ----
+hipError_t launch_init(const JobDev &d, const uint8_t *stage_rgb, int channels,
+                       const uint8_t *stage_mask, uint8_t *hdist, hipStream_t s);
+hipError_t launch_count_valid(const JobDev &d, hipStream_t s);
+hipError_t launch_prio_init(const JobDev &d, hipStream_t s);
+hipError_t launch_commit(const JobDev &d, hipStream_t s);
+hipError_t launch_search(const JobDev &d, bool query, int r, int rx0, int ry0, int rx1, int ry1,
+                         int tile_rows, int ntx, int nty, hipStream_t s);
+hipError_t launch_stage_query(const JobDev &d, int tx, int ty, int r, hipStream_t s);
+hipError_t launch_reduce_partials(const JobDev &d, int ntiles, uint64_t *out, hipStream_t s);
+hipError_t launch_commit_batched(const JobDev *slots, int nslots, hipStream_t s);
+hipError_t launch_count_active(const JobDev *slots, int nslots, int64_t *out, hipStream_t s);
+hipError_t launch_search_batched(const JobDev *slots, const WorkItem *items, const int32_t *nitems,
+                                 int r, int tile_rows, int grid, hipStream_t s);
+
+inline int search_tile_h(int tile_rows) { return kSearchWaves * tile_rows; }
+
+}  // namespace inpaint

@@ -1,0 +1,904 @@
+// Host runtime of libinpaint.so: the C ABI of include/inpaint.h.
+//
+// A context owns no device memory of its own: every device buffer of a job is
+// carved out of the caller's workspace (a torch tensor in the Python
+// binding), so the caller's allocator and a serving loop's admission see the
+// exact footprint.  Device work runs on the caller's stream.  The only
+// allocations the library makes are small pinned host mirrors of the
+// iteration state, and, for a batch, its slot table and work lists.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "inpaint.h"
+#include "inpaint_dev.h"
+
+using namespace inpaint;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr uint64_t kAlign = 256;
+constexpr int kDefaultTileRows = 8;
+
+uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    uint64_t img, gray, hole, vrad, conf, pkey, blk, partials, tgt, qtgt, st, info, key, log, total;
+    int64_t log_cap;
+    int max_tiles;
+};
+
+bool tile_rows_ok(int t) { return t == 4 || t == 8 || t == 16; }
+
+int64_t log_capacity(int W, int H, const inpaint_params &p) {
+    return p.log_capacity < 0 ? (int64_t)W * H : (int64_t)p.log_capacity;
+}
+
+Layout make_layout(int W, int H, const inpaint_params &p) {
+    Layout L{};
+    const uint64_t n = (uint64_t)W * H;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t o = off;
+        off = align_up(off + std::max<uint64_t>(bytes, 1));
+        return o;
+    };
+    L.img = take(4 * n);
+    L.gray = take(n);
+    L.hole = take(n);
+    L.vrad = take(n);
+    L.conf = take(8 * n);
+    L.pkey = take(8 * n);  // also the upload staging area during create (<= 6n bytes)
+    const uint64_t nblk = (uint64_t)((W + kBlock - 1) / kBlock) * ((H + kBlock - 1) / kBlock);
+    L.blk = take(sizeof(BlockBest) * nblk);
+    L.max_tiles = ((W + kTileW - 1) / kTileW) * ((H + search_tile_h(4) - 1) / search_tile_h(4));
+    L.partials = take(8ull * L.max_tiles);
+    L.tgt = take(sizeof(TargetStage));
+    L.qtgt = take(sizeof(TargetStage));
+    L.st = take(sizeof(IterState));
+    L.info = take(sizeof(InitInfo));
+    L.key = take(8);
+    L.log_cap = log_capacity(W, H, p);
+    L.log = take(sizeof(StepRec) * (uint64_t)L.log_cap);
+    L.total = off;
+    return L;
+}
+
+const char *status_name(int32_t s) {
+    switch (s) {
+        case INPAINT_OK: return "ok";
+        case INPAINT_DONE: return "done";
+        case INPAINT_INVALID_ARGUMENT: return "invalid argument";
+        case INPAINT_NO_CANDIDATE: return "no valid source centre in the search rectangle";
+        case INPAINT_OUT_OF_MEMORY: return "out of memory";
+        case INPAINT_DEVICE: return "device error";
+        default: return "unknown status";
+    }
+}
+
+// Alpha-window axis (Eq. 6): the object spans [b0, b1) on an axis of length n;
+// the window is round_half_up((1 + 2 alpha) * w) wide, the extra split with the
+// smaller half on the low side, clipped to [0, n).
+void alpha_axis(int b0, int b1, int n, int an, int ad, int *lo, int *hi) {
+    const int64_t w = b1 - b0;
+    const int64_t num = w * (ad + 2 * (int64_t)an);
+    const int64_t total = (2 * num + ad) / (2 * (int64_t)ad);
+    const int64_t extra = total - w;
+    const int64_t e_lo = extra / 2, e_hi = extra - e_lo;
+    *lo = (int)std::max<int64_t>(0, b0 - e_lo);
+    *hi = (int)std::min<int64_t>(n, b1 + e_hi);
+}
+
+}  // namespace
+
+struct inpaint_ctx {
+    JobDev d{};
+    inpaint_params p{};
+    Layout L{};
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    uint8_t *ws = nullptr;
+    int64_t hole0 = 0;
+    int64_t candidates = 0;
+    inpaint_rect rect{};      // image-clipped search rect (reported)
+    int32_t sticky = 0;
+    std::string err;
+    IterState *h_state = nullptr;   // pinned mirror of the device state
+    uint64_t *h_key = nullptr;      // pinned
+    hipGraphExec_t graph = nullptr;
+    int graph_n = 0;
+    inpaint_batch *batch = nullptr;
+
+    int32_t fail(int32_t st, const std::string &msg) {
+        err = msg;
+        return st;
+    }
+    int32_t hip_fail(hipError_t e, const char *what) {
+        sticky = INPAINT_DEVICE;
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return INPAINT_DEVICE;
+    }
+    // Reads the device iteration state into the pinned mirror (synchronous).
+    hipError_t pull_state() {
+        hipError_t e = hipMemcpyAsync(h_state, d.st, sizeof(IterState), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        return e;
+    }
+    hipError_t set_limit(int64_t limit) {
+        h_state->iter_limit = limit;
+        return hipMemcpyAsync(&d.st->iter_limit, &h_state->iter_limit, sizeof(int64_t),
+                              hipMemcpyHostToDevice, stream);
+    }
+};
+
+#define HIP_OR_FAIL(ctx, expr, what)                  \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return (ctx)->hip_fail(e_, what); \
+    } while (0)
+
+extern "C" {
+
+const char *inpaint_status_string(int32_t status) { return status_name(status); }
+
+const char *inpaint_last_error(const inpaint_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+static int32_t check_params(int32_t W, int32_t H, const inpaint_params *p, std::string *why) {
+    if (!p) {
+        *why = "params is NULL";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    if (p->patch_radius < 1 || p->patch_radius > kMaxRadius) {
+        *why = "patch_radius must be in 1..8";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    const int P = 2 * p->patch_radius + 1;
+    if (W < P || H < P) {
+        *why = "image smaller than the patch";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    if ((int64_t)W * H >= (1ll << 31)) {
+        *why = "image has 2^31 pixels or more";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    if (p->search_mode < INPAINT_SEARCH_FULL || p->search_mode > INPAINT_SEARCH_RECT) {
+        *why = "unknown search_mode";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    if (p->search_mode == INPAINT_SEARCH_ALPHA && (p->alpha_num < 0 || p->alpha_den <= 0)) {
+        *why = "alpha must be a non-negative rational with positive denominator";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    if (p->search_mode == INPAINT_SEARCH_RECT && (p->rect.x0 > p->rect.x1 || p->rect.y0 > p->rect.y1)) {
+        *why = "search rect has x0 > x1 or y0 > y1";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    if (p->path < INPAINT_PATH_AUTO || p->path > INPAINT_PATH_MFMA) {
+        *why = "unknown path";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    if (p->graph_iters < 0 || p->log_capacity < -1) {
+        *why = "graph_iters must be >= 0 and log_capacity >= -1";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    if (p->tile_rows != 0 && !tile_rows_ok(p->tile_rows)) {
+        *why = "tile_rows must be 0, 4, 8 or 16";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    for (int i = 0; i < 4; ++i)
+        if (p->reserved[i] != 0) {
+            *why = "reserved fields must be zero";
+            return INPAINT_INVALID_ARGUMENT;
+        }
+    return INPAINT_OK;
+}
+
+int32_t inpaint_workspace_bytes(int32_t W, int32_t H, const inpaint_params *p, uint64_t *bytes) {
+    std::string why;
+    const int32_t st = check_params(W, H, p, &why);
+    if (st != INPAINT_OK) return st;
+    if (!bytes) return INPAINT_INVALID_ARGUMENT;
+    *bytes = make_layout(W, H, *p).total;
+    return INPAINT_OK;
+}
+
+// Kernel rectangle of candidate centres: the image-clipped rect further
+// clipped to [r, W - r) x [r, H - r), outside of which no centre is valid.
+static void kernel_rect(int W, int H, int r, const inpaint_rect &img_rect, int *k) {
+    k[0] = std::max(img_rect.x0, r);
+    k[1] = std::max(img_rect.y0, r);
+    k[2] = std::min(img_rect.x1, W - r);
+    k[3] = std::min(img_rect.y1, H - r);
+}
+
+static void set_tiles(JobDev &d, int tile_rows) {
+    d.tile_rows = tile_rows;
+    const int rw = std::max(d.rx1 - d.rx0, 0), rh = std::max(d.ry1 - d.ry0, 0);
+    d.ntx = (rw + kTileW - 1) / kTileW;
+    d.nty = (rh + search_tile_h(tile_rows) - 1) / search_tile_h(tile_rows);
+    if (rw == 0 || rh == 0) d.ntx = d.nty = 0;
+}
+
+static int32_t create_fail(inpaint_ctx *c, int32_t st, const std::string &msg) {
+    g_create_error = msg;
+    if (c) {
+        if (c->stream) hipStreamSynchronize(c->stream);
+        if (c->h_state) hipHostFree(c->h_state);
+        if (c->h_key) hipHostFree(c->h_key);
+        if (c->cap_stream) hipStreamDestroy(c->cap_stream);
+        delete c;
+    }
+    return st;
+}
+
+int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t mask_stride,
+                       const inpaint_params *p, void *d_workspace, uint64_t ws_bytes, void *hip_stream,
+                       inpaint_ctx **out) {
+    g_create_error.clear();
+    if (!img || !img->data || !mask || !out || !d_workspace)
+        return create_fail(nullptr, INPAINT_INVALID_ARGUMENT, "NULL argument");
+    const int W = img->width, H = img->height, ch = img->channels;
+    std::string why;
+    int32_t st = check_params(W, H, p, &why);
+    if (st != INPAINT_OK) return create_fail(nullptr, st, why);
+    if (ch != 3 && ch != 4) return create_fail(nullptr, INPAINT_INVALID_ARGUMENT, "channels must be 3 or 4");
+    if (img->stride_bytes < W * ch || mask_stride < W)
+        return create_fail(nullptr, INPAINT_INVALID_ARGUMENT, "row stride smaller than the row");
+    if (((uintptr_t)d_workspace) % kAlign != 0)
+        return create_fail(nullptr, INPAINT_INVALID_ARGUMENT, "workspace not 256-byte aligned");
+    const Layout L = make_layout(W, H, *p);
+    if (ws_bytes < L.total) return create_fail(nullptr, INPAINT_OUT_OF_MEMORY, "workspace too small");
+
+    inpaint_ctx *c = new (std::nothrow) inpaint_ctx();
+    if (!c) return create_fail(nullptr, INPAINT_OUT_OF_MEMORY, "host allocation failed");
+    c->p = *p;
+    c->L = L;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (uint8_t *)d_workspace;
+    if (hipHostMalloc((void **)&c->h_state, sizeof(IterState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&c->h_key, 64, hipHostMallocDefault) != hipSuccess)
+        return create_fail(c, INPAINT_OUT_OF_MEMORY, "pinned host allocation failed");
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return create_fail(c, INPAINT_DEVICE, "stream creation failed");
+
+    JobDev &d = c->d;
+    uint8_t *ws = c->ws;
+    d.img = (uint32_t *)(ws + L.img);
+    d.gray = ws + L.gray;
+    d.hole = ws + L.hole;
+    d.vrad = ws + L.vrad;
+    d.conf = (double *)(ws + L.conf);
+    d.pkey = (int64_t *)(ws + L.pkey);
+    d.blk = (BlockBest *)(ws + L.blk);
+    d.partials = (uint64_t *)(ws + L.partials);
+    d.tgt = (TargetStage *)(ws + L.tgt);
+    d.qtgt = (TargetStage *)(ws + L.qtgt);
+    d.st = (IterState *)(ws + L.st);
+    d.info = (InitInfo *)(ws + L.info);
+    d.log = (StepRec *)(ws + L.log);
+    d.W = W;
+    d.H = H;
+    d.r = p->patch_radius;
+    d.log_cap = (int32_t)std::min<int64_t>(L.log_cap, INT32_MAX);
+    d.nbw = (W + kBlock - 1) / kBlock;
+    d.norm1 = 255.0;
+    d.norm2 = std::sqrt(2.0) * 255.0;
+
+    // Upload: compact RGB(A) rows and the mask into the staging area (the
+    // priority-key plane, unused until the priorities are initialised).
+    const uint64_t n = (uint64_t)W * H;
+    uint8_t *stage_rgb = (uint8_t *)d.pkey;
+    uint8_t *stage_mask = stage_rgb + 4 * n;
+    uint8_t *hdist = stage_mask + n;
+    hipStream_t s = c->stream;
+    hipError_t e = hipMemcpy2DAsync(stage_rgb, (size_t)W * ch, img->data, img->stride_bytes, (size_t)W * ch, H,
+                                    hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(stage_mask, W, mask, mask_stride, W, H, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_init(d, stage_rgb, ch, stage_mask, hdist, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->h_key, d.info, sizeof(InitInfo), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return create_fail(c, INPAINT_DEVICE, std::string("init: ") + hipGetErrorString(e));
+    InitInfo info;
+    std::memcpy(&info, c->h_key, sizeof(info));
+    if (info.hole_count <= 0) return create_fail(c, INPAINT_INVALID_ARGUMENT, "mask is empty");
+    if (info.hole_count >= (int64_t)n) return create_fail(c, INPAINT_INVALID_ARGUMENT, "mask covers the whole image");
+    c->hole0 = info.hole_count;
+
+    // Search rectangle.
+    inpaint_rect R{0, 0, W, H};
+    if (p->search_mode == INPAINT_SEARCH_ALPHA) {
+        alpha_axis(info.bx0, info.bx1, W, p->alpha_num, p->alpha_den, &R.x0, &R.x1);
+        alpha_axis(info.by0, info.by1, H, p->alpha_num, p->alpha_den, &R.y0, &R.y1);
+    } else if (p->search_mode == INPAINT_SEARCH_RECT) {
+        R.x0 = std::max(p->rect.x0, 0);
+        R.y0 = std::max(p->rect.y0, 0);
+        R.x1 = std::min(p->rect.x1, W);
+        R.y1 = std::min(p->rect.y1, H);
+    }
+    c->rect = R;
+    int k[4];
+    kernel_rect(W, H, d.r, R, k);
+    d.rx0 = k[0];
+    d.ry0 = k[1];
+    d.rx1 = std::max(k[2], k[0]);
+    d.ry1 = std::max(k[3], k[1]);
+    set_tiles(d, p->tile_rows ? p->tile_rows : kDefaultTileRows);
+
+    // Priority blocks: the hole's bbox grown by 2r+1 (how far a fill can
+    // change a priority), in 32x32 blocks.
+    const int reach = 2 * d.r + 1;
+    d.pbx0 = std::max(info.bx0 - reach, 0) / kBlock;
+    d.pby0 = std::max(info.by0 - reach, 0) / kBlock;
+    d.pbx1 = (std::min(info.bx1 + reach, W) + kBlock - 1) / kBlock;
+    d.pby1 = (std::min(info.by1 + reach, H) + kBlock - 1) / kBlock;
+
+    e = launch_count_valid(d, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->h_key, d.info, sizeof(InitInfo), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return create_fail(c, INPAINT_DEVICE, std::string("count: ") + hipGetErrorString(e));
+    std::memcpy(&info, c->h_key, sizeof(info));
+    if (info.valid_count <= 0)
+        return create_fail(c, INPAINT_INVALID_ARGUMENT, "no valid source centre in the search rectangle");
+    c->candidates = info.valid_count;
+
+    IterState &h = *c->h_state;
+    std::memset(&h, 0, sizeof(h));
+    h.remaining = c->hole0;
+    h.iter = 0;
+    h.iter_limit = INT64_MAX;
+    e = hipMemcpyAsync(d.st, &h, sizeof(IterState), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_prio_init(d, s);
+    if (e == hipSuccess) e = launch_commit(d, s);  // selects and stages the first target
+    if (e == hipSuccess) e = c->pull_state();
+    if (e != hipSuccess) return create_fail(c, INPAINT_DEVICE, std::string("first select: ") + hipGetErrorString(e));
+    if (c->h_state->error) return create_fail(c, INPAINT_DEVICE, "device error during the first selection");
+    *out = c;
+    return INPAINT_OK;
+}
+
+int32_t inpaint_search_info(const inpaint_ctx *ctx, inpaint_rect *rect, int64_t *candidates) {
+    if (!ctx) return INPAINT_INVALID_ARGUMENT;
+    if (rect) *rect = ctx->rect;
+    if (candidates) *candidates = ctx->candidates;
+    return INPAINT_OK;
+}
+
+int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t tx, int32_t ty, int32_t r, inpaint_rect rect,
+                              int64_t *source_index, uint32_t *ssd) {
+    if (!ctx) return INPAINT_INVALID_ARGUMENT;
+    if (ctx->sticky) return ctx->sticky;
+    const JobDev &d = ctx->d;
+    if (!source_index || !ssd) return ctx->fail(INPAINT_INVALID_ARGUMENT, "NULL output");
+    if (tx < 0 || ty < 0 || tx >= d.W || ty >= d.H) return ctx->fail(INPAINT_INVALID_ARGUMENT, "target outside the image");
+    if (r < 1 || r > kMaxRadius) return ctx->fail(INPAINT_INVALID_ARGUMENT, "patch_radius must be in 1..8");
+    if (rect.x0 > rect.x1 || rect.y0 > rect.y1) return ctx->fail(INPAINT_INVALID_ARGUMENT, "x0 > x1 or y0 > y1");
+    inpaint_rect R{std::max(rect.x0, 0), std::max(rect.y0, 0), std::min(rect.x1, d.W), std::min(rect.y1, d.H)};
+    int k[4];
+    kernel_rect(d.W, d.H, r, R, k);
+    if (k[2] <= k[0] || k[3] <= k[1]) return ctx->fail(INPAINT_NO_CANDIDATE, "no valid centre in the rect");
+    JobDev q = d;
+    q.rx0 = k[0];
+    q.ry0 = k[1];
+    q.rx1 = k[2];
+    q.ry1 = k[3];
+    set_tiles(q, d.tile_rows);
+    hipStream_t s = ctx->stream;
+    uint64_t *dkey = (uint64_t *)(ctx->ws + ctx->L.key);
+    HIP_OR_FAIL(ctx, launch_stage_query(q, tx, ty, r, s), "stage");
+    HIP_OR_FAIL(ctx, launch_search(q, true, r, q.rx0, q.ry0, q.rx1, q.ry1, q.tile_rows, q.ntx, q.nty, s), "search");
+    HIP_OR_FAIL(ctx, launch_reduce_partials(q, q.ntx * q.nty, dkey, s), "reduce");
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_key, dkey, 8, hipMemcpyDeviceToHost, s), "copy");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(s), "sync");
+    const uint64_t key = ctx->h_key[0];
+    if (key == ~0ull) return ctx->fail(INPAINT_NO_CANDIDATE, "no valid centre in the rect");
+    *source_index = (int64_t)(key & 0xffffffffu);
+    *ssd = (uint32_t)(key >> 32);
+    return INPAINT_OK;
+}
+
+static hipError_t enqueue_iteration(inpaint_ctx *ctx, hipStream_t s) {
+    const JobDev &d = ctx->d;
+    hipError_t e = launch_search(d, false, d.r, d.rx0, d.ry0, d.rx1, d.ry1, d.tile_rows, d.ntx, d.nty, s);
+    if (e == hipSuccess) e = launch_commit(d, s);
+    return e;
+}
+
+static int32_t check_device_state(inpaint_ctx *ctx) {
+    if (ctx->h_state->error) {
+        ctx->sticky = INPAINT_DEVICE;
+        ctx->err = std::string("device-side error: ") + status_name(ctx->h_state->error);
+        return INPAINT_DEVICE;
+    }
+    return INPAINT_OK;
+}
+
+int32_t inpaint_step(inpaint_ctx *ctx, inpaint_step_info *info) {
+    if (!ctx) return INPAINT_INVALID_ARGUMENT;
+    if (ctx->sticky) return ctx->sticky;
+    if (ctx->batch) return ctx->fail(INPAINT_INVALID_ARGUMENT, "context is attached to a batch");
+    if (ctx->h_state->done) return INPAINT_DONE;
+    hipStream_t s = ctx->stream;
+    HIP_OR_FAIL(ctx, ctx->set_limit(ctx->h_state->iter + 1), "limit");
+    HIP_OR_FAIL(ctx, enqueue_iteration(ctx, s), "launch");
+    HIP_OR_FAIL(ctx, ctx->pull_state(), "state");
+    if (check_device_state(ctx) != INPAINT_OK) return INPAINT_DEVICE;
+    if (info) std::memcpy(info, &ctx->h_state->last, sizeof(*info));
+    return INPAINT_OK;
+}
+
+static hipError_t ensure_graph(inpaint_ctx *ctx, int G) {
+    if (ctx->graph && ctx->graph_n == G) return hipSuccess;
+    if (ctx->graph) {
+        hipGraphExecDestroy(ctx->graph);
+        ctx->graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+    for (int i = 0; i < G && e == hipSuccess; ++i) e = enqueue_iteration(ctx, ctx->cap_stream);
+    hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    if (e == hipSuccess) ctx->graph_n = G;
+    return e;
+}
+
+int32_t inpaint_run(inpaint_ctx *ctx, int64_t max_iters, int64_t *iters_done, inpaint_step_info *log,
+                    int64_t log_cap) {
+    if (!ctx) return INPAINT_INVALID_ARGUMENT;
+    if (ctx->sticky) return ctx->sticky;
+    if (ctx->batch) return ctx->fail(INPAINT_INVALID_ARGUMENT, "context is attached to a batch");
+    const int64_t start = ctx->h_state->iter;
+    if (ctx->h_state->done) {
+        if (iters_done) *iters_done = 0;
+        return INPAINT_DONE;
+    }
+    const int64_t limit = max_iters < 0 ? INT64_MAX : start + max_iters;
+    hipStream_t s = ctx->stream;
+    HIP_OR_FAIL(ctx, ctx->set_limit(limit), "limit");
+    const int G = ctx->p.graph_iters;
+    if (G > 0) HIP_OR_FAIL(ctx, ensure_graph(ctx, G), "graph capture");
+    for (;;) {
+        if (G > 0)
+            HIP_OR_FAIL(ctx, hipGraphLaunch(ctx->graph, s), "graph launch");
+        else
+            HIP_OR_FAIL(ctx, enqueue_iteration(ctx, s), "launch");
+        HIP_OR_FAIL(ctx, ctx->pull_state(), "state");
+        if (check_device_state(ctx) != INPAINT_OK) return INPAINT_DEVICE;
+        if (ctx->h_state->done || ctx->h_state->iter >= limit) break;
+    }
+    const int64_t ran = ctx->h_state->iter - start;
+    if (iters_done) *iters_done = ran;
+    if (log && log_cap > 0) {
+        const int64_t avail = std::max<int64_t>(0, std::min<int64_t>(ctx->d.log_cap, start + ran) - start);
+        const int64_t cnt = std::min(avail, log_cap);
+        if (cnt > 0) {
+            HIP_OR_FAIL(ctx, hipMemcpyAsync(log, ctx->d.log + start, cnt * sizeof(StepRec), hipMemcpyDeviceToHost, s),
+                        "log copy");
+            HIP_OR_FAIL(ctx, hipStreamSynchronize(s), "sync");
+        }
+    }
+    return ctx->h_state->done ? INPAINT_DONE : INPAINT_OK;
+}
+
+int32_t inpaint_read_log(inpaint_ctx *ctx, int64_t first, int64_t count, inpaint_step_info *out) {
+    if (!ctx || !out || first < 0 || count < 0) return INPAINT_INVALID_ARGUMENT;
+    if (ctx->sticky) return ctx->sticky;
+    HIP_OR_FAIL(ctx, ctx->pull_state(), "state");
+    const int64_t have = std::min<int64_t>(ctx->h_state->iter, ctx->d.log_cap);
+    if (first + count > have) return ctx->fail(INPAINT_INVALID_ARGUMENT, "records not in the log");
+    if (count == 0) return INPAINT_OK;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(out, ctx->d.log + first, count * sizeof(StepRec), hipMemcpyDeviceToHost,
+                                    ctx->stream), "log copy");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "sync");
+    return INPAINT_OK;
+}
+
+int32_t inpaint_read_image(inpaint_ctx *ctx, uint8_t *rgb, int32_t stride) {
+    if (!ctx || !rgb) return INPAINT_INVALID_ARGUMENT;
+    if (ctx->sticky) return ctx->sticky;
+    const int W = ctx->d.W, H = ctx->d.H;
+    if (stride < 3 * W) return ctx->fail(INPAINT_INVALID_ARGUMENT, "stride smaller than a row");
+    std::vector<uint32_t> tmp((size_t)W * H);
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(tmp.data(), ctx->d.img, tmp.size() * 4, hipMemcpyDeviceToHost, ctx->stream), "copy");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "sync");
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const uint32_t v = tmp[(size_t)y * W + x];
+            uint8_t *o = rgb + (size_t)y * stride + 3 * x;
+            o[0] = v & 255;
+            o[1] = (v >> 8) & 255;
+            o[2] = (v >> 16) & 255;
+        }
+    return INPAINT_OK;
+}
+
+int32_t inpaint_read_state(inpaint_ctx *ctx, uint8_t *mask, double *conf) {
+    if (!ctx) return INPAINT_INVALID_ARGUMENT;
+    if (ctx->sticky) return ctx->sticky;
+    const size_t n = (size_t)ctx->d.W * ctx->d.H;
+    if (mask) HIP_OR_FAIL(ctx, hipMemcpyAsync(mask, ctx->d.hole, n, hipMemcpyDeviceToHost, ctx->stream), "copy");
+    if (conf) HIP_OR_FAIL(ctx, hipMemcpyAsync(conf, ctx->d.conf, n * 8, hipMemcpyDeviceToHost, ctx->stream), "copy");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "sync");
+    return INPAINT_OK;
+}
+
+int32_t inpaint_remaining(inpaint_ctx *ctx, int64_t *remaining) {
+    if (!ctx || !remaining) return INPAINT_INVALID_ARGUMENT;
+    if (ctx->sticky) return ctx->sticky;
+    HIP_OR_FAIL(ctx, ctx->pull_state(), "state");
+    *remaining = ctx->h_state->remaining;
+    return INPAINT_OK;
+}
+
+int32_t inpaint_batch_detach(inpaint_batch *b, inpaint_ctx *ctx);
+
+int32_t inpaint_destroy(inpaint_ctx *ctx) {
+    if (!ctx) return INPAINT_INVALID_ARGUMENT;
+    if (ctx->batch) inpaint_batch_detach(ctx->batch, ctx);
+    hipStreamSynchronize(ctx->stream);
+    if (ctx->graph) hipGraphExecDestroy(ctx->graph);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+    if (ctx->h_state) hipHostFree(ctx->h_state);
+    if (ctx->h_key) hipHostFree(ctx->h_key);
+    delete ctx;
+    return INPAINT_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batch
+
+namespace {
+
+struct TuneChoice {
+    int tile_rows = kDefaultTileRows;
+    int grid = 0;   // 0 = one work-group per item
+};
+
+struct RadiusGroup {
+    std::vector<WorkItem> items;
+    WorkItem *d_items = nullptr;
+    int32_t *d_n = nullptr;
+    size_t cap = 0;
+    TuneChoice tune;
+    bool tuned = false;
+};
+
+std::string device_key() {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    return std::string(prop.gcnArchName) + "-cu" + std::to_string(prop.multiProcessorCount);
+}
+
+// Minimal flat JSON cache: {"key": [tile_rows, grid], ...}
+std::map<std::string, TuneChoice> read_cache(const char *path) {
+    std::map<std::string, TuneChoice> m;
+    if (!path) return m;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return m;
+    std::string s;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof(buf), f)) > 0) s.append(buf, k);
+    std::fclose(f);
+    size_t pos = 0;
+    while ((pos = s.find('"', pos)) != std::string::npos) {
+        const size_t end = s.find('"', pos + 1);
+        if (end == std::string::npos) break;
+        const std::string key = s.substr(pos + 1, end - pos - 1);
+        TuneChoice t;
+        if (std::sscanf(s.c_str() + end + 1, " : [ %d , %d ]", &t.tile_rows, &t.grid) == 2 && tile_rows_ok(t.tile_rows))
+            m[key] = t;
+        pos = end + 1;
+    }
+    return m;
+}
+
+void write_cache(const char *path, const std::map<std::string, TuneChoice> &m) {
+    if (!path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto &kv : m)
+        std::fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.tile_rows, kv.second.grid,
+                     ++i < m.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
+struct inpaint_batch {
+    inpaint_batch_params bp{};
+    std::string cache_path;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::vector<inpaint_ctx *> slots;
+    JobDev *d_slots = nullptr;
+    JobDev *h_slots = nullptr;      // pinned staging of the slot table
+    int64_t *d_active = nullptr;
+    int64_t *h_active = nullptr;    // pinned
+    std::map<int, RadiusGroup> groups;
+    bool dirty = true;
+    hipGraphExec_t graph = nullptr;
+    int graph_n = 0;
+    std::string graph_sig;
+    int cu_count = 256;
+};
+
+namespace {
+
+hipError_t upload_slot(inpaint_batch *b, int i) {
+    return hipMemcpyAsync(b->d_slots + i, b->h_slots + i, sizeof(JobDev), hipMemcpyHostToDevice, b->stream);
+}
+
+JobDev slot_desc(const inpaint_ctx *c, int tile_rows) {
+    JobDev d = c->d;
+    set_tiles(d, tile_rows);
+    return d;
+}
+
+hipError_t upload_group(inpaint_batch *b, RadiusGroup &g) {
+    const size_t n = g.items.size();
+    if (n > g.cap || !g.d_items) {
+        if (g.d_items) hipFree(g.d_items);
+        if (g.d_n) hipFree(g.d_n);
+        g.cap = std::max<size_t>(n, 1024) * 2;
+        hipError_t e = hipMalloc(&g.d_items, g.cap * sizeof(WorkItem));
+        if (e == hipSuccess) e = hipMalloc(&g.d_n, sizeof(int32_t));
+        if (e != hipSuccess) return e;
+        b->graph_sig.clear();  // pointers changed: recapture
+    }
+    hipError_t e = hipSuccess;
+    if (n) e = hipMemcpyAsync(g.d_items, g.items.data(), n * sizeof(WorkItem), hipMemcpyHostToDevice, b->stream);
+    const int32_t nn = (int32_t)n;
+    if (e == hipSuccess) e = hipMemcpyAsync(g.d_n, &nn, sizeof(int32_t), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // nn is on the stack
+    return e;
+}
+
+// Rebuilds every radius group's (slot, tile) list for its tile shape.
+hipError_t rebuild(inpaint_batch *b) {
+    for (auto &kv : b->groups) kv.second.items.clear();
+    for (size_t i = 0; i < b->slots.size(); ++i) {
+        inpaint_ctx *c = b->slots[i];
+        if (!c) continue;
+        RadiusGroup &g = b->groups[c->d.r];
+        b->h_slots[i] = slot_desc(c, g.tune.tile_rows);
+        const int nt = b->h_slots[i].ntx * b->h_slots[i].nty;
+        for (int t = 0; t < nt; ++t) g.items.push_back(WorkItem{(int32_t)i, t});
+        hipError_t e = upload_slot(b, (int)i);
+        if (e != hipSuccess) return e;
+    }
+    for (auto &kv : b->groups) {
+        hipError_t e = upload_group(b, kv.second);
+        if (e != hipSuccess) return e;
+    }
+    b->dirty = false;
+    return hipSuccess;
+}
+
+int grid_for(const inpaint_batch *b, const RadiusGroup &g) {
+    const int n = (int)g.items.size();
+    if (g.tune.grid > 0) return std::max(1, std::min(g.tune.grid, n));
+    return std::max(1, n);
+}
+
+hipError_t enqueue_batch_iteration(inpaint_batch *b, hipStream_t s) {
+    for (auto &kv : b->groups) {
+        RadiusGroup &g = kv.second;
+        if (g.items.empty()) continue;
+        hipError_t e = launch_search_batched(b->d_slots, g.d_items, g.d_n, kv.first, g.tune.tile_rows,
+                                             grid_for(b, g), s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_commit_batched(b->d_slots, (int)b->slots.size(), s);
+}
+
+// Times the batched search of one radius group for each tile shape and
+// persistent grid size, keeps the fastest.  The searches only rewrite the
+// images' partial results, which every real search rewrites before use.
+hipError_t autotune_group(inpaint_batch *b, int r, RadiusGroup &g, std::map<std::string, TuneChoice> &cache) {
+    int64_t pixels = 0;
+    for (auto *c : b->slots)
+        if (c && c->d.r == r) pixels += (int64_t)(c->d.rx1 - c->d.rx0) * (c->d.ry1 - c->d.ry0);
+    int lg = 0;
+    while ((1ll << (lg + 1)) <= pixels) ++lg;
+    const std::string key = device_key() + "/r" + std::to_string(r) + "/px2^" + std::to_string(lg);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        g.tune = it->second;
+        g.tuned = true;
+        return rebuild(b);
+    }
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best_ms = 1e30f;
+    TuneChoice best = g.tune;
+    for (int rows : {4, 8, 16}) {
+        g.tune.tile_rows = rows;
+        g.tune.grid = 0;
+        hipError_t e = rebuild(b);
+        if (e != hipSuccess) return e;
+        const int n = (int)g.items.size();
+        for (int grid : {b->cu_count, 2 * b->cu_count, 4 * b->cu_count, 8 * b->cu_count, 0}) {
+            if (grid > n) continue;
+            g.tune.grid = grid;
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                hipEventRecord(e0, b->stream);
+                e = launch_search_batched(b->d_slots, g.d_items, g.d_n, r, rows, grid_for(b, g), b->stream);
+                hipEventRecord(e1, b->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e != hipSuccess) return e;
+                float ms = 0;
+                hipEventElapsedTime(&ms, e0, e1);
+                ms_min = std::min(ms_min, ms);
+            }
+            if (ms_min < best_ms) {
+                best_ms = ms_min;
+                best = g.tune;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    g.tune = best;
+    g.tuned = true;
+    cache[key] = best;
+    return rebuild(b);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t inpaint_batch_create(const inpaint_batch_params *bp, void *hip_stream, inpaint_batch **out) {
+    if (!bp || !out || bp->capacity < 1 || bp->graph_iters < 1) return INPAINT_INVALID_ARGUMENT;
+    inpaint_batch *b = new (std::nothrow) inpaint_batch();
+    if (!b) return INPAINT_OUT_OF_MEMORY;
+    b->bp = *bp;
+    if (bp->tune_cache) b->cache_path = bp->tune_cache;
+    b->stream = (hipStream_t)hip_stream;
+    b->slots.assign(bp->capacity, nullptr);
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) b->cu_count = prop.multiProcessorCount;
+    hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&b->d_slots, sizeof(JobDev) * bp->capacity);
+    if (e == hipSuccess) e = hipMalloc(&b->d_active, sizeof(int64_t));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_slots, sizeof(JobDev) * bp->capacity, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_active, sizeof(int64_t), hipHostMallocDefault);
+    if (e == hipSuccess) {
+        std::memset(b->h_slots, 0, sizeof(JobDev) * bp->capacity);
+        e = hipMemcpyAsync(b->d_slots, b->h_slots, sizeof(JobDev) * bp->capacity, hipMemcpyHostToDevice, b->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        inpaint_batch_destroy(b);
+        return INPAINT_DEVICE;
+    }
+    *out = b;
+    return INPAINT_OK;
+}
+
+int32_t inpaint_batch_attach(inpaint_batch *b, inpaint_ctx *ctx, int32_t *slot) {
+    if (!b || !ctx || ctx->batch || ctx->sticky) return INPAINT_INVALID_ARGUMENT;
+    int i = 0;
+    while (i < (int)b->slots.size() && b->slots[i]) ++i;
+    if (i == (int)b->slots.size()) return INPAINT_INVALID_ARGUMENT;
+    // Make sure the context's own work has finished and its limit is open.
+    if (ctx->set_limit(INT64_MAX) != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return ctx->hip_fail(hipErrorUnknown, "attach");
+    b->slots[i] = ctx;
+    ctx->batch = b;
+    if (b->groups.find(ctx->d.r) == b->groups.end()) b->graph_sig.clear();
+    b->groups[ctx->d.r];
+    b->dirty = true;
+    if (slot) *slot = i;
+    return INPAINT_OK;
+}
+
+int32_t inpaint_batch_detach(inpaint_batch *b, inpaint_ctx *ctx) {
+    if (!b || !ctx || ctx->batch != b) return INPAINT_INVALID_ARGUMENT;
+    for (size_t i = 0; i < b->slots.size(); ++i)
+        if (b->slots[i] == ctx) {
+            hipStreamSynchronize(b->stream);
+            b->slots[i] = nullptr;
+            std::memset(&b->h_slots[i], 0, sizeof(JobDev));
+            upload_slot(b, (int)i);
+            hipStreamSynchronize(b->stream);
+        }
+    ctx->batch = nullptr;
+    ctx->pull_state();
+    b->dirty = true;
+    return INPAINT_OK;
+}
+
+int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active) {
+    if (!b || G < 1) return INPAINT_INVALID_ARGUMENT;
+    hipError_t e = hipSuccess;
+    if (b->dirty) e = rebuild(b);
+    if (e != hipSuccess) return INPAINT_DEVICE;
+    if (b->bp.autotune) {
+        std::map<std::string, TuneChoice> cache;
+        bool loaded = false, changed = false;
+        for (auto &kv : b->groups) {
+            if (kv.second.tuned || kv.second.items.empty()) continue;
+            if (!loaded) {
+                cache = read_cache(b->cache_path.empty() ? nullptr : b->cache_path.c_str());
+                loaded = true;
+            }
+            e = autotune_group(b, kv.first, kv.second, cache);
+            if (e != hipSuccess) return INPAINT_DEVICE;
+            changed = true;
+            b->graph_sig.clear();
+        }
+        if (changed && !b->cache_path.empty()) write_cache(b->cache_path.c_str(), cache);
+    }
+    std::string sig = std::to_string(G);
+    for (auto &kv : b->groups)
+        sig += "|" + std::to_string(kv.first) + ":" + std::to_string(kv.second.tune.tile_rows) + ":" +
+               std::to_string(grid_for(b, kv.second)) + ":" + std::to_string(kv.second.items.empty());
+    if (sig != b->graph_sig || !b->graph) {
+        if (b->graph) hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+        hipGraph_t g = nullptr;
+        e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+        for (int i = 0; i < G && e == hipSuccess; ++i) e = enqueue_batch_iteration(b, b->cap_stream);
+        hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+        if (g) hipGraphDestroy(g);
+        if (e != hipSuccess) return INPAINT_DEVICE;
+        b->graph_sig = sig;
+        b->graph_n = G;
+    }
+    e = hipGraphLaunch(b->graph, b->stream);
+    if (e == hipSuccess) e = launch_count_active(b->d_slots, (int)b->slots.size(), b->d_active, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->h_active, b->d_active, sizeof(int64_t), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return INPAINT_DEVICE;
+    if (active) *active = *b->h_active;
+    return INPAINT_OK;
+}
+
+int32_t inpaint_batch_destroy(inpaint_batch *b) {
+    if (!b) return INPAINT_INVALID_ARGUMENT;
+    for (auto *c : b->slots)
+        if (c) c->batch = nullptr;
+    if (b->stream) hipStreamSynchronize(b->stream);
+    if (b->graph) hipGraphExecDestroy(b->graph);
+    for (auto &kv : b->groups) {
+        if (kv.second.d_items) hipFree(kv.second.d_items);
+        if (kv.second.d_n) hipFree(kv.second.d_n);
+    }
+    if (b->d_slots) hipFree(b->d_slots);
+    if (b->d_active) hipFree(b->d_active);
+    if (b->h_slots) hipHostFree(b->h_slots);
+    if (b->h_active) hipHostFree(b->h_active);
+    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+    delete b;
+    return INPAINT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+"""The C-ABI library loads and exports every symbol include/inpaint.h
+declares; host-only argument checks (no device work) behave as documented."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "inpaint.h")
+LIB = os.path.join(ROOT, "paper_1403_4238_amd", "libinpaint.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(inpaint_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def so():
+    if not os.path.exists(LIB):
+        pytest.fail(f"{LIB} not built (run __graft_entry__.build())")
+    return LIB
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["inpaint_create", "inpaint_find_exemplar", "inpaint_step", "inpaint_run",
+                     "inpaint_workspace_bytes", "inpaint_batch_step", "inpaint_destroy"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(so):
+    out = subprocess.run(["nm", "-D", "--defined-only", so], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s(inpaint_\w+)", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    # C linkage: no mangled inpaint symbols leak out
+    assert not re.search(r"\sT\s_Z\w*inpaint_(create|run|step)\b", out)
+
+
+def test_library_loads_and_host_only_calls(so):
+    L = ctypes.CDLL(so)
+    L.inpaint_status_string.restype = ctypes.c_char_p
+    assert L.inpaint_status_string(0) == b"ok"
+    assert L.inpaint_status_string(-2).startswith(b"no valid source")
+
+    from paper_1403_4238_amd.binding import inpaint_params, inpaint_rect
+    p = inpaint_params()
+    p.patch_radius = 4
+    p.alpha_den = 1
+    b = ctypes.c_uint64()
+    f = L.inpaint_workspace_bytes
+    f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(inpaint_params), ctypes.POINTER(ctypes.c_uint64)]
+    assert f(1920, 1080, ctypes.byref(p), ctypes.byref(b)) == 0
+    n = 1920 * 1080
+    # RGBX + gray + hole + validity + confidence + priority keys, plus small tables
+    assert 4 * n + 3 * n + 8 * n + 8 * n <= b.value < 4 * n + 3 * n + 8 * n + 8 * n + 2_000_000
+    p.log_capacity = 1000
+    b2 = ctypes.c_uint64()
+    assert f(1920, 1080, ctypes.byref(p), ctypes.byref(b2)) == 0
+    assert b2.value - b.value >= 64 * 1000 - 256
+    # argument checks
+    assert f(8, 8, ctypes.byref(p), ctypes.byref(b)) == -1         # smaller than the 9x9 patch
+    p.patch_radius = 9
+    assert f(100, 100, ctypes.byref(p), ctypes.byref(b)) == -1     # radius out of range
+    p.patch_radius = 4
+    p.tile_rows = 5
+    assert f(100, 100, ctypes.byref(p), ctypes.byref(b)) == -1
+    p.tile_rows = 0
+    p.search_mode = 2
+    p.rect = inpaint_rect(10, 0, 5, 10)
+    assert f(100, 100, ctypes.byref(p), ctypes.byref(b)) == -1     # x0 > x1
+    p.search_mode = 1
+    p.alpha_den = 0
+    assert f(100, 100, ctypes.byref(p), ctypes.byref(b)) == -1
+    p.alpha_den = 1
+    p.reserved[0] = 3
+    assert f(100, 100, ctypes.byref(p), ctypes.byref(b)) == -1
+
+
+def test_step_record_layout():
+    from paper_1403_4238_amd.binding import STEP_DTYPE, inpaint_params
+    import oracle
+    assert STEP_DTYPE.itemsize == 64
+    assert ctypes.sizeof(inpaint_params) == 4 * 16
+    assert oracle.STEP_DTYPE.names == STEP_DTYPE.names

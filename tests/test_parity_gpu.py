@@ -1,0 +1,280 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Exemplar indices, SSDs, fill logs, final images and confidence maps must be
+bit-exact; priorities are compared by their bit patterns (the device
+evaluates them in the same operation order, without fused multiply-add).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1403_4238_amd import synth
+
+from _util import assert_logs_equal, assert_matches_golden, load_golden
+
+pytestmark = pytest.mark.gpu
+
+B = pytest.importorskip("paper_1403_4238_amd.binding")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build()
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    B.lib()
+
+
+def _pair(job, **kw):
+    o = oracle.Oracle(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, rect=job.rect)
+    g = B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, rect=job.rect, **kw)
+    return o, g
+
+
+def _full_run_parity(job, label, **kw):
+    o, g = _pair(job, **kw)
+    want = o.run()
+    st, n, got = g.run(log_cap=len(want) + 8)
+    assert st == B.DONE and n == len(want)
+    assert_logs_equal(got, want, label)
+    rgb_o, _, hole_o, conf_o = o.read()
+    hole_g, conf_g = g.read_state()
+    assert (g.read_image() == rgb_o).all(), f"{label}: final image differs"
+    assert (hole_g == hole_o).all() and hole_g.sum() == 0
+    assert (conf_g.view(np.int64) == conf_o.view(np.int64)).all(), f"{label}: confidence differs"
+    return got
+
+
+# ------------------------------------------------------------ single search
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_find_exemplar_matches_oracle_all_radii(r):
+    job = synth.small()
+    o, g = _pair(job)
+    rng = np.random.default_rng(r)
+    front = o.front()
+    targets = [(int(i % job.width), int(i // job.width)) for i in front[:: max(len(front) // 6, 1)]]
+    targets += [(int(rng.integers(0, job.width)), int(rng.integers(0, job.height))) for _ in range(4)]
+    targets += [(0, 0), (job.width - 1, job.height - 1), (0, job.height - 1)]
+    for (x, y) in targets:
+        want = o.find_exemplar(x, y, r, (0, 0, job.width, job.height))[:2]
+        got = g.find_exemplar(x, y, r, (0, 0, job.width, job.height))
+        assert got == want, (r, x, y)
+
+
+@pytest.mark.parametrize("rect", [(0, 0, 128, 96), (10, 7, 60, 41), (70, 50, 128, 96), (-5, -5, 300, 300),
+                                  (20, 20, 21, 90), (0, 60, 128, 61)])
+def test_find_exemplar_rects(rect):
+    job = synth.small()
+    o, g = _pair(job)
+    for i in o.front()[::9]:
+        x, y = int(i % 128), int(i // 128)
+        try:
+            want = o.find_exemplar(x, y, 4, rect)[:2]
+        except oracle.OracleError as e:
+            assert e.status == oracle.NO_CANDIDATE
+            with pytest.raises(B.InpaintError) as ge:
+                g.find_exemplar(x, y, 4, rect)
+            assert ge.value.status == B.NO_CANDIDATE
+            continue
+        assert g.find_exemplar(x, y, 4, rect) == want
+
+
+def test_find_exemplar_errors():
+    job = synth.small()
+    _, g = _pair(job)
+    for args in [(-1, 5, 4, None), (5, 96, 4, None), (5, 5, 0, None), (5, 5, 9, None), (5, 5, 4, (9, 0, 3, 5))]:
+        with pytest.raises(B.InpaintError) as e:
+            g.find_exemplar(*args)
+        assert e.value.status == B.INVALID_ARGUMENT
+    with pytest.raises(B.InpaintError) as e:
+        g.find_exemplar(5, 5, 4, (0, 0, 3, 3))
+    assert e.value.status == B.NO_CANDIDATE
+    # a query does not disturb the fill state
+    assert g.remaining() == int(job.mask.sum())
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_find_exemplar_vga_initial_state(seed):
+    # Full-size 640x480 search (several hundred tiles, ragged edges) at the
+    # initial state, for front targets and arbitrary targets.
+    job = synth.vga()
+    o, g = _pair(job)
+    rng = np.random.default_rng(50 + seed)
+    front = o.front()
+    picks = [int(front[int(k)]) for k in rng.integers(0, len(front), size=2)]
+    for i in picks:
+        x, y = i % job.width, i // job.width
+        assert g.find_exemplar(x, y) == o.find_exemplar(x, y)[:2]
+    x, y = int(rng.integers(0, job.width)), int(rng.integers(0, job.height))
+    assert g.find_exemplar(x, y, 2 + seed) == o.find_exemplar(x, y, 2 + seed)[:2]
+
+
+def test_find_exemplar_planted_copy_on_gpu():
+    rng = np.random.default_rng(11)
+    W, H, r = 200, 150, 4
+    rgb = rng.integers(0, 256, size=(H, W, 3)).astype(np.uint8)
+    mask = np.zeros((H, W), np.uint8)
+    mask[60:80, 90:120] = 1
+    tx, ty, cx, cy = 90, 70, 171, 133
+    rgb[cy - r:cy + r + 1, cx - r:cx + r + 1] = rgb[ty - r:ty + r + 1, tx - r:tx + r + 1]
+    g = B.Inpainter(rgb, mask, r)
+    assert g.find_exemplar(tx, ty) == (cy * W + cx, 0)
+
+
+# ----------------------------------------------------------- full removals
+
+def test_small_workload_full_run():
+    job = synth.small()
+    got = _full_run_parity(job, "small")
+    gold = load_golden("small")
+    if gold is not None:
+        assert gold["input_sha256"] == job.sha256()
+        g = B.Inpainter(job.rgb, job.mask, 4)
+        _, _, log = g.run(log_cap=10_000)
+        assert_matches_golden(gold, log, g.read_image(), "small")
+    assert len(got) == 16
+
+
+@pytest.mark.parametrize("seed,W,H,r", [(1, 16, 16, 1), (2, 24, 20, 2), (3, 40, 31, 3), (4, 67, 45, 5),
+                                        (5, 90, 70, 8), (6, 33, 70, 6), (7, 130, 21, 4)])
+def test_random_images_full_run(seed, W, H, r):
+    rng = np.random.default_rng(seed)
+    rgb = rng.integers(0, 256, size=(H, W, 3)).astype(np.uint8)
+    mask = np.zeros((H, W), np.uint8)
+    # one interior blob and one blob touching the border
+    mask[H // 3:H // 3 + max(H // 5, 2), W // 3:W // 3 + max(W // 6, 2)] = 1
+    mask[0:max(H // 8, 1), W - max(W // 7, 2):] = 1
+    job = synth.Job(f"rand{seed}", rgb, mask, r)
+    _full_run_parity(job, job.name)
+
+
+def test_low_contrast_ties_full_run():
+    # Few gray levels: many equal SSDs and equal priorities, so every
+    # tie-break is exercised.
+    rng = np.random.default_rng(8)
+    W, H = 70, 50
+    rgb = (rng.integers(0, 3, size=(H, W, 1)) * 40).repeat(3, axis=2).astype(np.uint8)
+    mask = np.zeros((H, W), np.uint8)
+    mask[20:31, 25:40] = 1
+    _full_run_parity(synth.Job("ties", rgb, mask, 2), "ties")
+
+
+def test_uniform_and_periodic_images():
+    W, H = 60, 48
+    rgb, mask = synth.periodic_texture(1, W, H, 5, 7, (22, 17, 37, 30))
+    got = _full_run_parity(synth.Job("periodic", rgb, mask, 3), "periodic")
+    assert (got["ssd"] == 0).all()
+    flat = np.full((H, W, 3), 90, np.uint8)
+    _full_run_parity(synth.Job("uniform", flat, mask, 2), "uniform")
+
+
+def test_rgba_input_and_alpha_window():
+    job = synth.small()
+    rgba = np.concatenate([job.rgb, np.full(job.rgb.shape[:2] + (1,), 77, np.uint8)], axis=2)
+    j2 = synth.Job("rgba-win", rgba, job.mask, 4, synth.SEARCH_ALPHA, (1, 2))
+    o, g = _pair(j2)
+    assert g.search_info()[0] == o.rect()
+    want = o.run()
+    _, _, got = g.run(log_cap=1000)
+    assert_logs_equal(got, want, "rgba-win")
+    assert (g.read_image() == o.read()[0]).all()
+
+
+def test_rect_search_mode():
+    job = synth.small()
+    j2 = synth.Job("rect", job.rgb, job.mask, 3, synth.SEARCH_RECT, rect=(5, 0, 70, 60))
+    o, g = _pair(j2)
+    want = o.run()
+    _, _, got = g.run(log_cap=1000)
+    assert_logs_equal(got, want, "rect")
+
+
+@pytest.mark.parametrize("tile_rows", [4, 8, 16])
+def test_tile_shapes_give_identical_results(tile_rows):
+    job = synth.small()
+    o, g = _pair(job, tile_rows=tile_rows)
+    _, _, got = g.run(log_cap=100)
+    assert_logs_equal(got, o.run(), f"tile_rows={tile_rows}")
+
+
+def test_graph_form_equals_plain_form():
+    job = synth.small()
+    plain = B.Inpainter(job.rgb, job.mask, 4, graph_iters=0)
+    graph = B.Inpainter(job.rgb, job.mask, 4, graph_iters=5)
+    _, n1, l1 = plain.run(log_cap=100)
+    _, n2, l2 = graph.run(log_cap=100)
+    assert n1 == n2
+    assert_logs_equal(l2, l1, "graph")
+    assert (plain.read_image() == graph.read_image()).all()
+
+
+def test_step_and_partial_runs_equal_one_run():
+    job = synth.small()
+    o = oracle.Oracle(job.rgb, job.mask, 4)
+    want = o.run()
+    g = B.Inpainter(job.rgb, job.mask, 4, graph_iters=3)
+    recs = [g.step(), g.step()]
+    st, n, more = g.run(max_iters=4, log_cap=10)
+    assert st == B.OK and n == 4
+    st, n2, rest = g.run(log_cap=100)
+    assert st == B.DONE
+    got = np.concatenate([np.array(recs, dtype=B.STEP_DTYPE), more, rest])
+    assert_logs_equal(got, want, "step+run")
+    assert_logs_equal(g.read_log(0, len(want)), want, "device log")
+    assert g.step() is None
+    assert g.run()[0] == B.DONE
+
+
+def test_create_errors():
+    rgb = np.zeros((20, 20, 3), np.uint8)
+    for mask, r, status in [(np.zeros((20, 20), np.uint8), 2, B.INVALID_ARGUMENT),
+                            (np.ones((20, 20), np.uint8), 2, B.INVALID_ARGUMENT)]:
+        with pytest.raises(B.InpaintError) as e:
+            B.Inpainter(rgb, mask, r)
+        assert e.value.status == status
+    grid = np.zeros((20, 20), np.uint8)
+    grid[::4, ::4] = 1
+    with pytest.raises(B.InpaintError) as e:
+        B.Inpainter(rgb, grid, 4)
+    assert e.value.status == B.INVALID_ARGUMENT
+
+
+# --------------------------------------------- full-size workloads (stored)
+
+def test_vga_full_run_matches_stored_oracle():
+    gold = load_golden("vga")
+    if gold is None:
+        pytest.skip("stored oracle result for the 640x480 workload not generated")
+    job = synth.vga()
+    assert job.sha256() == gold["input_sha256"]
+    g = B.Inpainter(job.rgb, job.mask, 4)
+    st, n, log = g.run(log_cap=gold["iterations"] + 8)
+    assert st == B.DONE
+    assert_matches_golden(gold, log, g.read_image(), "vga")
+    _, cands = g.search_info()
+    assert cands == gold["candidates_per_search"]
+
+
+@pytest.mark.parametrize("key", ["hd9", "hd9w", "hd13", "hd13w"])
+def test_hd_full_run_matches_stored_oracle(key):
+    gold = load_golden(key)
+    if gold is None:
+        pytest.skip(f"stored oracle result for {key} not generated")
+    job = synth.hd(patch=int(key[2:].rstrip("w")), window=key.endswith("w"))
+    assert job.sha256() == gold["input_sha256"]
+    g = B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, graph_iters=16)
+    st, n, log = g.run(log_cap=gold["iterations"] + 8)
+    assert st == B.DONE
+    assert_matches_golden(gold, log, g.read_image(), key)
+
+
+@pytest.mark.parametrize("patch,window", [(9, False), (13, True)])
+def test_hd_first_iterations_live_oracle(patch, window):
+    # 1920x1080: the oracle runs the first iterations live (about a second
+    # each), the GPU must match them exactly.
+    job = synth.hd(patch=patch, window=window)
+    o, g = _pair(job)
+    want = o.run(max_iters=2)
+    _, _, got = g.run(max_iters=2, log_cap=4)
+    assert_logs_equal(got, want, f"hd p{patch} {'win' if window else 'full'}")
