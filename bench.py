@@ -1,0 +1,230 @@
+"""Benchmark: masked-SSD patch evaluations/s and ms per removal on one MI355X.
+
+A step is one complete object removal (fill front, FP64 priority, exemplar
+search, copy/confidence update, repeated until the hole is empty) of the
+1920x1080 synthetic workload with a 9x9 patch and a full-image search.  The
+image and mask are uploaded and initialised before the timed region (each
+timed removal has its own pre-created context, so the inputs are resident in
+HBM when timing starts).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--form graph|plain]
+                    [--workload hd|vga|small] [--patch 9|13] [--window]
+
+Prints one JSON line.  Besides the headline it reports the other form
+(plain = two launches and one host check per iteration; graph = hipGraph
+replay of G iterations), the live-measured search-kernel roofline, and the
+CPU oracle timed on a bounded prefix of the same removal.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X (gfx950) public figures used for the roofline.
+CUS, LANES_PER_CU_CYCLE, CLOCK_HZ = 256, 64, 2.4e9
+VALU_LANE_OPS = CUS * LANES_PER_CU_CYCLE * CLOCK_HZ          # 39.32e12 lane-instructions/s
+TERMS_PER_VALU_OP = 1.5   # dot4 form: 2 VALU ops (cross dot4 + square add) per 3 RGB terms
+TERM_PEAK = VALU_LANE_OPS * TERMS_PER_VALU_OP                # 58.98e12 terms/s
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="hd", choices=["hd", "vga", "small"])
+    ap.add_argument("--patch", type=int, default=9)
+    ap.add_argument("--window", action="store_true", help="alpha = 1 search window (3x the hole bbox)")
+    ap.add_argument("--form", default="stream", choices=["stream", "plain"],
+                    help="timed form (search-kernel events need a non-graph form)")
+    ap.add_argument("--iters-per-check", type=int, default=32)
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--no-other-form", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def make_job(a):
+    from paper_1403_4238_amd import synth
+    if a.workload == "hd":
+        return synth.hd(patch=a.patch, window=a.window)
+    if a.workload == "vga":
+        return synth.vga()
+    return synth.small()
+
+
+def timed_removals(job, n_steps, n_warmup, form, iters_per_check, tile_rows, timing=True):
+    """Runs n_warmup + n_steps removals; times the last n_steps together."""
+    import torch
+    from paper_1403_4238_amd import binding as B
+    ctxs = [B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, rect=job.rect,
+                        form=form, iters_per_check=iters_per_check, tile_rows=tile_rows)
+            for _ in range(n_warmup + n_steps)]
+    for c in ctxs[:n_warmup]:
+        c.run()
+    for c in ctxs[n_warmup:]:
+        c.profile_search(timing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for c in ctxs[n_warmup:]:
+        st, n, _ = c.run()
+        assert st == B.DONE
+        iters.append(n)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kernel_ms = sum(c.search_time()[0] for c in ctxs[n_warmup:])
+    searches = sum(c.search_time()[1] for c in ctxs[n_warmup:])
+    last = ctxs[-1]
+    log = last.read_log(0, iters[-1])
+    out = last.read_image()
+    rect, cands = last.search_info()
+    for c in ctxs:
+        c.close()
+    return dict(seconds=dt, iters=iters, kernel_ms=kernel_ms, searches=searches, log=log, image=out,
+                candidates=cands, rect=rect, ws_bytes=ctxs[0].ws_bytes)
+
+
+def cpu_baseline(job, seconds):
+    """The oracle as it stands, single-threaded, on a prefix of the removal."""
+    import oracle
+    oracle.build()
+    t0 = time.perf_counter()
+    o = oracle.Oracle(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, rect=job.rect)
+    t_create = time.perf_counter() - t0
+    x0, y0, x1, y1 = o.rect()
+    ncand = int(o.valid_map()[y0:y1, x0:x1].sum())
+    n = 0
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < seconds:
+        if o.step() is None:
+            break
+        n += 1
+    dt = time.perf_counter() - t1
+    return {
+        "value": round(n * ncand / dt, 1), "unit": "patch evals/s", "cores": 1, "kind": "oracle",
+        "sample": f"first {n} fill iterations of the same removal ({n * ncand} patch evals), "
+                  f"oracle create excluded ({t_create:.2f}s)",
+        "ms_per_iteration": round(1000 * dt / max(n, 1), 2),
+        "host_cpu": _cpu_name(), "host_nproc": os.cpu_count(),
+    }
+
+
+def _cpu_name():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def golden_check(job, a, log, image):
+    key = {("hd", 9, False): "hd9", ("hd", 9, True): "hd9w", ("hd", 13, False): "hd13",
+           ("hd", 13, True): "hd13w"}.get((a.workload, a.patch, a.window), a.workload)
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{key}.json")
+    if not os.path.exists(path):
+        return "no stored oracle result"
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _util import log_sha256
+    with open(path) as f:
+        gold = json.load(f)
+    ok = (gold["input_sha256"] == job.sha256() and gold["iterations"] == len(log)
+          and gold["log_sha256"] == log_sha256(log)
+          and gold["final_rgb_sha256"] == hashlib.sha256(image.tobytes()).hexdigest())
+    return "bit-exact vs stored oracle" if ok else "MISMATCH vs stored oracle"
+
+
+def main():
+    a = parse()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(independent jobs would be placed one per GPU; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    job = make_job(a)
+    res = timed_removals(job, a.steps, a.warmup, a.form, a.iters_per_check, a.tile_rows)
+    n_steps = a.steps
+    evals = sum(res["iters"]) * res["candidates"]
+    value = evals / res["seconds"]
+    ms_per_step = 1000 * res["seconds"] / n_steps
+
+    log = res["log"]
+    terms_per_removal = 3 * int(np.asarray(log["known_k"], dtype=np.int64).sum()) * res["candidates"]
+    avg_kernel_ms = res["kernel_ms"] / max(res["searches"], 1)
+    terms_per_launch = terms_per_removal / max(len(log), 1)
+    achieved = terms_per_launch / (avg_kernel_ms * 1e-3)
+    # HBM bytes a search must move at least: the RGBX words of the candidate
+    # windows' rows once (the frame is read through L2 / MALL every search).
+    rx0, ry0, rx1, ry1 = res["rect"]
+    r = job.patch_radius
+    bytes_per_launch = 4 * (min(rx1 + r, job.width) - max(rx0 - r, 0)) * (min(ry1 + r, job.height) - max(ry0 - r, 0))
+
+    # The other forms, untimed by events: the plain form (host check every
+    # iteration) and the graph form (hipGraph replay of the same iterations).
+    others = {}
+    if not a.no_other_form:
+        for form in ("plain", "graph"):
+            if form == a.form:
+                continue
+            o = timed_removals(job, 1, 0, form, a.iters_per_check, a.tile_rows, timing=False)
+            others[form] = {"ms_per_removal": round(1000 * o["seconds"], 2),
+                            "patch_evals_per_s": round(sum(o["iters"]) * o["candidates"] / o["seconds"], 1)}
+
+    line = {
+        "metric": "masked-SSD patch evals/s (ms per 1080p removal alongside)",
+        "value": round(value, 1),
+        "unit": "patch evals/s",
+        "n_gpus": 1, "steps": n_steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8 (SSD: u8 x u8 -> u32 exact; priority: f64)",
+        "data": "synthetic (seeded)",
+        "config": {
+            "workload": f"{job.name}: {job.width}x{job.height} RGB u8, hole {int(job.mask.sum())} px, "
+                        f"{2 * r + 1}x{2 * r + 1} patch, "
+                        f"{'alpha=1 window' if a.window else 'full search'}, SIMT dot4 search, "
+                        f"{a.form} form" + (f" ({a.iters_per_check} iterations per host check)"
+                                             if a.form != "plain" else ""),
+            "width": job.width, "height": job.height, "patch": 2 * r + 1,
+            "search_rect": list(res["rect"]), "candidates_per_search": res["candidates"],
+            "iterations_per_removal": res["iters"][-1], "form": a.form,
+            "workspace_bytes": res["ws_bytes"],
+        },
+        "ms_per_removal": round(ms_per_step, 3),
+        "iterations_per_s": round(sum(res["iters"]) / res["seconds"], 1),
+        "parity": golden_check(job, a, log, res["image"]),
+        "roofline": {
+            "bound": "alu", "kernel": f"k_search<R={r},NY={a.tile_rows or 8}>",
+            "achieved": round(achieved / 1e12, 3), "peak": round(TERM_PEAK / 1e12, 2),
+            "unit": "Tterm/s", "frac": round(achieved / TERM_PEAK, 4),
+            "traffic": None,
+            "avg_launch_us": round(1000 * avg_kernel_ms, 3), "launches_timed": res["searches"],
+            "terms_per_launch": round(terms_per_launch),
+            "min_hbm_bytes_per_launch": bytes_per_launch,
+            "hbm_frac_if_streamed": round(bytes_per_launch / (avg_kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "search_share_of_step": round(res["kernel_ms"] / (1000 * res["seconds"]), 4),
+        },
+        "other_forms": others,
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(job, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -60,6 +60,16 @@ extern "C" {
 #define INPAINT_SEARCH_ALPHA 1   /* window around the hole, Eq. 6            */
 #define INPAINT_SEARCH_RECT  2   /* caller-given rectangle of centres        */
 
+/* Execution forms of inpaint_run.  Every form runs the same two kernels per
+ * iteration (exemplar search, then commit); they differ in how the host
+ * drives them.  Kernels skip their work once the hole is empty or the
+ * iteration limit is reached, so overshooting a batch of iterations is
+ * harmless. */
+#define INPAINT_FORM_PLAIN  0    /* launch one iteration, host check, repeat  */
+#define INPAINT_FORM_STREAM 1    /* enqueue iters_per_check iterations, check */
+#define INPAINT_FORM_GRAPH  2    /* replay a hipGraph of iters_per_check      */
+                                 /*   iterations, check                       */
+
 #define INPAINT_PATH_AUTO 0
 #define INPAINT_PATH_SIMT 1      /* integer dot-product SSD on the VALU      */
 #define INPAINT_PATH_MFMA 2      /* int8 matrix-core cross term (exact)      */
@@ -83,15 +93,17 @@ typedef struct {
     int32_t alpha_den;     /*   used by INPAINT_SEARCH_ALPHA (alpha >= 0)   */
     inpaint_rect rect;     /* used by INPAINT_SEARCH_RECT; clipped to image */
     int32_t path;          /* INPAINT_PATH_*                                 */
-    int32_t graph_iters;   /* inpaint_run: 0 = plain form (two launches per  */
-                           /*   iteration, host checks termination after    */
-                           /*   each); N > 0 = replay a captured hipGraph of */
-                           /*   N iterations, host checks after each replay */
-    int32_t log_capacity;  /* device log records kept (>= 0); -1 = one per   */
-                           /*   hole pixel, which covers any run            */
+    int32_t form;          /* inpaint_run execution form, INPAINT_FORM_*     */
+    int32_t iters_per_check; /* STREAM / GRAPH forms: iterations enqueued   */
+                           /*   (or replayed as one hipGraph) between two   */
+                           /*   host checks of termination (>= 1)           */
+    int32_t log_capacity;  /* device log records kept (>= 0), one per fill   */
+                           /*   iteration; -1 = width*height, enough for    */
+                           /*   any mask (a removal never needs more than   */
+                           /*   its hole-pixel count)                       */
     int32_t tile_rows;     /* search tile: candidate rows per thread (0 =   */
                            /*   default; 4, 8 or 16)                        */
-    int32_t reserved[4];   /* must be zero                                   */
+    int32_t reserved[3];   /* must be zero                                   */
 } inpaint_params;
 
 /* One fill iteration (64 bytes). */
@@ -152,7 +164,7 @@ int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t target_x, int32_t target
 int32_t inpaint_step(inpaint_ctx *ctx, inpaint_step_info *info);
 
 /* Iterates until the hole is empty or max_iters iterations (max_iters < 0:
- * no limit) have run, in the form chosen by params.graph_iters.  Writes the
+ * no limit) have run, in the form chosen by params.form.  Writes the
  * number of iterations run to *iters_done and, when log is not NULL, the
  * first min(log_cap, iterations, log capacity) records of this call.  Returns
  * INPAINT_DONE when the hole is empty, INPAINT_OK when stopped by max_iters.
@@ -180,6 +192,15 @@ int32_t inpaint_remaining(inpaint_ctx *ctx, int64_t *remaining);
  * the number of valid source centres in it, i.e. patch evaluations per
  * search.  No device work. */
 int32_t inpaint_search_info(const inpaint_ctx *ctx, inpaint_rect *rect, int64_t *candidates);
+
+/* Measurement: with enable != 0, every exemplar-search launch of the fill
+ * loop is bracketed by HIP events on the context's stream, and
+ * inpaint_search_time reports the summed kernel time and the number of
+ * searches timed since the last enable.  Off by default.  Supported in the
+ * PLAIN and STREAM forms; inpaint_run in the GRAPH form returns
+ * INVALID_ARGUMENT while timing is on. */
+int32_t inpaint_profile_search(inpaint_ctx *ctx, int32_t enable);
+int32_t inpaint_search_time(inpaint_ctx *ctx, double *total_ms, int64_t *searches);
 
 /* Releases the context (not the caller's workspace).  Waits for its work. */
 int32_t inpaint_destroy(inpaint_ctx *ctx);

@@ -21,6 +21,8 @@ OK, DONE = 0, 1
 INVALID_ARGUMENT, NO_CANDIDATE, OUT_OF_MEMORY, DEVICE = -1, -2, -3, -4
 SEARCH_FULL, SEARCH_ALPHA, SEARCH_RECT = 0, 1, 2
 PATH_AUTO, PATH_SIMT, PATH_MFMA = 0, 1, 2
+FORM_PLAIN, FORM_STREAM, FORM_GRAPH = 0, 1, 2
+FORMS = {"plain": FORM_PLAIN, "stream": FORM_STREAM, "graph": FORM_GRAPH}
 
 
 class inpaint_image(ctypes.Structure):
@@ -36,9 +38,9 @@ class inpaint_rect(ctypes.Structure):
 class inpaint_params(ctypes.Structure):
     _fields_ = [("patch_radius", ctypes.c_int32), ("search_mode", ctypes.c_int32),
                 ("alpha_num", ctypes.c_int32), ("alpha_den", ctypes.c_int32),
-                ("rect", inpaint_rect), ("path", ctypes.c_int32), ("graph_iters", ctypes.c_int32),
-                ("log_capacity", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("rect", inpaint_rect), ("path", ctypes.c_int32), ("form", ctypes.c_int32),
+                ("iters_per_check", ctypes.c_int32), ("log_capacity", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class inpaint_batch_params(ctypes.Structure):
@@ -80,6 +82,8 @@ def lib() -> ctypes.CDLL:
         "inpaint_read_state": (i32, [vp, vp, vp]),
         "inpaint_remaining": (i32, [vp, P(i64)]),
         "inpaint_search_info": (i32, [vp, P(inpaint_rect), P(i64)]),
+        "inpaint_profile_search": (i32, [vp, i32]),
+        "inpaint_search_time": (i32, [vp, P(ctypes.c_double), P(i64)]),
         "inpaint_destroy": (i32, [vp]),
         "inpaint_status_string": (ctypes.c_char_p, [i32]),
         "inpaint_last_error": (ctypes.c_char_p, [vp]),
@@ -116,15 +120,16 @@ def inpaint_last_error(ctx) -> str:
 
 
 def make_params(patch_radius: int, search_mode: int = SEARCH_FULL, alpha=(0, 1), rect=(0, 0, 0, 0),
-                path: int = PATH_AUTO, graph_iters: int = 0, log_capacity: int = 0,
-                tile_rows: int = 0) -> inpaint_params:
+                path: int = PATH_AUTO, form: str = "plain", iters_per_check: int = 16,
+                log_capacity: int = 0, tile_rows: int = 0) -> inpaint_params:
     p = inpaint_params()
     p.patch_radius = patch_radius
     p.search_mode = search_mode
     p.alpha_num, p.alpha_den = int(alpha[0]), int(alpha[1])
     p.rect = inpaint_rect(*rect)
     p.path = path
-    p.graph_iters = graph_iters
+    p.form = FORMS[form]
+    p.iters_per_check = iters_per_check
     p.log_capacity = log_capacity
     p.tile_rows = tile_rows
     return p
@@ -147,8 +152,9 @@ class Inpainter:
 
     def __init__(self, rgb: np.ndarray, mask: np.ndarray, patch_radius: int,
                  search_mode: int = SEARCH_FULL, alpha=(0, 1), rect=(0, 0, 0, 0),
-                 path: int = PATH_AUTO, graph_iters: int = 0, log_capacity: int | None = None,
-                 tile_rows: int = 0, device: str = "cuda", stream=None):
+                 path: int = PATH_AUTO, form: str = "plain", iters_per_check: int = 16,
+                 log_capacity: int | None = None, tile_rows: int = 0, device: str = "cuda",
+                 stream=None):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: libinpaint has no CPU path")
         rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
@@ -158,8 +164,8 @@ class Inpainter:
             raise ValueError("mask shape does not match the image")
         if log_capacity is None:
             log_capacity = int(np.count_nonzero(mask))
-        self.params = make_params(patch_radius, search_mode, alpha, rect, path, graph_iters,
-                                  log_capacity, tile_rows)
+        self.params = make_params(patch_radius, search_mode, alpha, rect, path, form,
+                                  iters_per_check, log_capacity, tile_rows)
         self.width, self.height = W, H
         self.ws_bytes = inpaint_workspace_bytes(W, H, self.params)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
@@ -233,6 +239,15 @@ class Inpainter:
         out = ctypes.c_int64()
         self._check(lib().inpaint_remaining(self.ctx, ctypes.byref(out)), "inpaint_remaining")
         return out.value
+
+    def profile_search(self, enable: bool = True):
+        self._check(lib().inpaint_profile_search(self.ctx, 1 if enable else 0), "inpaint_profile_search")
+
+    def search_time(self):
+        """(summed search-kernel milliseconds, searches timed)."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(lib().inpaint_search_time(self.ctx, ctypes.byref(ms), ctypes.byref(n)), "inpaint_search_time")
+        return ms.value, n.value
 
     def search_info(self):
         rc, n = inpaint_rect(), ctypes.c_int64()

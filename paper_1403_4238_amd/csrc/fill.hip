@@ -4,12 +4,15 @@
 // Everything here except the exemplar search (search.hip) is latency-bound
 // work on at most a few thousand pixels per iteration, so the per-iteration
 // part runs as ONE work-group of 1024 threads per image ("commit" kernel):
-//   reduce the search partials -> copy the source patch -> refresh the
-//   priorities near the filled patch -> argmax -> stage the next target.
+//   reduce the search partials -> copy the source patch -> stage the
+//   neighbourhood of the patch in LDS -> refresh the priorities there ->
+//   refresh the affected block maxima -> argmax -> stage the next target.
 //
 // Priorities are binary64 and must match a plain sequential CPU evaluation
 // bit for bit, so this file is compiled with FP contraction off and every
-// sum runs in the fixed raster order of the patch offsets.
+// sum runs in the fixed raster order of the patch offsets.  The same
+// templated routine evaluates a priority from global memory (initialisation)
+// and from the LDS copy of the neighbourhood (per iteration).
 #pragma clang fp contract(off)
 
 #include "inpaint_dev.h"
@@ -18,25 +21,79 @@ namespace inpaint {
 
 namespace {
 
+// Neighbourhood the commit kernel stages around the target: the refresh
+// window reaches 2r+1 from it, a priority reads its patch (r) and gradients
+// one pixel further, so 3r+2.
+template <int R>
+struct Stage {
+    static constexpr int half = 3 * R + 2;
+    static constexpr int side = 2 * half + 1;
+    static constexpr int n = side * side;
+};
+
 __device__ __forceinline__ bool in_img(const JobDev &d, int x, int y) {
     return (unsigned)x < (unsigned)d.W && (unsigned)y < (unsigned)d.H;
 }
 
-// Known = inside the image and not in the current hole.
-__device__ __forceinline__ bool known_px(const JobDev &d, int x, int y) {
-    return in_img(d, x, y) && d.hole[(int64_t)y * d.W + x] == 0;
-}
+// ---- pixel views: what a priority evaluation reads -------------------------
 
-// Hole indicator with out-of-image pixels counted as hole (normal estimate).
-__device__ __forceinline__ int hole_or_out(const JobDev &d, int x, int y) {
-    return (!in_img(d, x, y) || d.hole[(int64_t)y * d.W + x]) ? 1 : 0;
-}
+// Straight from global memory.
+struct GlobalView {
+    const JobDev &d;
+    __device__ bool known(int x, int y) const { return in_img(d, x, y) && d.hole[(int64_t)y * d.W + x] == 0; }
+    // hole indicator with out-of-image pixels counted as hole (the normal)
+    __device__ int hole_or_out(int x, int y) const {
+        return (!in_img(d, x, y) || d.hole[(int64_t)y * d.W + x]) ? 1 : 0;
+    }
+    __device__ double conf(int x, int y) const { return d.conf[(int64_t)y * d.W + x]; }
+    // Central-difference gradient of the gray image at a known pixel whose
+    // four neighbours are known: returns gx^2 + gy^2, or -1 otherwise.
+    __device__ int grad(int x, int y, int *gx, int *gy) const {
+        if (!known(x, y) || !known(x + 1, y) || !known(x - 1, y) || !known(x, y + 1) || !known(x, y - 1))
+            return -1;
+        const uint8_t *g = d.gray;
+        const int W = d.W;
+        *gx = (int)g[(int64_t)y * W + x + 1] - (int)g[(int64_t)y * W + x - 1];
+        *gy = (int)g[(int64_t)(y + 1) * W + x] - (int)g[(int64_t)(y - 1) * W + x];
+        return *gx * *gx + *gy * *gy;
+    }
+};
+
+// The LDS copy of a square neighbourhood: status 0 known, 1 hole, 2 outside
+// the image; confidences; gradients precomputed per pixel.
+template <int R>
+struct LdsStage {
+    uint8_t st[Stage<R>::n];
+    uint8_t gray[Stage<R>::n];
+    double conf[Stage<R>::n];
+    int mag[Stage<R>::n];
+    int gxy[Stage<R>::n];   // gx in the low 16 bits, gy in the high 16 (signed)
+};
+
+template <int R>
+struct LdsView {
+    const LdsStage<R> &s;
+    int ox, oy;
+    static constexpr int side = Stage<R>::side;
+    __device__ int at(int x, int y) const { return (y - oy) * side + (x - ox); }
+    __device__ bool known(int x, int y) const { return s.st[at(x, y)] == 0; }
+    __device__ int hole_or_out(int x, int y) const { return s.st[at(x, y)] != 0 ? 1 : 0; }
+    __device__ double conf(int x, int y) const { return s.conf[at(x, y)]; }
+    __device__ int grad(int x, int y, int *gx, int *gy) const {
+        const int i = at(x, y);
+        const int v = s.gxy[i];
+        *gx = (int)(int16_t)(v & 0xffff);
+        *gy = v >> 16;
+        return s.mag[i];
+    }
+};
 
 // Fill front: a hole pixel with at least one in-image 4-neighbour known.
-__device__ __forceinline__ bool on_front(const JobDev &d, int x, int y) {
-    if (!in_img(d, x, y) || d.hole[(int64_t)y * d.W + x] == 0) return false;
-    return known_px(d, x + 1, y) || known_px(d, x - 1, y) || known_px(d, x, y + 1) ||
-           known_px(d, x, y - 1);
+// (x, y) is always inside the image here.
+template <class V>
+__device__ __forceinline__ bool on_front(const V &v, int x, int y) {
+    if (v.hole_or_out(x, y) == 0) return false;
+    return v.known(x + 1, y) || v.known(x - 1, y) || v.known(x, y + 1) || v.known(x, y - 1);
 }
 
 // Eq. 2.  Confidence: sum of C over the known pixels of the patch, in raster
@@ -45,52 +102,59 @@ __device__ __forceinline__ bool on_front(const JobDev &d, int x, int y) {
 // central-difference gradient of the gray image (all four neighbours known;
 // first in raster order on ties), dotted with the unit normal of the front
 // (central differences of the hole indicator), absolute value, over 255.
-__device__ void priority_terms(const JobDev &d, int px, int py, double *C, double *D) {
-    const int r = d.r, P = 2 * r + 1, W = d.W;
+// Unknown offsets add +0.0, which leaves the running sum bit-identical (it
+// starts at +0.0 and only non-negative values are added), so the loop needs
+// no branches and unrolls fully.
+template <int R, class V>
+__device__ void priority_terms(const V &v, int px, int py, double norm1, double norm2, double *C, double *D) {
+    constexpr int P = 2 * R + 1;
     double sum = 0.0;
-    for (int dy = -r; dy <= r; ++dy)
-        for (int dx = -r; dx <= r; ++dx) {
-            const int x = px + dx, y = py + dy;
-            if (known_px(d, x, y)) sum = sum + d.conf[(int64_t)y * W + x];
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx) {
+            const bool k = v.known(px + dx, py + dy);
+            const double c = k ? v.conf(px + dx, py + dy) : 0.0;
+            sum = sum + c;
         }
     *C = sum / (double)(P * P);
 
     int gx = 0, gy = 0, best = -1;
-    for (int dy = -r; dy <= r; ++dy)
-        for (int dx = -r; dx <= r; ++dx) {
-            const int x = px + dx, y = py + dy;
-            if (!known_px(d, x, y) || !known_px(d, x + 1, y) || !known_px(d, x - 1, y) ||
-                !known_px(d, x, y + 1) || !known_px(d, x, y - 1))
-                continue;
-            const uint8_t *g = d.gray;
-            const int ax = (int)g[(int64_t)y * W + x + 1] - (int)g[(int64_t)y * W + x - 1];
-            const int ay = (int)g[(int64_t)(y + 1) * W + x] - (int)g[(int64_t)(y - 1) * W + x];
-            const int mag = ax * ax + ay * ay;
-            if (mag > best) {
-                best = mag;
-                gx = ax;
-                gy = ay;
-            }
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy)
+#pragma unroll
+        for (int dx = -R; dx <= R; ++dx) {
+            int ax = 0, ay = 0;
+            const int mag = v.grad(px + dx, py + dy, &ax, &ay);
+            const bool take = mag > best;
+            best = take ? mag : best;
+            gx = take ? ax : gx;
+            gy = take ? ay : gy;
         }
-    const int nx = hole_or_out(d, px + 1, py) - hole_or_out(d, px - 1, py);
-    const int ny = hole_or_out(d, px, py + 1) - hole_or_out(d, px, py - 1);
+    const int nx = v.hole_or_out(px + 1, py) - v.hole_or_out(px - 1, py);
+    const int ny = v.hole_or_out(px, py + 1) - v.hole_or_out(px, py - 1);
     const int kn = nx * nx + ny * ny;
     if (kn == 0) {
         *D = 0.0;
     } else {
         int a = gx * ny - gy * nx;
         if (a < 0) a = -a;
-        *D = (0.5 * (double)a) / (kn == 1 ? d.norm1 : d.norm2);
+        *D = (0.5 * (double)a) / (kn == 1 ? norm1 : norm2);
     }
 }
 
-// Priority key of a pixel: bits of P = C * D (Eq. 1) on the front, else -1.
+// (C, D) of a pixel: C = -1 marks "not on the front".
+template <int R, class V>
+__device__ double2 pixel_terms(const V &v, const JobDev &d, int x, int y) {
+    double2 cd = make_double2(-1.0, 0.0);
+    if (on_front(v, x, y)) priority_terms<R>(v, x, y, d.norm1, d.norm2, &cd.x, &cd.y);
+    return cd;
+}
+
+// Priority key from cached terms: bits of P = C * D (Eq. 1), -1 off the front.
 // Non-negative doubles order like their bit patterns.
-__device__ int64_t pixel_key(const JobDev &d, int x, int y) {
-    if (!on_front(d, x, y)) return -1;
-    double C, D;
-    priority_terms(d, x, y, &C, &D);
-    return __double_as_longlong(C * D);
+__device__ __forceinline__ int64_t key_of(double2 cd) {
+    return cd.x < 0.0 ? -1 : __double_as_longlong(cd.x * cd.y);
 }
 
 // ---- work-group reductions (blockDim.x a multiple of 64, <= 1024) ----
@@ -179,38 +243,50 @@ struct Scratch {
     int64_t i[16];
     uint64_t u[16];
     uint32_t mbits[16];
-    int64_t bcast[8];
 };
 
-// Recomputes the priority-block maximum of block (bx, by).
-__device__ void refresh_block(const JobDev &d, int bx, int by, Scratch &s) {
-    const int x = bx * kBlock + (int)(threadIdx.x & (kBlock - 1));
-    const int y = by * kBlock + (int)(threadIdx.x / kBlock);
-    int64_t key = -1, idx = INT64_MAX;
-    if (threadIdx.x < kBlock * kBlock && in_img(d, x, y)) {
-        idx = (int64_t)y * d.W + x;
-        key = d.pkey[idx];
+__device__ __forceinline__ void wave_argmax(int64_t &key, int64_t &idx) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t k2 = __shfl_xor(key, off);
+        const int64_t i2 = __shfl_xor(idx, off);
+        if (better(k2, i2, key, idx)) {
+            key = k2;
+            idx = i2;
+        }
     }
-    block_argmax(key, idx, s.k, s.i);
-    if (threadIdx.x == 0) {
+}
+
+// One wave recomputes the maximum of the 8x8 priority block (bx, by).
+__device__ void refresh_block_wave(const JobDev &d, int bx, int by) {
+    const int lane = threadIdx.x & 63;
+    const int x = bx * kBlock + (lane & (kBlock - 1)), y = by * kBlock + lane / kBlock;
+    int64_t key = -1, idx = INT64_MAX;
+    if (in_img(d, x, y)) {
+        idx = (int64_t)y * d.W + x;
+        key = key_of(d.pcd[idx]);
+    }
+    wave_argmax(key, idx);
+    if (lane == 0) {
         d.blk[by * d.nbw + bx].key = key;
         d.blk[by * d.nbw + bx].idx = idx;
     }
 }
 
 // Stages the target patch at (tx, ty) with radius r into *tg: known mask,
-// RGBX words, k and T2 = sum of squared known target values.
+// RGBX words and T2 = sum of squared known target values, in column-major
+// slot order (dx + r) * P + (dy + r).
 __device__ void stage_target(const JobDev &d, int tx, int ty, int r, TargetStage *tg, Scratch &s) {
     const int P = 2 * r + 1;
+    const GlobalView v{d};
     if (threadIdx.x < 16) s.mbits[threadIdx.x] = 0;
     __syncthreads();
     int64_t kk = 0, t2 = 0;
     for (int t = threadIdx.x; t < kMaxOffsets + 15; t += blockDim.x) {
         uint32_t pix = 0;
         if (t < P * P) {
-            const int dx = t % P - r, dy = t / P - r;
+            const int dx = t / P - r, dy = t % P - r;
             const int x = tx + dx, y = ty + dy;
-            if (known_px(d, x, y)) {
+            if (v.known(x, y)) {
                 pix = d.img[(int64_t)y * d.W + x] & 0x00ffffffu;
                 const int R = pix & 255, G = (pix >> 8) & 255, B = (pix >> 16) & 255;
                 kk += 1;
@@ -254,14 +330,73 @@ __device__ void select_and_stage(const JobDev &d, Scratch &s) {
     const int px = (int)(idx % d.W), py = (int)(idx / d.W);
     stage_target(d, px, py, d.r, d.tgt, s);
     if (threadIdx.x == 0) {
-        double C, D;
-        priority_terms(d, px, py, &C, &D);
+        const double2 cd = d.pcd[idx];
         st->p_idx = idx;
-        st->C = C;
-        st->D = D;
-        st->Pr = C * D;
+        st->C = cd.x;
+        st->D = cd.y;
+        st->Pr = cd.x * cd.y;
         st->pending = 1;
     }
+}
+
+// Stages the neighbourhood of (px, py) into LDS (status, gray, confidence).
+template <int R>
+__device__ void stage_neighbourhood(const JobDev &d, int px, int py, LdsStage<R> &L) {
+    using S = Stage<R>;
+    const int ox = px - S::half, oy = py - S::half;
+    for (int t = threadIdx.x; t < S::n; t += blockDim.x) {
+        const int x = ox + t % S::side, y = oy + t / S::side;
+        uint8_t stv = 2;
+        if (in_img(d, x, y)) {
+            const int64_t i = (int64_t)y * d.W + x;
+            stv = d.hole[i] ? 1 : 0;
+            L.gray[t] = d.gray[i];
+            L.conf[t] = d.conf[i];
+        }
+        L.st[t] = stv;
+    }
+}
+
+// Re-evaluates the priorities within 2r+1 (Chebyshev) of the filled target
+// (px, py): that is where the hole, the confidences and the gray values read
+// by a priority evaluation changed.  Expects the neighbourhood (already
+// updated by the copy) in LDS.  Gradients are computed once per pixel, then
+// each front pixel of the window evaluates its terms from LDS, and one wave
+// per 8x8 block refreshes the affected block maxima.
+template <int R>
+__device__ void refresh_near(const JobDev &d, int px, int py, LdsStage<R> &L) {
+    using S = Stage<R>;
+    const int ox = px - S::half, oy = py - S::half;
+    const LdsView<R> v{L, ox, oy};
+    // gradients on the inner (side - 2)^2 square
+    constexpr int gs = S::side - 2, gn = gs * gs;
+    for (int t = threadIdx.x; t < gn; t += blockDim.x) {
+        const int x = ox + 1 + t % gs, y = oy + 1 + t / gs;
+        const int i = v.at(x, y);
+        int mag = -1, gxy = 0;
+        if (v.known(x, y) && v.known(x + 1, y) && v.known(x - 1, y) && v.known(x, y + 1) && v.known(x, y - 1)) {
+            const int gx = (int)L.gray[i + 1] - (int)L.gray[i - 1];
+            const int gy = (int)L.gray[i + S::side] - (int)L.gray[i - S::side];
+            mag = gx * gx + gy * gy;
+            gxy = (gx & 0xffff) | (gy << 16);
+        }
+        L.mag[i] = mag;
+        L.gxy[i] = gxy;
+    }
+    __syncthreads();
+    constexpr int reach = 2 * R + 1;
+    const int wx0 = max(px - reach, 0), wx1 = min(px + reach + 1, d.W);
+    const int wy0 = max(py - reach, 0), wy1 = min(py + reach + 1, d.H);
+    const int ww = wx1 - wx0, nwin = ww * (wy1 - wy0);
+    for (int t = threadIdx.x; t < nwin; t += blockDim.x) {
+        const int x = wx0 + t % ww, y = wy0 + t / ww;
+        d.pcd[(int64_t)y * d.W + x] = pixel_terms<R>(v, d, x, y);
+    }
+    __syncthreads();
+    const int bx0 = wx0 / kBlock, by0 = wy0 / kBlock;
+    const int nbx = (wx1 - 1) / kBlock - bx0 + 1, nb = nbx * ((wy1 - 1) / kBlock - by0 + 1);
+    for (int b = threadIdx.x >> 6; b < nb; b += blockDim.x >> 6) refresh_block_wave(d, bx0 + b % nbx, by0 + b / nbx);
+    __syncthreads();
 }
 
 }  // namespace
@@ -375,112 +510,120 @@ __global__ __launch_bounds__(256) void k_count_valid(JobDev d) {
         atomicAdd((unsigned long long *)&d.info->valid_count, (unsigned long long)s_cnt);
 }
 
-// Priority keys and block maxima of every block of the priority range.
-__global__ __launch_bounds__(1024) void k_prio_init(JobDev d) {
-    __shared__ Scratch s;
-    const int bw = d.pbx1 - d.pbx0;
-    const int bx = d.pbx0 + (int)blockIdx.x % bw, by = d.pby0 + (int)blockIdx.x / bw;
-    const int x = bx * kBlock + (int)(threadIdx.x & (kBlock - 1));
-    const int y = by * kBlock + (int)(threadIdx.x / kBlock);
-    if (in_img(d, x, y)) d.pkey[(int64_t)y * d.W + x] = pixel_key(d, x, y);
-    __syncthreads();
-    refresh_block(d, bx, by, s);
+// Priority terms and block maxima of every block of the priority range; one
+// wave per 8x8 block.
+template <int R>
+__global__ __launch_bounds__(256) void k_prio_init(JobDev d) {
+    const int bw = d.pbx1 - d.pbx0, nb = bw * (d.pby1 - d.pby0);
+    const int b = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (b >= nb) return;
+    const int bx = d.pbx0 + b % bw, by = d.pby0 + b / bw;
+    const int lane = threadIdx.x & 63;
+    const int x = bx * kBlock + (lane & (kBlock - 1)), y = by * kBlock + lane / kBlock;
+    const GlobalView v{d};
+    if (in_img(d, x, y)) d.pcd[(int64_t)y * d.W + x] = pixel_terms<R>(v, d, x, y);
+    refresh_block_wave(d, bx, by);   // same wave: its own writes are visible
 }
 
 // One fill iteration after the search: reduce the search partials, copy the
 // source patch into the target's hole pixels (they take the target's
 // confidence), log, refresh priorities near the patch, select and stage the
-// next target.  With no staged target it only selects and stages.
-__device__ void commit_body(const JobDev &d, Scratch &s) {
+// next target.  With no staged target it only selects and stages.  The
+// target's neighbourhood is staged in LDS while the partials are reduced, and
+// the copy updates both global memory and that LDS copy.
+template <int R>
+__device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L) {
     IterState *st = d.st;
-    if (st->done || st->error) return;
-    if (st->pending) {
-        if (st->iter >= st->iter_limit) return;
+    const int done = st->done, err = st->error, pending = st->pending;
+    const int64_t iter = st->iter, limit = st->iter_limit, rem0 = st->remaining, p = st->p_idx;
+    const double C = st->C, D = st->D, Pr = st->Pr;
+    if (done || err) return;
+    if (pending) {
+        if (iter >= limit) return;
+        constexpr int P = 2 * R + 1;
+        const int W = d.W;
+        const int px = (int)(p % W), py = (int)(p / W);
+        const int known_k = d.tgt->k;
+        stage_neighbourhood<R>(d, px, py, L);
         const int ntiles = d.ntx * d.nty;
         uint64_t best = ~0ull;
         for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
             const uint64_t v = d.partials[t];
             best = v < best ? v : best;
         }
-        best = block_min_u64(best, s.u);
+        best = block_min_u64(best, s.u);   // also orders the LDS staging
         if (best == ~0ull) {
             if (threadIdx.x == 0) st->error = INPAINT_NO_CANDIDATE;
             return;
         }
         const int64_t q = (int64_t)(best & 0xffffffffu);
         const uint32_t ssd = (uint32_t)(best >> 32);
-        const int64_t p = st->p_idx;
-        const double C = st->C;
-        const int W = d.W, r = d.r, P = 2 * r + 1;
-        const int px = (int)(p % W), py = (int)(p / W), qx = (int)(q % W), qy = (int)(q / W);
+        const int qx = (int)(q % W), qy = (int)(q / W);
         int64_t filled = 0;
         if (threadIdx.x < P * P) {
-            const int dx = (int)threadIdx.x % P - r, dy = (int)threadIdx.x / P - r;
+            const int dx = (int)threadIdx.x % P - R, dy = (int)threadIdx.x / P - R;
             const int x = px + dx, y = py + dy;
-            if (in_img(d, x, y) && d.hole[(int64_t)y * W + x]) {
+            const int li = (dy + Stage<R>::half) * Stage<R>::side + (dx + Stage<R>::half);
+            if (L.st[li] == 1) {
                 const int64_t dst = (int64_t)y * W + x, src = (int64_t)(qy + dy) * W + (qx + dx);
-                d.img[dst] = d.img[src];
-                d.gray[dst] = d.gray[src];
+                const uint32_t pix = d.img[src];
+                const uint8_t g = d.gray[src];
+                d.img[dst] = pix;
+                d.gray[dst] = g;
                 d.conf[dst] = C;
                 d.hole[dst] = 0;
+                L.st[li] = 0;
+                L.gray[li] = g;
+                L.conf[li] = C;
                 filled = 1;
             }
         }
         filled = block_sum_i64(filled, s.k);
-        const int64_t remaining = st->remaining - filled;
-        __syncthreads();
+        const int64_t remaining = rem0 - filled;
         if (threadIdx.x == 0) {
             StepRec rec;
             rec.target_index = p;
             rec.source_index = q;
             rec.ssd = ssd;
-            rec.known_k = d.tgt->k;
+            rec.known_k = known_k;
             rec.n_filled = (int32_t)filled;
             rec.reserved = 0;
-            rec.priority = st->Pr;
+            rec.priority = Pr;
             rec.confidence = C;
-            rec.data_term = st->D;
+            rec.data_term = D;
             rec.remaining = remaining;
-            const int64_t it = st->iter;
-            if (it < d.log_cap) d.log[it] = rec;
+            if (iter < d.log_cap) d.log[iter] = rec;
             st->last = rec;
             st->remaining = remaining;
-            st->iter = it + 1;
+            st->iter = iter + 1;
             st->pending = 0;
             if (remaining == 0) st->done = 1;
         }
         if (remaining == 0) return;
-        // Priorities can change only within 2r+1 (Chebyshev) of the target:
-        // that is where the hole, the confidences and the gray values read
-        // by a priority evaluation changed.
-        const int reach = 2 * r + 1;
-        const int wx0 = max(px - reach, 0), wx1 = min(px + reach + 1, d.W);
-        const int wy0 = max(py - reach, 0), wy1 = min(py + reach + 1, d.H);
-        const int ww = wx1 - wx0, nwin = ww * (wy1 - wy0);
-        __syncthreads();
-        for (int t = threadIdx.x; t < nwin; t += blockDim.x) {
-            const int x = wx0 + t % ww, y = wy0 + t / ww;
-            d.pkey[(int64_t)y * W + x] = pixel_key(d, x, y);
-        }
-        __syncthreads();
-        for (int by = wy0 / kBlock; by <= (wy1 - 1) / kBlock; ++by)
-            for (int bx = wx0 / kBlock; bx <= (wx1 - 1) / kBlock; ++bx) refresh_block(d, bx, by, s);
-        __syncthreads();
+        refresh_near<R>(d, px, py, L);
     }
     select_and_stage(d, s);
 }
 
+template <int R>
 __global__ __launch_bounds__(kCommitThreads) void k_commit(JobDev d) {
     __shared__ Scratch s;
-    commit_body(d, s);
+    __shared__ LdsStage<R> L;
+    commit_body<R>(d, s, L);
 }
 
-__global__ __launch_bounds__(kCommitThreads) void k_commit_batched(const JobDev *slots, int nslots) {
+// One work-group per listed slot (all with patch radius R); the list length
+// is read from device memory so the slot list can change between graph
+// replays without re-capture.
+template <int R>
+__global__ __launch_bounds__(kCommitThreads) void k_commit_batched(const JobDev *slots, const int32_t *ids,
+                                                                   const int32_t *n) {
     __shared__ Scratch s;
-    if ((int)blockIdx.x >= nslots) return;
-    const JobDev d = slots[blockIdx.x];
+    __shared__ LdsStage<R> L;
+    if ((int)blockIdx.x >= *n) return;
+    const JobDev d = slots[ids[blockIdx.x]];
     if (d.st == nullptr) return;   // empty slot
-    commit_body(d, s);
+    commit_body<R>(d, s, L);
 }
 
 __global__ __launch_bounds__(kCommitThreads) void k_stage_query(JobDev d, int tx, int ty, int r) {
@@ -498,6 +641,19 @@ __global__ __launch_bounds__(kCommitThreads) void k_reduce_partials(const uint64
     }
     best = block_min_u64(best, sh);
     if (threadIdx.x == 0) *out = best;
+}
+
+// Number of attached images that are still unfinished and error-free.
+__global__ void k_count_active(const JobDev *slots, int nslots, int64_t *out) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nslots; i += blockDim.x) {
+        const IterState *st = slots[i].st;
+        if (st && !st->done && !st->error) atomicAdd(&cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *out = cnt;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -523,19 +679,40 @@ hipError_t launch_count_valid(const JobDev &d, hipStream_t s) {
     return hipGetLastError();
 }
 
+#define INPAINT_RADIUS_SWITCH(r, CALL) \
+    switch (r) {                          \
+        case 1: CALL(1); break;           \
+        case 2: CALL(2); break;           \
+        case 3: CALL(3); break;           \
+        case 4: CALL(4); break;           \
+        case 5: CALL(5); break;           \
+        case 6: CALL(6); break;           \
+        case 7: CALL(7); break;           \
+        case 8: CALL(8); break;           \
+        default: return hipErrorInvalidValue; \
+    }
+
 hipError_t launch_prio_init(const JobDev &d, hipStream_t s) {
     const int nb = (d.pbx1 - d.pbx0) * (d.pby1 - d.pby0);
-    hipLaunchKernelGGL(k_prio_init, dim3(nb), dim3(1024), 0, s, d);
+#define CALL(R) hipLaunchKernelGGL(k_prio_init<R>, dim3((nb + 3) / 4), dim3(256), 0, s, d)
+    INPAINT_RADIUS_SWITCH(d.r, CALL)
+#undef CALL
     return hipGetLastError();
 }
 
 hipError_t launch_commit(const JobDev &d, hipStream_t s) {
-    hipLaunchKernelGGL(k_commit, dim3(1), dim3(kCommitThreads), 0, s, d);
+#define CALL(R) hipLaunchKernelGGL(k_commit<R>, dim3(1), dim3(kCommitThreads), 0, s, d)
+    INPAINT_RADIUS_SWITCH(d.r, CALL)
+#undef CALL
     return hipGetLastError();
 }
 
-hipError_t launch_commit_batched(const JobDev *slots, int nslots, hipStream_t s) {
-    hipLaunchKernelGGL(k_commit_batched, dim3(nslots), dim3(kCommitThreads), 0, s, slots, nslots);
+hipError_t launch_commit_batched(const JobDev *slots, const int32_t *ids, const int32_t *n, int grid, int r,
+                                 hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+#define CALL(R) hipLaunchKernelGGL(k_commit_batched<R>, dim3(grid), dim3(kCommitThreads), 0, s, slots, ids, n)
+    INPAINT_RADIUS_SWITCH(r, CALL)
+#undef CALL
     return hipGetLastError();
 }
 
@@ -548,23 +725,6 @@ hipError_t launch_reduce_partials(const JobDev &d, int ntiles, uint64_t *out, hi
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kCommitThreads), 0, s,
                        (const uint64_t *)d.partials, ntiles, out);
     return hipGetLastError();
-}
-
-}  // namespace inpaint
-
-namespace inpaint {
-
-// Number of attached images that are still unfinished and error-free.
-__global__ void k_count_active(const JobDev *slots, int nslots, int64_t *out) {
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < nslots; i += blockDim.x) {
-        const IterState *st = slots[i].st;
-        if (st && !st->done && !st->error) atomicAdd(&cnt, 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) *out = cnt;
 }
 
 hipError_t launch_count_active(const JobDev *slots, int nslots, int64_t *out, hipStream_t s) {

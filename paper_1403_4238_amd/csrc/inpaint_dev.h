@@ -13,14 +13,15 @@ constexpr int kMaxRadius = 8;
 constexpr int kMaxPatch = 2 * kMaxRadius + 1;          // 17
 constexpr int kMaxOffsets = kMaxPatch * kMaxPatch;     // 289
 constexpr int kMaskWords = (kMaxOffsets + 31) / 32;    // 10
-constexpr int kBlock = 32;                             // priority block side
+constexpr int kBlock = 8;                              // priority block side (one wave)
 constexpr int kTileW = 64;                             // search tile width (one wave)
 constexpr int kSearchWaves = 4;                        // waves per search work-group
 constexpr int kCommitThreads = 1024;
 
 // Target patch as the search kernels read it.  Offset o = (dx, dy) has slot
-// (dy + r) * P + (dx + r).  tpix holds the target's RGBX word (X = 0) where
-// the pixel is known and 0 elsewhere; bit `slot` of mbits is 1 where known.
+// (dx + r) * P + (dy + r) (column-major, so one column's P values are
+// contiguous).  tpix holds the target's RGBX word (X = 0) where the pixel is
+// known and 0 elsewhere; bit `slot` of mbits is 1 where known.
 struct alignas(256) TargetStage {
     int32_t tx, ty, r, k;
     uint32_t t2;                 // sum over known pixels of R^2 + G^2 + B^2
@@ -53,8 +54,8 @@ struct alignas(256) IterState {
 };
 
 // Per-block maximum of the priority keys: larger key wins, ties go to the
-// lower raster index.  key = bit pattern of the (non-negative) priority for
-// front pixels, -1 elsewhere.
+// lower raster index.  key = bit pattern of the (non-negative) priority
+// P = C * D for front pixels, -1 elsewhere.
 struct BlockBest {
     int64_t key;
     int64_t idx;
@@ -74,8 +75,8 @@ struct JobDev {
     uint8_t *hole;       // W*H, 1 = still to fill
     uint8_t *vrad;       // W*H, largest r <= 8 with a valid patch at the centre
     double *conf;        // W*H
-    int64_t *pkey;       // W*H priority keys
-    BlockBest *blk;      // ceil(W/32)*ceil(H/32)
+    double2 *pcd;        // W*H (C, D) of front pixels; C = -1 elsewhere
+    BlockBest *blk;      // ceil(W/8)*ceil(H/8)
     uint64_t *partials;  // one (ssd << 32 | index) per search tile
     TargetStage *tgt;    // staged target of the fill loop
     TargetStage *qtgt;   // staged target of inpaint_find_exemplar
@@ -104,10 +105,12 @@ hipError_t launch_count_valid(const JobDev &d, hipStream_t s);
 hipError_t launch_prio_init(const JobDev &d, hipStream_t s);
 hipError_t launch_commit(const JobDev &d, hipStream_t s);
 hipError_t launch_search(const JobDev &d, bool query, int r, int rx0, int ry0, int rx1, int ry1,
-                         int tile_rows, int ntx, int nty, hipStream_t s);
+                         int tile_rows, int ntx, int nty, hipStream_t s,
+                         hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_stage_query(const JobDev &d, int tx, int ty, int r, hipStream_t s);
 hipError_t launch_reduce_partials(const JobDev &d, int ntiles, uint64_t *out, hipStream_t s);
-hipError_t launch_commit_batched(const JobDev *slots, int nslots, hipStream_t s);
+hipError_t launch_commit_batched(const JobDev *slots, const int32_t *ids, const int32_t *n, int grid, int r,
+                                 hipStream_t s);
 hipError_t launch_count_active(const JobDev *slots, int nslots, int64_t *out, hipStream_t s);
 hipError_t launch_search_batched(const JobDev *slots, const WorkItem *items, const int32_t *nitems,
                                  int r, int tile_rows, int grid, hipStream_t s);

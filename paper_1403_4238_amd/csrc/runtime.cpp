@@ -31,7 +31,7 @@ constexpr int kDefaultTileRows = 8;
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t img, gray, hole, vrad, conf, pkey, blk, partials, tgt, qtgt, st, info, key, log, total;
+    uint64_t img, gray, hole, vrad, conf, pcd, blk, partials, tgt, qtgt, st, info, key, log, total;
     int64_t log_cap;
     int max_tiles;
 };
@@ -56,7 +56,7 @@ Layout make_layout(int W, int H, const inpaint_params &p) {
     L.hole = take(n);
     L.vrad = take(n);
     L.conf = take(8 * n);
-    L.pkey = take(8 * n);  // also the upload staging area during create (<= 6n bytes)
+    L.pcd = take(16 * n);  // also the upload staging area during create (<= 6n bytes)
     const uint64_t nblk = (uint64_t)((W + kBlock - 1) / kBlock) * ((H + kBlock - 1) / kBlock);
     L.blk = take(sizeof(BlockBest) * nblk);
     L.max_tiles = ((W + kTileW - 1) / kTileW) * ((H + search_tile_h(4) - 1) / search_tile_h(4));
@@ -116,6 +116,11 @@ struct inpaint_ctx {
     hipGraphExec_t graph = nullptr;
     int graph_n = 0;
     inpaint_batch *batch = nullptr;
+    // search-kernel timing (inpaint_profile_search)
+    bool prof = false;
+    std::vector<hipEvent_t> ev0, ev1;   // one pair per iteration of a replay
+    double prof_ms = 0.0;
+    int64_t prof_n = 0;
 
     int32_t fail(int32_t st, const std::string &msg) {
         err = msg;
@@ -187,15 +192,23 @@ static int32_t check_params(int32_t W, int32_t H, const inpaint_params *p, std::
         *why = "unknown path";
         return INPAINT_INVALID_ARGUMENT;
     }
-    if (p->graph_iters < 0 || p->log_capacity < -1) {
-        *why = "graph_iters must be >= 0 and log_capacity >= -1";
+    if (p->form < INPAINT_FORM_PLAIN || p->form > INPAINT_FORM_GRAPH) {
+        *why = "unknown form";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    if (p->form != INPAINT_FORM_PLAIN && p->iters_per_check < 1) {
+        *why = "iters_per_check must be >= 1 in the stream and graph forms";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    if (p->log_capacity < -1) {
+        *why = "log_capacity must be >= -1";
         return INPAINT_INVALID_ARGUMENT;
     }
     if (p->tile_rows != 0 && !tile_rows_ok(p->tile_rows)) {
         *why = "tile_rows must be 0, 4, 8 or 16";
         return INPAINT_INVALID_ARGUMENT;
     }
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
         if (p->reserved[i] != 0) {
             *why = "reserved fields must be zero";
             return INPAINT_INVALID_ARGUMENT;
@@ -278,7 +291,7 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     d.hole = ws + L.hole;
     d.vrad = ws + L.vrad;
     d.conf = (double *)(ws + L.conf);
-    d.pkey = (int64_t *)(ws + L.pkey);
+    d.pcd = (double2 *)(ws + L.pcd);
     d.blk = (BlockBest *)(ws + L.blk);
     d.partials = (uint64_t *)(ws + L.partials);
     d.tgt = (TargetStage *)(ws + L.tgt);
@@ -295,9 +308,9 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     d.norm2 = std::sqrt(2.0) * 255.0;
 
     // Upload: compact RGB(A) rows and the mask into the staging area (the
-    // priority-key plane, unused until the priorities are initialised).
+    // priority-term plane, unused until the priorities are initialised).
     const uint64_t n = (uint64_t)W * H;
-    uint8_t *stage_rgb = (uint8_t *)d.pkey;
+    uint8_t *stage_rgb = (uint8_t *)d.pcd;
     uint8_t *stage_mask = stage_rgb + 4 * n;
     uint8_t *hdist = stage_mask + n;
     hipStream_t s = c->stream;
@@ -407,11 +420,38 @@ int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t tx, int32_t ty, int32_t 
     return INPAINT_OK;
 }
 
-static hipError_t enqueue_iteration(inpaint_ctx *ctx, hipStream_t s) {
+static hipError_t ensure_events(inpaint_ctx *ctx, size_t n) {
+    while (ctx->ev0.size() < n) {
+        hipEvent_t a, b;
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        if (e != hipSuccess) return e;
+        ctx->ev0.push_back(a);
+        ctx->ev1.push_back(b);
+    }
+    return hipSuccess;
+}
+
+// One fill iteration: exemplar search, then the commit kernel.  With timing
+// on, event pair `slot` brackets the search.
+static hipError_t enqueue_iteration(inpaint_ctx *ctx, hipStream_t s, int slot = -1) {
     const JobDev &d = ctx->d;
-    hipError_t e = launch_search(d, false, d.r, d.rx0, d.ry0, d.rx1, d.ry1, d.tile_rows, d.ntx, d.nty, s);
+    hipError_t e = hipSuccess;
+    e = launch_search(d, false, d.r, d.rx0, d.ry0, d.rx1, d.ry1, d.tile_rows, d.ntx, d.nty, s,
+                      slot >= 0 ? ctx->ev0[slot] : nullptr, slot >= 0 ? ctx->ev1[slot] : nullptr);
     if (e == hipSuccess) e = launch_commit(d, s);
     return e;
+}
+
+// Adds the search times of the first `ran` event pairs (after a sync).
+static void collect_times(inpaint_ctx *ctx, int64_t ran) {
+    for (int64_t i = 0; i < ran && i < (int64_t)ctx->ev0.size(); ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ctx->ev0[i], ctx->ev1[i]) == hipSuccess) {
+            ctx->prof_ms += ms;
+            ctx->prof_n += 1;
+        }
+    }
 }
 
 static int32_t check_device_state(inpaint_ctx *ctx) {
@@ -429,10 +469,13 @@ int32_t inpaint_step(inpaint_ctx *ctx, inpaint_step_info *info) {
     if (ctx->batch) return ctx->fail(INPAINT_INVALID_ARGUMENT, "context is attached to a batch");
     if (ctx->h_state->done) return INPAINT_DONE;
     hipStream_t s = ctx->stream;
-    HIP_OR_FAIL(ctx, ctx->set_limit(ctx->h_state->iter + 1), "limit");
-    HIP_OR_FAIL(ctx, enqueue_iteration(ctx, s), "launch");
+    const int64_t before = ctx->h_state->iter;
+    HIP_OR_FAIL(ctx, ctx->set_limit(before + 1), "limit");
+    if (ctx->prof) HIP_OR_FAIL(ctx, ensure_events(ctx, 1), "events");
+    HIP_OR_FAIL(ctx, enqueue_iteration(ctx, s, ctx->prof ? 0 : -1), "launch");
     HIP_OR_FAIL(ctx, ctx->pull_state(), "state");
     if (check_device_state(ctx) != INPAINT_OK) return INPAINT_DEVICE;
+    if (ctx->prof) collect_times(ctx, ctx->h_state->iter - before);
     if (info) std::memcpy(info, &ctx->h_state->last, sizeof(*info));
     return INPAINT_OK;
 }
@@ -467,15 +510,28 @@ int32_t inpaint_run(inpaint_ctx *ctx, int64_t max_iters, int64_t *iters_done, in
     const int64_t limit = max_iters < 0 ? INT64_MAX : start + max_iters;
     hipStream_t s = ctx->stream;
     HIP_OR_FAIL(ctx, ctx->set_limit(limit), "limit");
-    const int G = ctx->p.graph_iters;
-    if (G > 0) HIP_OR_FAIL(ctx, ensure_graph(ctx, G), "graph capture");
+    const int form = ctx->p.form;
+    const int G = form == INPAINT_FORM_PLAIN ? 1 : ctx->p.iters_per_check;
+    if (form == INPAINT_FORM_GRAPH) {
+        if (ctx->prof) return ctx->fail(INPAINT_INVALID_ARGUMENT, "search timing is not available in the graph form");
+        HIP_OR_FAIL(ctx, ensure_graph(ctx, G), "graph capture");
+    } else if (ctx->prof) {
+        HIP_OR_FAIL(ctx, ensure_events(ctx, G), "events");
+    }
     for (;;) {
-        if (G > 0)
+        const int64_t before = ctx->h_state->iter;
+        if (form == INPAINT_FORM_GRAPH) {
             HIP_OR_FAIL(ctx, hipGraphLaunch(ctx->graph, s), "graph launch");
-        else
-            HIP_OR_FAIL(ctx, enqueue_iteration(ctx, s), "launch");
+        } else {
+            // Stop enqueueing at the iteration limit; past the end of the
+            // hole the kernels are no-ops.
+            const int64_t n = std::min<int64_t>(G, limit - before);
+            for (int64_t i = 0; i < n; ++i)
+                HIP_OR_FAIL(ctx, enqueue_iteration(ctx, s, ctx->prof ? (int)i : -1), "launch");
+        }
         HIP_OR_FAIL(ctx, ctx->pull_state(), "state");
         if (check_device_state(ctx) != INPAINT_OK) return INPAINT_DEVICE;
+        if (ctx->prof) collect_times(ctx, ctx->h_state->iter - before);
         if (ctx->h_state->done || ctx->h_state->iter >= limit) break;
     }
     const int64_t ran = ctx->h_state->iter - start;
@@ -542,6 +598,21 @@ int32_t inpaint_remaining(inpaint_ctx *ctx, int64_t *remaining) {
     return INPAINT_OK;
 }
 
+int32_t inpaint_profile_search(inpaint_ctx *ctx, int32_t enable) {
+    if (!ctx) return INPAINT_INVALID_ARGUMENT;
+    ctx->prof = enable != 0;
+    ctx->prof_ms = 0.0;
+    ctx->prof_n = 0;
+    return INPAINT_OK;
+}
+
+int32_t inpaint_search_time(inpaint_ctx *ctx, double *total_ms, int64_t *searches) {
+    if (!ctx) return INPAINT_INVALID_ARGUMENT;
+    if (total_ms) *total_ms = ctx->prof_ms;
+    if (searches) *searches = ctx->prof_n;
+    return INPAINT_OK;
+}
+
 int32_t inpaint_batch_detach(inpaint_batch *b, inpaint_ctx *ctx);
 
 int32_t inpaint_destroy(inpaint_ctx *ctx) {
@@ -549,6 +620,8 @@ int32_t inpaint_destroy(inpaint_ctx *ctx) {
     if (ctx->batch) inpaint_batch_detach(ctx->batch, ctx);
     hipStreamSynchronize(ctx->stream);
     if (ctx->graph) hipGraphExecDestroy(ctx->graph);
+    for (auto ev : ctx->ev0) hipEventDestroy(ev);
+    for (auto ev : ctx->ev1) hipEventDestroy(ev);
     if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     if (ctx->h_state) hipHostFree(ctx->h_state);
     if (ctx->h_key) hipHostFree(ctx->h_key);
@@ -568,9 +641,12 @@ struct TuneChoice {
 };
 
 struct RadiusGroup {
-    std::vector<WorkItem> items;
+    std::vector<WorkItem> items;     // (slot, tile) search work list
+    std::vector<int32_t> ids;        // slots of this radius (commit list)
     WorkItem *d_items = nullptr;
-    int32_t *d_n = nullptr;
+    int32_t *d_n = nullptr;          // [0] = items, [1] = ids
+    int32_t *d_ids = nullptr;        // capacity entries
+    int32_t *h_n = nullptr;          // pinned staging of the two counts
     size_t cap = 0;
     TuneChoice tune;
     bool tuned = false;
@@ -657,30 +733,41 @@ JobDev slot_desc(const inpaint_ctx *c, int tile_rows) {
 
 hipError_t upload_group(inpaint_batch *b, RadiusGroup &g) {
     const size_t n = g.items.size();
+    hipError_t e = hipSuccess;
+    if (!g.d_ids) {
+        e = hipMalloc(&g.d_ids, sizeof(int32_t) * b->slots.size());
+        if (e == hipSuccess) e = hipMalloc(&g.d_n, 2 * sizeof(int32_t));
+        if (e == hipSuccess) e = hipHostMalloc((void **)&g.h_n, 2 * sizeof(int32_t), hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+    }
     if (n > g.cap || !g.d_items) {
         if (g.d_items) hipFree(g.d_items);
-        if (g.d_n) hipFree(g.d_n);
         g.cap = std::max<size_t>(n, 1024) * 2;
-        hipError_t e = hipMalloc(&g.d_items, g.cap * sizeof(WorkItem));
-        if (e == hipSuccess) e = hipMalloc(&g.d_n, sizeof(int32_t));
+        e = hipMalloc(&g.d_items, g.cap * sizeof(WorkItem));
         if (e != hipSuccess) return e;
-        b->graph_sig.clear();  // pointers changed: recapture
+        b->graph_sig.clear();  // pointer changed: recapture
     }
-    hipError_t e = hipSuccess;
     if (n) e = hipMemcpyAsync(g.d_items, g.items.data(), n * sizeof(WorkItem), hipMemcpyHostToDevice, b->stream);
-    const int32_t nn = (int32_t)n;
-    if (e == hipSuccess) e = hipMemcpyAsync(g.d_n, &nn, sizeof(int32_t), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // nn is on the stack
+    if (e == hipSuccess && !g.ids.empty())
+        e = hipMemcpyAsync(g.d_ids, g.ids.data(), g.ids.size() * sizeof(int32_t), hipMemcpyHostToDevice, b->stream);
+    g.h_n[0] = (int32_t)n;
+    g.h_n[1] = (int32_t)g.ids.size();
+    if (e == hipSuccess) e = hipMemcpyAsync(g.d_n, g.h_n, 2 * sizeof(int32_t), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);  // host vectors may change next
     return e;
 }
 
 // Rebuilds every radius group's (slot, tile) list for its tile shape.
 hipError_t rebuild(inpaint_batch *b) {
-    for (auto &kv : b->groups) kv.second.items.clear();
+    for (auto &kv : b->groups) {
+        kv.second.items.clear();
+        kv.second.ids.clear();
+    }
     for (size_t i = 0; i < b->slots.size(); ++i) {
         inpaint_ctx *c = b->slots[i];
         if (!c) continue;
         RadiusGroup &g = b->groups[c->d.r];
+        g.ids.push_back((int32_t)i);
         b->h_slots[i] = slot_desc(c, g.tune.tile_rows);
         const int nt = b->h_slots[i].ntx * b->h_slots[i].nty;
         for (int t = 0; t < nt; ++t) g.items.push_back(WorkItem{(int32_t)i, t});
@@ -695,21 +782,30 @@ hipError_t rebuild(inpaint_batch *b) {
     return hipSuccess;
 }
 
+// Persistent grid of the batched search: the tuned size, else 8 work-groups
+// per CU.  It does not depend on the work-list length, so a captured graph
+// survives attach / detach.
 int grid_for(const inpaint_batch *b, const RadiusGroup &g) {
-    const int n = (int)g.items.size();
-    if (g.tune.grid > 0) return std::max(1, std::min(g.tune.grid, n));
-    return std::max(1, n);
+    if (g.tune.grid > 0) return g.tune.grid;
+    return 8 * b->cu_count;
 }
 
+// One batch iteration: the persistent search of every radius group, then
+// the commit work-groups of every group.  Work-list lengths are read on the
+// device, so the captured graph stays valid while slots come and go.
 hipError_t enqueue_batch_iteration(inpaint_batch *b, hipStream_t s) {
     for (auto &kv : b->groups) {
         RadiusGroup &g = kv.second;
-        if (g.items.empty()) continue;
         hipError_t e = launch_search_batched(b->d_slots, g.d_items, g.d_n, kv.first, g.tune.tile_rows,
                                              grid_for(b, g), s);
         if (e != hipSuccess) return e;
     }
-    return launch_commit_batched(b->d_slots, (int)b->slots.size(), s);
+    for (auto &kv : b->groups) {
+        hipError_t e = launch_commit_batched(b->d_slots, kv.second.d_ids, kv.second.d_n + 1,
+                                             (int)b->slots.size(), kv.first, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // Times the batched search of one radius group for each tile shape and
@@ -739,8 +835,8 @@ hipError_t autotune_group(inpaint_batch *b, int r, RadiusGroup &g, std::map<std:
         hipError_t e = rebuild(b);
         if (e != hipSuccess) return e;
         const int n = (int)g.items.size();
-        for (int grid : {b->cu_count, 2 * b->cu_count, 4 * b->cu_count, 8 * b->cu_count, 0}) {
-            if (grid > n) continue;
+        for (int grid : {b->cu_count, 2 * b->cu_count, 4 * b->cu_count, 8 * b->cu_count, 16 * b->cu_count}) {
+            if (grid > 2 * n + b->cu_count) continue;
             g.tune.grid = grid;
             float ms_min = 1e30f;
             for (int rep = 0; rep < 3; ++rep) {
@@ -858,7 +954,7 @@ int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active) {
     std::string sig = std::to_string(G);
     for (auto &kv : b->groups)
         sig += "|" + std::to_string(kv.first) + ":" + std::to_string(kv.second.tune.tile_rows) + ":" +
-               std::to_string(grid_for(b, kv.second)) + ":" + std::to_string(kv.second.items.empty());
+               std::to_string(grid_for(b, kv.second));
     if (sig != b->graph_sig || !b->graph) {
         if (b->graph) hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
@@ -891,6 +987,8 @@ int32_t inpaint_batch_destroy(inpaint_batch *b) {
     for (auto &kv : b->groups) {
         if (kv.second.d_items) hipFree(kv.second.d_items);
         if (kv.second.d_n) hipFree(kv.second.d_n);
+        if (kv.second.d_ids) hipFree(kv.second.d_ids);
+        if (kv.second.h_n) hipHostFree(kv.second.h_n);
     }
     if (b->d_slots) hipFree(b->d_slots);
     if (b->d_active) hipFree(b->d_active);

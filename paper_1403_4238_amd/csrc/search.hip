@@ -20,6 +20,8 @@
 // are reduced to one key (ssd << 32 | raster index) per tile: the minimum key
 // is the (ssd, index)-lexicographic minimum, i.e. ties go to the lowest
 // raster index.  No SSD array is ever written.
+#include <hip/hip_ext.h>
+
 #include "inpaint_dev.h"
 
 namespace inpaint {
@@ -34,6 +36,11 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
     return v;
 }
 
+// The target patch is read-only for the whole search and uniform across the
+// wave; reading it through the constant address space lets the compiler use
+// scalar loads into SGPRs instead of a vector memory round trip per offset.
+typedef const __attribute__((address_space(4))) TargetStage ConstTarget;
+
 template <int R, int NY>
 struct TileGeom {
     static constexpr int P = 2 * R + 1;
@@ -45,11 +52,12 @@ struct TileGeom {
 
 // Scores one tile and writes its minimum key to out[tile].
 template <int R, int NY>
-__device__ __forceinline__ void search_tile(const JobDev &d, const TargetStage *__restrict__ tg,
+__device__ __forceinline__ void search_tile(const JobDev &d, const TargetStage *tg_generic,
                                             int rx0, int ry0, int rx1, int ry1, int ntx, int tile,
                                             uint64_t *__restrict__ out, uint32_t *lds,
                                             uint64_t *red) {
     using G = TileGeom<R, NY>;
+    ConstTarget *tg = (ConstTarget *)tg_generic;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tx0 = rx0 + (tile % ntx) * kTileW;
     const int ty0 = ry0 + (tile / ntx) * G::TH;
@@ -86,9 +94,16 @@ __device__ __forceinline__ void search_tile(const JobDev &d, const TargetStage *
         A[i] = 0;
         B[i] = 0;
     }
+    uint32_t mb[(G::P * G::P + 31) / 32];
+#pragma unroll
+    for (int w = 0; w < (G::P * G::P + 31) / 32; ++w) mb[w] = tg->mbits[w];
     const uint32_t *colp = lds + wave * NY * G::LW + lane;
 #pragma unroll
     for (int dxi = 0; dxi < G::P; ++dxi) {
+        // This column's target words, loaded unconditionally (scalar loads).
+        uint32_t tcol[G::P];
+#pragma unroll
+        for (int dyi = 0; dyi < G::P; ++dyi) tcol[dyi] = tg->tpix[dxi * G::P + dyi];
         uint32_t col[NY + 2 * R], sq[NY + 2 * R];
 #pragma unroll
         for (int j = 0; j < NY + 2 * R; ++j) {
@@ -97,9 +112,9 @@ __device__ __forceinline__ void search_tile(const JobDev &d, const TargetStage *
         }
 #pragma unroll
         for (int dyi = 0; dyi < G::P; ++dyi) {
-            const int slot = dyi * G::P + dxi;
-            if (tg->mbits[slot >> 5] & (1u << (slot & 31))) {
-                const uint32_t t = tg->tpix[slot];
+            const int slot = dxi * G::P + dyi;
+            if (mb[slot >> 5] & (1u << (slot & 31))) {
+                const uint32_t t = tcol[dyi];
 #pragma unroll
                 for (int i = 0; i < NY; ++i) {
                     A[i] = __builtin_amdgcn_udot4(t, col[i + dyi], A[i], false);
@@ -176,22 +191,28 @@ __global__ __launch_bounds__(kSearchWaves * 64) void k_search_batched(const JobD
 
 template <int R, int NY>
 hipError_t launch_search_t(const JobDev &d, bool query, int rx0, int ry0, int rx1, int ry1, int ntx,
-                           int nty, hipStream_t s) {
+                           int nty, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
     const int ntiles = ntx * nty;
     if (ntiles <= 0) return hipSuccess;
     const int grid = (ntiles + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_search<R, NY>), dim3(grid), dim3(kSearchWaves * 64), 0, s, d, query ? 1 : 0,
-                       rx0, ry0, rx1, ry1, ntx, ntiles);
+    if (start) {
+        // The runtime stamps these events with the kernel's own begin / end.
+        hipExtLaunchKernelGGL((k_search<R, NY>), dim3(grid), dim3(kSearchWaves * 64), 0, s, start, stop, 0, d,
+                              query ? 1 : 0, rx0, ry0, rx1, ry1, ntx, ntiles);
+    } else {
+        hipLaunchKernelGGL((k_search<R, NY>), dim3(grid), dim3(kSearchWaves * 64), 0, s, d, query ? 1 : 0, rx0,
+                           ry0, rx1, ry1, ntx, ntiles);
+    }
     return hipGetLastError();
 }
 
 template <int R>
 hipError_t launch_search_r(const JobDev &d, bool query, int rx0, int ry0, int rx1, int ry1, int tile_rows,
-                           int ntx, int nty, hipStream_t s) {
+                           int ntx, int nty, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (tile_rows) {
-        case 4: return launch_search_t<R, 4>(d, query, rx0, ry0, rx1, ry1, ntx, nty, s);
-        case 8: return launch_search_t<R, 8>(d, query, rx0, ry0, rx1, ry1, ntx, nty, s);
-        case 16: return launch_search_t<R, 16>(d, query, rx0, ry0, rx1, ry1, ntx, nty, s);
+        case 4: return launch_search_t<R, 4>(d, query, rx0, ry0, rx1, ry1, ntx, nty, s, e0, e1);
+        case 8: return launch_search_t<R, 8>(d, query, rx0, ry0, rx1, ry1, ntx, nty, s, e0, e1);
+        case 16: return launch_search_t<R, 16>(d, query, rx0, ry0, rx1, ry1, ntx, nty, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
@@ -212,16 +233,16 @@ hipError_t launch_search_batched_r(const JobDev *slots, const WorkItem *items, c
 }  // namespace
 
 hipError_t launch_search(const JobDev &d, bool query, int r, int rx0, int ry0, int rx1, int ry1,
-                         int tile_rows, int ntx, int nty, hipStream_t s) {
+                         int tile_rows, int ntx, int nty, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (r) {
-        case 1: return launch_search_r<1>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s);
-        case 2: return launch_search_r<2>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s);
-        case 3: return launch_search_r<3>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s);
-        case 4: return launch_search_r<4>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s);
-        case 5: return launch_search_r<5>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s);
-        case 6: return launch_search_r<6>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s);
-        case 7: return launch_search_r<7>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s);
-        case 8: return launch_search_r<8>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s);
+        case 1: return launch_search_r<1>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 2: return launch_search_r<2>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 3: return launch_search_r<3>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 4: return launch_search_r<4>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 5: return launch_search_r<5>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 6: return launch_search_r<6>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 7: return launch_search_r<7>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 8: return launch_search_r<8>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }

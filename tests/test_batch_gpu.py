@@ -1,0 +1,109 @@
+"""The batched persistent form (many images per iteration, hipGraph replay,
+autotuned tiles) gives each image exactly its single-image result."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1403_4238_amd import synth
+
+from _util import assert_logs_equal
+
+pytestmark = pytest.mark.gpu
+
+B = pytest.importorskip("paper_1403_4238_amd.binding")
+
+
+def _mixed_jobs():
+    jobs = []
+    for seed, (W, H, r) in enumerate([(64, 48, 2), (90, 70, 4), (50, 61, 3), (128, 40, 4), (33, 33, 1),
+                                      (77, 90, 4)]):
+        rng = np.random.default_rng(200 + seed)
+        rgb = rng.integers(0, 256, size=(H, W, 3)).astype(np.uint8)
+        mask = np.zeros((H, W), np.uint8)
+        mask[H // 3:H // 3 + H // 5, W // 4:W // 4 + W // 5] = 1
+        if seed % 2:
+            mask[0:3, 0:W // 3] = 1   # a second blob on the border
+        jobs.append(synth.Job(f"mix{seed}", rgb, mask, r))
+    jobs.append(synth.small())
+    return jobs
+
+
+def _oracle_result(job):
+    o = oracle.Oracle(job.rgb, job.mask, job.patch_radius)
+    log = o.run()
+    return log, o.read()[0]
+
+
+@pytest.mark.parametrize("G,autotune", [(4, False), (7, True)])
+def test_batch_equals_alone(tmp_path, G, autotune):
+    jobs = _mixed_jobs()
+    cache = str(tmp_path / "tune.json")
+    batch = B.Batch(capacity=len(jobs) + 2, graph_iters=G, autotune=autotune, tune_cache=cache)
+    ctxs = [B.Inpainter(j.rgb, j.mask, j.patch_radius) for j in jobs]
+    for c in ctxs:
+        batch.attach(c)
+    steps = 0
+    while batch.step() > 0:
+        steps += 1
+        assert steps < 10_000
+    for j, c in zip(jobs, ctxs):
+        want_log, want_img = _oracle_result(j)
+        got = c.read_log(0, len(want_log))
+        assert_logs_equal(got, want_log, j.name)
+        assert c.remaining() == 0
+        assert (c.read_image() == want_img).all(), j.name
+    if autotune:
+        assert os.path.exists(cache)
+        # a second batch picks its choices from the cache and still agrees
+        b2 = B.Batch(capacity=2, graph_iters=G, autotune=True, tune_cache=cache)
+        c2 = B.Inpainter(jobs[1].rgb, jobs[1].mask, jobs[1].patch_radius)
+        b2.attach(c2)
+        while b2.step() > 0:
+            pass
+        want_log, _ = _oracle_result(jobs[1])
+        assert_logs_equal(c2.read_log(0, len(want_log)), want_log, "cached tune")
+
+
+def test_attach_detach_mid_run():
+    jobs = _mixed_jobs()
+    batch = B.Batch(capacity=4, graph_iters=3, autotune=False)
+    ctxs = [B.Inpainter(j.rgb, j.mask, j.patch_radius) for j in jobs]
+    batch.attach(ctxs[0])
+    batch.attach(ctxs[1])
+    batch.step()
+    batch.attach(ctxs[2])            # joins while the others are mid-run
+    batch.step()
+    batch.detach(ctxs[1])            # leaves unfinished ...
+    batch.attach(ctxs[3])            # ... and its slot is reused
+    batch.step()
+    with pytest.raises(B.InpaintError):
+        batch.attach(ctxs[0])        # already attached
+    batch.attach(ctxs[4])
+    with pytest.raises(B.InpaintError):
+        batch.attach(ctxs[5])        # full
+    while batch.step() > 0:
+        pass
+    ctxs[1].run()                    # the detached job finishes on its own
+    for i in range(5):
+        want_log, want_img = _oracle_result(jobs[i])
+        assert_logs_equal(ctxs[i].read_log(0, len(want_log)), want_log, jobs[i].name)
+        assert (ctxs[i].read_image() == want_img).all()
+
+
+def test_batch_of_vga_sized_images_prefix():
+    # Two 640x480 images in one batch for a few replays: every logged
+    # iteration equals the oracle's (the oracle runs the same prefix).
+    a = synth.vga()
+    b = synth.Job("vga-shift", np.ascontiguousarray(a.rgb[::-1]), np.ascontiguousarray(a.mask[:, ::-1]), 4)
+    batch = B.Batch(capacity=2, graph_iters=5, autotune=False)
+    ctxs = [B.Inpainter(j.rgb, j.mask, 4) for j in (a, b)]
+    for c in ctxs:
+        batch.attach(c)
+    batch.step()
+    batch.step()
+    for j, c in zip((a, b), ctxs):
+        o = oracle.Oracle(j.rgb, j.mask, 4)
+        want = o.run(max_iters=10)
+        assert_logs_equal(c.read_log(0, 10), want, j.name)

@@ -198,22 +198,23 @@ def test_tile_shapes_give_identical_results(tile_rows):
     assert_logs_equal(got, o.run(), f"tile_rows={tile_rows}")
 
 
-def test_graph_form_equals_plain_form():
+@pytest.mark.parametrize("form,n", [("stream", 5), ("graph", 5), ("graph", 1), ("stream", 64)])
+def test_forms_equal_plain_form(form, n):
     job = synth.small()
-    plain = B.Inpainter(job.rgb, job.mask, 4, graph_iters=0)
-    graph = B.Inpainter(job.rgb, job.mask, 4, graph_iters=5)
+    plain = B.Inpainter(job.rgb, job.mask, 4, form="plain")
+    other = B.Inpainter(job.rgb, job.mask, 4, form=form, iters_per_check=n)
     _, n1, l1 = plain.run(log_cap=100)
-    _, n2, l2 = graph.run(log_cap=100)
+    _, n2, l2 = other.run(log_cap=100)
     assert n1 == n2
-    assert_logs_equal(l2, l1, "graph")
-    assert (plain.read_image() == graph.read_image()).all()
+    assert_logs_equal(l2, l1, f"{form} {n}")
+    assert (plain.read_image() == other.read_image()).all()
 
 
 def test_step_and_partial_runs_equal_one_run():
     job = synth.small()
     o = oracle.Oracle(job.rgb, job.mask, 4)
     want = o.run()
-    g = B.Inpainter(job.rgb, job.mask, 4, graph_iters=3)
+    g = B.Inpainter(job.rgb, job.mask, 4, form="graph", iters_per_check=3)
     recs = [g.step(), g.step()]
     st, n, more = g.run(max_iters=4, log_cap=10)
     assert st == B.OK and n == 4
@@ -263,7 +264,8 @@ def test_hd_full_run_matches_stored_oracle(key):
         pytest.skip(f"stored oracle result for {key} not generated")
     job = synth.hd(patch=int(key[2:].rstrip("w")), window=key.endswith("w"))
     assert job.sha256() == gold["input_sha256"]
-    g = B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, graph_iters=16)
+    g = B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, form="stream",
+                    iters_per_check=32)
     st, n, log = g.run(log_cap=gold["iterations"] + 8)
     assert st == B.DONE
     assert_matches_golden(gold, log, g.read_image(), key)
@@ -278,3 +280,20 @@ def test_hd_first_iterations_live_oracle(patch, window):
     want = o.run(max_iters=2)
     _, _, got = g.run(max_iters=2, log_cap=4)
     assert_logs_equal(got, want, f"hd p{patch} {'win' if window else 'full'}")
+
+
+@pytest.mark.parametrize("form", ["plain", "stream"])
+def test_search_timing_hooks(form):
+    job = synth.small()
+    o = oracle.Oracle(job.rgb, job.mask, 4)
+    g = B.Inpainter(job.rgb, job.mask, 4, form=form, iters_per_check=4)
+    g.profile_search(True)
+    st, n, log = g.run(log_cap=100)
+    ms, cnt = g.search_time()
+    assert st == B.DONE and cnt == n and ms > 0.0
+    assert_logs_equal(log, o.run(), f"timed {form}")
+    gg = B.Inpainter(job.rgb, job.mask, 4, form="graph", iters_per_check=4)
+    gg.profile_search(True)
+    with pytest.raises(B.InpaintError) as e:
+        gg.run()
+    assert e.value.status == B.INVALID_ARGUMENT
