@@ -42,7 +42,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="hd", choices=["hd", "vga", "small"])
+    ap.add_argument("--workload", default="hd", choices=["hd", "vga", "small", "batch", "serve"])
+    ap.add_argument("--jobs", type=int, default=32, help="serve: number of jobs")
+    ap.add_argument("--graph-iters", type=int, default=16, help="batch / serve: iterations per replay")
+    ap.add_argument("--capacity", type=int, default=16, help="serve: batch slots")
+    ap.add_argument("--budget-gb", type=float, default=4.0, help="serve: device memory budget")
     ap.add_argument("--patch", type=int, default=9)
     ap.add_argument("--window", action="store_true", help="alpha = 1 search window (3x the hole bbox)")
     ap.add_argument("--form", default="stream", choices=["stream", "plain"],
@@ -148,6 +152,138 @@ def golden_check(job, a, log, image):
     return "bit-exact vs stored oracle" if ok else "MISMATCH vs stored oracle"
 
 
+def batch_bench(a):
+    """64 images of uneven size: batched persistent form vs one after another."""
+    import torch
+    from paper_1403_4238_amd import binding as B
+    from paper_1403_4238_amd import synth
+    jobs = synth.batch()
+    tune = os.path.join(ROOT, "gpurun_out", "tune_cache.json") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) \
+        else None
+
+    def make(form="plain"):
+        return [B.Inpainter(j.rgb, j.mask, j.patch_radius, form=form, iters_per_check=a.iters_per_check)
+                for j in jobs]
+
+    batch = B.Batch(capacity=len(jobs), graph_iters=a.graph_iters, autotune=True, tune_cache=tune)
+    # warm-up set: first step tunes the tile shape / grid and captures the graph
+    warm = make()
+    for c in warm:
+        batch.attach(c)
+    batch.step()
+    for c in warm:
+        batch.detach(c)
+        c.close()
+    del warm
+    ctxs = make()
+    for c in ctxs:
+        batch.attach(c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = 0
+    while batch.step() > 0:
+        steps += 1
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = [c.progress()[0] for c in ctxs]
+    cands = [c.search_info()[1] for c in ctxs]
+    evals = sum(i * n for i, n in zip(iters, cands))
+    # parity with the stored oracle results, where present
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _util import load_golden, log_sha256
+    checked = ok = 0
+    for i, (j, c) in enumerate(zip(jobs, ctxs)):
+        gold = load_golden(f"batch{i:02d}")
+        if gold is None:
+            continue
+        checked += 1
+        log = c.read_log(0, iters[i])
+        ok += (gold["input_sha256"] == j.sha256() and gold["log_sha256"] == log_sha256(log)
+               and gold["final_rgb_sha256"] == hashlib.sha256(c.read_image().tobytes()).hexdigest())
+    for c in ctxs:
+        batch.detach(c)
+        c.close()
+    del ctxs
+    # the plain form: each image alone, two launches + one host check per iteration
+    plain = {}
+    for form in ("plain", "stream"):
+        cs = make(form)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for c in cs:
+            c.run()
+        torch.cuda.synchronize()
+        plain[form] = time.perf_counter() - t1
+        for c in cs:
+            c.close()
+    line = {
+        "metric": "masked-SSD patch evals/s (batch of 64 images, batched persistent form)",
+        "value": round(evals / dt, 1), "unit": "patch evals/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(1000 * dt, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8 (SSD: u8 x u8 -> u32 exact; priority: f64)", "data": "synthetic (seeded)",
+        "config": {"workload": "batch of 64 RGB u8 images 320x240..1280x720, 1-3 blobs covering 2-10%, "
+                               "9x9 patch, full search; one persistent search launch + one commit launch "
+                               f"per iteration for all images, hipGraph of {a.graph_iters} iterations, "
+                               "autotuned tiles",
+                   "images": len(jobs), "total_iterations": int(sum(iters)), "batch_steps": steps + 1},
+        "batched_ms": round(1000 * dt, 2),
+        "one_by_one": {f: {"ms": round(1000 * t, 2), "patch_evals_per_s": round(evals / t, 1)}
+                       for f, t in plain.items()},
+        "speedup_vs_plain": round(plain["plain"] / dt, 3),
+        "parity": f"{ok}/{checked} images bit-exact vs stored oracle",
+    }
+    print(json.dumps(line), flush=True)
+
+
+def serve_bench(a):
+    """Poisson arrivals, memory-admitted continuous batching: p50/p99 latency."""
+    import torch
+    from paper_1403_4238_amd import binding as B
+    from paper_1403_4238_amd import serve, synth
+    jobs = synth.serving(n=a.jobs)
+    budget = int(a.budget_gb * (1 << 30))
+
+    def run(js):
+        eng = serve.GpuEngine(capacity=a.capacity, graph_iters=a.graph_iters, autotune=True, log=False)
+        srv = serve.Server(eng, budget, a.capacity, a.graph_iters, keep_results=True)
+        torch.cuda.synchronize()
+        recs = srv.run(js)
+        torch.cuda.synchronize()
+        return srv, recs
+
+    # capacity: everything arrives at once
+    sat_jobs = synth.rescaled_arrivals(jobs, 1e9)
+    run(sat_jobs[:2])   # warm-up (tuning, graph capture)
+    srv_sat, recs_sat = run(sat_jobs)
+    sat = serve.summarize(recs_sat)
+    rate = 0.7 * sat["jobs_per_s"]
+    srv_p, recs_p = run(synth.rescaled_arrivals(jobs, rate))
+    poisson = serve.summarize(recs_p)
+    # each served image equals the same job run alone (first jobs)
+    same = 0
+    n_check = min(4, len(jobs))
+    for j, r in zip(jobs[:n_check], recs_p[:n_check]):
+        alone = B.Inpainter(j.rgb, j.mask, j.patch_radius, log_capacity=0)
+        alone.run()
+        same += bool((alone.read_image() == r.result["image"]).all())
+        alone.close()
+    line = {
+        "metric": "serving: jobs/s and p50/p99 latency (Poisson arrivals at 0.7x measured capacity)",
+        "value": poisson["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1, "steps": len(jobs), "warmup": 2,
+        "ms_per_step": poisson["mean_latency_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8 (SSD: u8 x u8 -> u32 exact; priority: f64)",
+        "data": "synthetic (seeded)",
+        "config": {"workload": f"{len(jobs)} removal jobs, RGB u8 256x256..2048x1536, holes 1-10% (1-3 blobs), "
+                               "patch 7/9/11, full search; admission by workspace bytes "
+                               f"(budget {a.budget_gb} GiB), {a.capacity} slots, G={a.graph_iters}",
+                   "rate_jobs_per_s": round(rate, 3)},
+        "poisson": poisson, "saturation": sat,
+        "peak_active": srv_p.peak_active, "peak_bytes": srv_p.peak_used,
+        "mix_equals_alone": f"{same}/{n_check}",
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -156,6 +292,10 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.workload == "batch":
+        return batch_bench(a)
+    if a.workload == "serve":
+        return serve_bench(a)
     job = make_job(a)
     res = timed_removals(job, a.steps, a.warmup, a.form, a.iters_per_check, a.tile_rows)
     n_steps = a.steps

@@ -188,6 +188,10 @@ int32_t inpaint_read_state(inpaint_ctx *ctx, uint8_t *mask, double *conf);
 /* Hole pixels still to fill.  Synchronises. */
 int32_t inpaint_remaining(inpaint_ctx *ctx, int64_t *remaining);
 
+/* Iterations committed so far and hole pixels left (either may be NULL).
+ * Synchronises. */
+int32_t inpaint_progress(inpaint_ctx *ctx, int64_t *iterations, int64_t *remaining);
+
 /* The context's search rectangle after clipping (alpha windows resolved) and
  * the number of valid source centres in it, i.e. patch evaluations per
  * search.  No device work. */
@@ -244,6 +248,15 @@ int32_t inpaint_batch_detach(inpaint_batch *b, inpaint_ctx *ctx);
 /* Runs G iterations for every attached image and writes the number of
  * attached images still unfinished to *active.  Synchronises once. */
 int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active);
+
+/* State of a slot as of the end of the last inpaint_batch_step:
+ * 0 empty, 1 running, 2 finished (hole empty), 3 device error.  No device
+ * work. */
+#define INPAINT_SLOT_EMPTY    0
+#define INPAINT_SLOT_RUNNING  1
+#define INPAINT_SLOT_FINISHED 2
+#define INPAINT_SLOT_ERROR    3
+int32_t inpaint_batch_status(const inpaint_batch *b, int32_t slot, int32_t *status);
 
 int32_t inpaint_batch_destroy(inpaint_batch *b);
 

@@ -82,6 +82,8 @@ def lib() -> ctypes.CDLL:
         "inpaint_read_state": (i32, [vp, vp, vp]),
         "inpaint_remaining": (i32, [vp, P(i64)]),
         "inpaint_search_info": (i32, [vp, P(inpaint_rect), P(i64)]),
+        "inpaint_progress": (i32, [vp, P(i64), P(i64)]),
+        "inpaint_batch_status": (i32, [vp, i32, P(i32)]),
         "inpaint_profile_search": (i32, [vp, i32]),
         "inpaint_search_time": (i32, [vp, P(ctypes.c_double), P(i64)]),
         "inpaint_destroy": (i32, [vp]),
@@ -240,6 +242,12 @@ class Inpainter:
         self._check(lib().inpaint_remaining(self.ctx, ctypes.byref(out)), "inpaint_remaining")
         return out.value
 
+    def progress(self):
+        """(iterations committed, hole pixels left)."""
+        it, rem = ctypes.c_int64(), ctypes.c_int64()
+        self._check(lib().inpaint_progress(self.ctx, ctypes.byref(it), ctypes.byref(rem)), "inpaint_progress")
+        return it.value, rem.value
+
     def profile_search(self, enable: bool = True):
         self._check(lib().inpaint_profile_search(self.ctx, 1 if enable else 0), "inpaint_profile_search")
 
@@ -277,6 +285,20 @@ class Batch:
             raise InpaintError(st, "inpaint_batch_attach", inpaint_last_error(job.ctx))
         self.members[slot.value] = job
         return slot.value
+
+    def slot_of(self, job: Inpainter) -> int:
+        for k, v in self.members.items():
+            if v is job:
+                return k
+        raise KeyError("job is not attached")
+
+    def status(self, job: Inpainter) -> int:
+        """Slot state after the last step: 1 running, 2 finished, 3 error."""
+        out = ctypes.c_int32()
+        st = lib().inpaint_batch_status(self.h, self.slot_of(job), ctypes.byref(out))
+        if st != OK:
+            raise InpaintError(st, "inpaint_batch_status")
+        return out.value
 
     def detach(self, job: Inpainter):
         st = lib().inpaint_batch_detach(self.h, job.ctx)

@@ -643,14 +643,18 @@ __global__ __launch_bounds__(kCommitThreads) void k_reduce_partials(const uint64
     if (threadIdx.x == 0) *out = best;
 }
 
-// Number of attached images that are still unfinished and error-free.
-__global__ void k_count_active(const JobDev *slots, int nslots, int64_t *out) {
+// Number of attached images that are still unfinished and error-free, and
+// each slot's state (0 empty, 1 running, 2 finished, 3 error).
+__global__ void k_count_active(const JobDev *slots, int nslots, int64_t *out, int32_t *status) {
     __shared__ int cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
     for (int i = threadIdx.x; i < nslots; i += blockDim.x) {
         const IterState *st = slots[i].st;
-        if (st && !st->done && !st->error) atomicAdd(&cnt, 1);
+        int v = 0;
+        if (st) v = st->error ? 3 : (st->done ? 2 : 1);
+        if (v == 1) atomicAdd(&cnt, 1);
+        status[i] = v;
     }
     __syncthreads();
     if (threadIdx.x == 0) *out = cnt;
@@ -727,8 +731,8 @@ hipError_t launch_reduce_partials(const JobDev &d, int ntiles, uint64_t *out, hi
     return hipGetLastError();
 }
 
-hipError_t launch_count_active(const JobDev *slots, int nslots, int64_t *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, s, slots, nslots, out);
+hipError_t launch_count_active(const JobDev *slots, int nslots, int64_t *out, int32_t *status, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, s, slots, nslots, out, status);
     return hipGetLastError();
 }
 

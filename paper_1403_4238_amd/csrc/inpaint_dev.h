@@ -111,7 +111,7 @@ hipError_t launch_stage_query(const JobDev &d, int tx, int ty, int r, hipStream_
 hipError_t launch_reduce_partials(const JobDev &d, int ntiles, uint64_t *out, hipStream_t s);
 hipError_t launch_commit_batched(const JobDev *slots, const int32_t *ids, const int32_t *n, int grid, int r,
                                  hipStream_t s);
-hipError_t launch_count_active(const JobDev *slots, int nslots, int64_t *out, hipStream_t s);
+hipError_t launch_count_active(const JobDev *slots, int nslots, int64_t *out, int32_t *status, hipStream_t s);
 hipError_t launch_search_batched(const JobDev *slots, const WorkItem *items, const int32_t *nitems,
                                  int r, int tile_rows, int grid, hipStream_t s);
 

@@ -598,6 +598,15 @@ int32_t inpaint_remaining(inpaint_ctx *ctx, int64_t *remaining) {
     return INPAINT_OK;
 }
 
+int32_t inpaint_progress(inpaint_ctx *ctx, int64_t *iterations, int64_t *remaining) {
+    if (!ctx) return INPAINT_INVALID_ARGUMENT;
+    if (ctx->sticky) return ctx->sticky;
+    HIP_OR_FAIL(ctx, ctx->pull_state(), "state");
+    if (iterations) *iterations = ctx->h_state->iter;
+    if (remaining) *remaining = ctx->h_state->remaining;
+    return INPAINT_OK;
+}
+
 int32_t inpaint_profile_search(inpaint_ctx *ctx, int32_t enable) {
     if (!ctx) return INPAINT_INVALID_ARGUMENT;
     ctx->prof = enable != 0;
@@ -709,8 +718,8 @@ struct inpaint_batch {
     std::vector<inpaint_ctx *> slots;
     JobDev *d_slots = nullptr;
     JobDev *h_slots = nullptr;      // pinned staging of the slot table
-    int64_t *d_active = nullptr;
-    int64_t *h_active = nullptr;    // pinned
+    int64_t *d_active = nullptr;    // [0] = active count, then capacity int32 slot states
+    int64_t *h_active = nullptr;    // pinned mirror of the same
     std::map<int, RadiusGroup> groups;
     bool dirty = true;
     hipGraphExec_t graph = nullptr;
@@ -881,9 +890,11 @@ int32_t inpaint_batch_create(const inpaint_batch_params *bp, void *hip_stream, i
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) b->cu_count = prop.multiProcessorCount;
     hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&b->d_slots, sizeof(JobDev) * bp->capacity);
-    if (e == hipSuccess) e = hipMalloc(&b->d_active, sizeof(int64_t));
+    const size_t status_bytes = sizeof(int64_t) + sizeof(int32_t) * (size_t)bp->capacity;
+    if (e == hipSuccess) e = hipMalloc(&b->d_active, status_bytes);
     if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_slots, sizeof(JobDev) * bp->capacity, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_active, sizeof(int64_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->h_active, status_bytes, hipHostMallocDefault);
+    if (e == hipSuccess) std::memset(b->h_active, 0, status_bytes);
     if (e == hipSuccess) {
         std::memset(b->h_slots, 0, sizeof(JobDev) * bp->capacity);
         e = hipMemcpyAsync(b->d_slots, b->h_slots, sizeof(JobDev) * bp->capacity, hipMemcpyHostToDevice, b->stream);
@@ -906,6 +917,7 @@ int32_t inpaint_batch_attach(inpaint_batch *b, inpaint_ctx *ctx, int32_t *slot) 
     if (ctx->set_limit(INT64_MAX) != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess)
         return ctx->hip_fail(hipErrorUnknown, "attach");
     b->slots[i] = ctx;
+    ((int32_t *)(b->h_active + 1))[i] = ctx->h_state->done ? INPAINT_SLOT_FINISHED : INPAINT_SLOT_RUNNING;
     ctx->batch = b;
     if (b->groups.find(ctx->d.r) == b->groups.end()) b->graph_sig.clear();
     b->groups[ctx->d.r];
@@ -970,11 +982,21 @@ int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active) {
         b->graph_n = G;
     }
     e = hipGraphLaunch(b->graph, b->stream);
-    if (e == hipSuccess) e = launch_count_active(b->d_slots, (int)b->slots.size(), b->d_active, b->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->h_active, b->d_active, sizeof(int64_t), hipMemcpyDeviceToHost, b->stream);
+    const int ns = (int)b->slots.size();
+    if (e == hipSuccess)
+        e = launch_count_active(b->d_slots, ns, b->d_active, (int32_t *)(b->d_active + 1), b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->h_active, b->d_active, sizeof(int64_t) + sizeof(int32_t) * ns, hipMemcpyDeviceToHost,
+                           b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return INPAINT_DEVICE;
     if (active) *active = *b->h_active;
+    return INPAINT_OK;
+}
+
+int32_t inpaint_batch_status(const inpaint_batch *b, int32_t slot, int32_t *status) {
+    if (!b || !status || slot < 0 || slot >= (int32_t)b->slots.size()) return INPAINT_INVALID_ARGUMENT;
+    *status = b->slots[slot] ? ((const int32_t *)(b->h_active + 1))[slot] : INPAINT_SLOT_EMPTY;
     return INPAINT_OK;
 }
 

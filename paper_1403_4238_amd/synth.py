@@ -113,20 +113,24 @@ def content_gradient_rects(W: int, H: int, rng: np.random.Generator, n_rects: in
 
 
 def _value_noise(W: int, H: int, spacing: int, rng: np.random.Generator) -> np.ndarray:
-    """Lattice value noise with smoothstep interpolation, values in [-1, 1]."""
+    """Lattice value noise with smoothstep interpolation, values in [-1, 1].
+
+    Interpolates along x once per lattice row, then between lattice rows;
+    every pixel sees the same arithmetic as a direct per-pixel evaluation.
+    """
     gw, gh = W // spacing + 2, H // spacing + 2
     lat = rng.uniform(-1.0, 1.0, size=(gh, gw))
-    y, x = np.mgrid[0:H, 0:W]
+    x = np.arange(W)
+    y = np.arange(H)
     fx = (x % spacing).astype(np.float64) / spacing
     fy = (y % spacing).astype(np.float64) / spacing
     ix, iy = x // spacing, y // spacing
     sx = fx * fx * (3.0 - 2.0 * fx)
     sy = fy * fy * (3.0 - 2.0 * fy)
-    v00, v10 = lat[iy, ix], lat[iy, ix + 1]
-    v01, v11 = lat[iy + 1, ix], lat[iy + 1, ix + 1]
-    top = v00 + (v10 - v00) * sx
-    bot = v01 + (v11 - v01) * sx
-    return top + (bot - top) * sy
+    a, b = lat[:, ix], lat[:, ix + 1]          # [gh, W]
+    rows = a + (b - a) * sx[None, :]           # x-interpolated lattice rows
+    top, bot = rows[iy], rows[iy + 1]          # [H, W]
+    return top + (bot - top) * sy[:, None]
 
 
 def content_noise_edges(W: int, H: int, rng: np.random.Generator, n_edges: int = 10) -> np.ndarray:
@@ -223,8 +227,8 @@ def mask_blobs(W: int, H: int, rng: np.random.Generator, area_frac: float, n_blo
             y0, y1 = cy - rad, cy + rad + 1
             yy, xx = np.mgrid[y0:y1, x0:x1]
             disc = (xx - cx) ** 2 + (yy - cy) ** 2 <= rad * rad
+            area += int((disc & ~m[y0:y1, x0:x1]).sum())
             m[y0:y1, x0:x1] |= disc
-            area = int(m.sum())
             while True:
                 dx, dy = (int(v) for v in rng.integers(-20, 21, size=2))
                 if 100 <= dx * dx + dy * dy <= 400:

@@ -1,0 +1,111 @@
+"""Host logic of the continuous-batching server, on a fake engine (CPU)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_1403_4238_amd.serve import FakeClock, FakeEngine, Server, summarize
+
+
+@dataclasses.dataclass
+class J:
+    name: str
+    arrival_s: float
+    iters: int
+    nbytes: int
+    bad: bool = False
+
+
+def _server(jobs, budget, capacity, G=1, step_cost=0.001, **kw):
+    clock = FakeClock()
+    eng = FakeEngine(lambda j: j.iters, lambda j: j.nbytes, clock=clock, step_cost_s=step_cost,
+                     fail_on=lambda j: j.bad)
+    srv = Server(eng, budget, capacity, G, clock=clock, sleep=clock.sleep, **kw)
+    return srv, eng, srv.run(jobs)
+
+
+def test_all_jobs_complete_with_exact_latency():
+    # One job at a time, 1 ms per step, G = 1: a job of n iterations that
+    # starts at once finishes n ms after it arrives.
+    jobs = [J("a", 0.0, 5, 10), J("b", 0.100, 3, 10)]
+    srv, eng, recs = _server(jobs, budget=100, capacity=4)
+    assert [r.status for r in recs] == ["done", "done"]
+    assert recs[0].latency_s == pytest.approx(0.005)
+    assert recs[1].latency_s == pytest.approx(0.003)
+    assert eng.released == 2
+
+
+def test_admission_by_memory_budget():
+    jobs = [J(f"j{i}", 0.0, 10, 40) for i in range(6)]
+    srv, eng, recs = _server(jobs, budget=100, capacity=8)
+    assert all(r.status == "done" for r in recs)
+    assert eng.max_live == 2            # 2 x 40 bytes fit in 100, a third does not
+    assert srv.peak_used <= 100
+
+
+def test_admission_by_slots():
+    jobs = [J(f"j{i}", 0.0, 4, 1) for i in range(7)]
+    srv, eng, recs = _server(jobs, budget=1 << 30, capacity=3)
+    assert eng.max_live == 3 and all(r.status == "done" for r in recs)
+
+
+def test_continuous_batching_admits_while_others_run():
+    # A long job is running; a short job arriving later is admitted next to it
+    # and finishes first.
+    jobs = [J("long", 0.0, 200, 10), J("short", 0.010, 5, 10)]
+    srv, eng, recs = _server(jobs, budget=100, capacity=2)
+    long, short = recs
+    assert short.admit_s < long.done_s
+    assert short.done_s < long.done_s
+    assert eng.max_live == 2
+
+
+def test_fifo_order_under_memory_pressure():
+    # A big job at the head of the queue is not overtaken by smaller ones.
+    jobs = [J("a", 0.0, 50, 60), J("big", 0.001, 5, 80), J("small", 0.002, 5, 10)]
+    srv, eng, recs = _server(jobs, budget=100, capacity=4)
+    a, big, small = recs
+    assert big.admit_s >= a.done_s - 1e-12
+    assert small.admit_s >= big.admit_s
+
+
+def test_rejects_jobs_larger_than_the_budget_and_isolates_failures():
+    jobs = [J("ok1", 0.0, 3, 10), J("huge", 0.0, 3, 1000), J("bad", 0.0, 3, 10, bad=True), J("ok2", 0.0, 3, 10)]
+    srv, eng, recs = _server(jobs, budget=100, capacity=4)
+    assert [r.status for r in recs] == ["done", "rejected", "failed", "done"]
+    s = summarize(recs)
+    assert s["completed"] == 2 and s["rejected"] == 1 and s["failed"] == 1
+    assert srv.used == 0
+
+
+def test_percentiles_and_throughput():
+    rng = np.random.default_rng(0)
+    t, jobs = 0.0, []
+    for i in range(200):
+        t += float(rng.exponential(0.01))
+        jobs.append(J(f"j{i}", t, int(rng.integers(1, 30)), int(rng.integers(1, 20))))
+    srv, eng, recs = _server(jobs, budget=60, capacity=8, G=2, step_cost=0.0005)
+    s = summarize(recs)
+    lat = np.array([r.latency_s for r in recs])
+    assert s["completed"] == 200
+    assert s["p50_latency_ms"] == pytest.approx(1000 * np.percentile(lat, 50), rel=1e-6, abs=1e-3)
+    assert s["p99_latency_ms"] == pytest.approx(1000 * np.percentile(lat, 99), rel=1e-6, abs=1e-3)
+    assert s["p99_latency_ms"] >= s["p50_latency_ms"] > 0
+    assert s["jobs_per_s"] == pytest.approx(200 / s["span_s"], rel=1e-3)
+    assert srv.peak_used <= 60 and eng.max_live <= 8
+    # every job needed exactly its scripted iterations
+    assert all(r.iterations == j.iters for r, j in zip(recs, jobs))
+
+
+def test_idle_gaps_are_waited_out():
+    jobs = [J("a", 0.0, 2, 1), J("b", 5.0, 2, 1)]
+    srv, eng, recs = _server(jobs, budget=10, capacity=2)
+    assert recs[1].admit_s >= 5.0
+    assert recs[1].latency_s == pytest.approx(0.002)
+
+
+def test_bad_configuration():
+    with pytest.raises(ValueError):
+        Server(FakeEngine(lambda j: 1, lambda j: 1), budget_bytes=0, capacity=1)
+    with pytest.raises(ValueError):
+        Server(FakeEngine(lambda j: 1, lambda j: 1), budget_bytes=10, capacity=0)

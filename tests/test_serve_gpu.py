@@ -1,0 +1,63 @@
+"""Serving on the GPU: jobs arriving while others run share batch steps, and
+each job's result is exactly its result alone (and the oracle's)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1403_4238_amd import synth
+
+from _util import assert_logs_equal
+
+pytestmark = pytest.mark.gpu
+
+B = pytest.importorskip("paper_1403_4238_amd.binding")
+serve = pytest.importorskip("paper_1403_4238_amd.serve")
+
+
+def _jobs(n=10, rate=400.0, seed=9):
+    rng = np.random.default_rng(seed)
+    t, jobs = 0.0, []
+    for i in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        W, H = int(rng.integers(40, 140)), int(rng.integers(40, 110))
+        r = int(rng.choice([3, 4, 5]))
+        rgb = rng.integers(0, 256, size=(H, W, 3)).astype(np.uint8)
+        mask = np.zeros((H, W), np.uint8)
+        y0, x0 = int(rng.integers(r + 2, H // 2)), int(rng.integers(r + 2, W // 2))
+        mask[y0:y0 + H // 5, x0:x0 + W // 6] = 1
+        jobs.append(synth.Job(f"s{i}-{W}x{H}-r{r}", rgb, mask, r, arrival_s=t))
+    return jobs
+
+
+@pytest.mark.parametrize("capacity,budget_jobs", [(4, 3), (16, 16)])
+def test_served_results_equal_alone_and_oracle(capacity, budget_jobs):
+    jobs = _jobs()
+    eng = serve.GpuEngine(capacity=capacity, graph_iters=6, autotune=False)
+    budget = budget_jobs * max(eng.footprint(j) for j in jobs)
+    srv = serve.Server(eng, budget, capacity, graph_iters=6)
+    recs = srv.run(jobs)
+    assert all(r.status == "done" for r in recs), [(r.name, r.status, r.error) for r in recs]
+    assert srv.peak_active <= capacity and srv.peak_used <= budget
+    s = serve.summarize(recs)
+    assert s["completed"] == len(jobs) and s["p99_latency_ms"] >= s["p50_latency_ms"]
+    for j, r in zip(jobs, recs):
+        o = oracle.Oracle(j.rgb, j.mask, j.patch_radius)
+        want = o.run()
+        assert_logs_equal(r.result["log"], want, j.name)
+        assert (r.result["image"] == o.read()[0]).all(), j.name
+        alone = B.Inpainter(j.rgb, j.mask, j.patch_radius)
+        _, n, log = alone.run(log_cap=len(want))
+        assert_logs_equal(log, r.result["log"], j.name + " alone")
+    if capacity == 4:
+        assert srv.peak_active >= 2      # jobs did overlap on the device
+
+
+def test_invalid_job_is_isolated():
+    jobs = _jobs(4)
+    bad = synth.Job("bad", jobs[0].rgb, np.zeros_like(jobs[0].mask), 3, arrival_s=jobs[1].arrival_s)
+    jobs.insert(2, bad)
+    eng = serve.GpuEngine(capacity=4, graph_iters=4, autotune=False)
+    srv = serve.Server(eng, 1 << 32, 4, graph_iters=4)
+    recs = srv.run(jobs)
+    assert [r.status for r in recs].count("failed") == 1 and recs[2].status == "failed"
+    assert all(r.status == "done" for k, r in enumerate(recs) if k != 2)
