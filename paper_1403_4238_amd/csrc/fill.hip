@@ -3,7 +3,7 @@
 //
 // Everything here except the exemplar search (search.hip) is latency-bound
 // work on at most a few thousand pixels per iteration, so the per-iteration
-// part runs as ONE work-group of 1024 threads per image ("commit" kernel):
+// part runs as ONE work-group of 256 threads per image ("commit" kernel):
 //   reduce the search partials -> copy the source patch -> stage the
 //   neighbourhood of the patch in LDS -> refresh the priorities there ->
 //   refresh the affected block maxima -> argmax -> stage the next target.
@@ -46,6 +46,8 @@ struct GlobalView {
         return (!in_img(d, x, y) || d.hole[(int64_t)y * d.W + x]) ? 1 : 0;
     }
     __device__ double conf(int x, int y) const { return d.conf[(int64_t)y * d.W + x]; }
+    // C of a known pixel, +0.0 for any other
+    __device__ double conf_known(int x, int y) const { return known(x, y) ? conf(x, y) : 0.0; }
     // Central-difference gradient of the gray image at a known pixel whose
     // four neighbours are known: returns gx^2 + gy^2, or -1 otherwise.
     __device__ int grad(int x, int y, int *gx, int *gy) const {
@@ -63,11 +65,18 @@ struct GlobalView {
 // the image; confidences; gradients precomputed per pixel.
 template <int R>
 struct LdsStage {
+    static constexpr int WIN = 4 * R + 3;          // refresh window side
+    static constexpr int NBA = (WIN + 6) / 8 + 1;  // 8x8 blocks it can touch per axis
     uint8_t st[Stage<R>::n];
     uint8_t gray[Stage<R>::n];
     double conf[Stage<R>::n];
+    uint32_t img[Stage<R>::n];
     int mag[Stage<R>::n];
     int gxy[Stage<R>::n];   // gx in the low 16 bits, gy in the high 16 (signed)
+    int64_t bkey[NBA * NBA * 64];   // priority keys of the blocks the window touches
+    double2 wcd[WIN * WIN];         // (C, D) of the window pixels
+    int16_t front[WIN * WIN];       // window pixels on the front (window-local index)
+    int nfront;
 };
 
 template <int R>
@@ -79,6 +88,15 @@ struct LdsView {
     __device__ bool known(int x, int y) const { return s.st[at(x, y)] == 0; }
     __device__ int hole_or_out(int x, int y) const { return s.st[at(x, y)] != 0 ? 1 : 0; }
     __device__ double conf(int x, int y) const { return s.conf[at(x, y)]; }
+    // C of a known pixel, +0.0 for any other.  Both LDS reads are
+    // unconditional (every staged address is valid) and the value is masked
+    // with integer operations, so no branch (and no serialised LDS round
+    // trip) is generated per offset.
+    __device__ double conf_known(int x, int y) const {
+        const int i = at(x, y);
+        const uint64_t mask = s.st[i] == 0 ? ~0ull : 0ull;
+        return __longlong_as_double((long long)((uint64_t)__double_as_longlong(s.conf[i]) & mask));
+    }
     __device__ int grad(int x, int y, int *gx, int *gy) const {
         const int i = at(x, y);
         const int v = s.gxy[i];
@@ -90,10 +108,18 @@ struct LdsView {
 
 // Fill front: a hole pixel with at least one in-image 4-neighbour known.
 // (x, y) is always inside the image here.
-template <class V>
-__device__ __forceinline__ bool on_front(const V &v, int x, int y) {
+__device__ __forceinline__ bool on_front(const GlobalView &v, int x, int y) {
     if (v.hole_or_out(x, y) == 0) return false;
     return v.known(x + 1, y) || v.known(x - 1, y) || v.known(x, y + 1) || v.known(x, y - 1);
+}
+
+// The same test on the LDS copy, with all five reads unconditional.
+template <int R>
+__device__ __forceinline__ bool on_front(const LdsView<R> &v, int x, int y) {
+    const int i = v.at(x, y);
+    const uint8_t *st = v.s.st;
+    const int c = st[i], e = st[i + 1], w = st[i - 1], n = st[i - LdsView<R>::side], so = st[i + LdsView<R>::side];
+    return c == 1 && (e == 0 || w == 0 || n == 0 || so == 0);
 }
 
 // Eq. 2.  Confidence: sum of C over the known pixels of the patch, in raster
@@ -108,19 +134,18 @@ __device__ __forceinline__ bool on_front(const V &v, int x, int y) {
 template <int R, class V>
 __device__ void priority_terms(const V &v, int px, int py, double norm1, double norm2, double *C, double *D) {
     constexpr int P = 2 * R + 1;
+    // Unrolled a few rows at a time: enough independent LDS reads in flight
+    // without running out of registers (a fully unrolled 9x9 spills).
+    constexpr int kRows = R <= 2 ? P : (R <= 4 ? 3 : 1);
     double sum = 0.0;
-#pragma unroll
+#pragma unroll kRows
     for (int dy = -R; dy <= R; ++dy)
 #pragma unroll
-        for (int dx = -R; dx <= R; ++dx) {
-            const bool k = v.known(px + dx, py + dy);
-            const double c = k ? v.conf(px + dx, py + dy) : 0.0;
-            sum = sum + c;
-        }
+        for (int dx = -R; dx <= R; ++dx) sum = sum + v.conf_known(px + dx, py + dy);
     *C = sum / (double)(P * P);
 
     int gx = 0, gy = 0, best = -1;
-#pragma unroll
+#pragma unroll kRows
     for (int dy = -R; dy <= R; ++dy)
 #pragma unroll
         for (int dx = -R; dx <= R; ++dx) {
@@ -339,35 +364,41 @@ __device__ void select_and_stage(const JobDev &d, Scratch &s) {
     }
 }
 
-// Stages the neighbourhood of (px, py) into LDS (status, gray, confidence).
+// Geometry of one refresh: the window of pixels whose priority can change
+// (within 2r+1 of the filled target, clipped to the image) and the 8x8
+// blocks it touches.
+struct Refresh {
+    int wx0, wx1, wy0, wy1;   // window
+    int abx0, aby0, nabx, naby;
+};
+
 template <int R>
-__device__ void stage_neighbourhood(const JobDev &d, int px, int py, LdsStage<R> &L) {
-    using S = Stage<R>;
-    const int ox = px - S::half, oy = py - S::half;
-    for (int t = threadIdx.x; t < S::n; t += blockDim.x) {
-        const int x = ox + t % S::side, y = oy + t / S::side;
-        uint8_t stv = 2;
-        if (in_img(d, x, y)) {
-            const int64_t i = (int64_t)y * d.W + x;
-            stv = d.hole[i] ? 1 : 0;
-            L.gray[t] = d.gray[i];
-            L.conf[t] = d.conf[i];
-        }
-        L.st[t] = stv;
-    }
+__device__ Refresh refresh_geometry(const JobDev &d, int px, int py) {
+    constexpr int reach = 2 * R + 1;
+    Refresh g;
+    g.wx0 = max(px - reach, 0);
+    g.wx1 = min(px + reach + 1, d.W);
+    g.wy0 = max(py - reach, 0);
+    g.wy1 = min(py + reach + 1, d.H);
+    g.abx0 = g.wx0 / kBlock;
+    g.aby0 = g.wy0 / kBlock;
+    g.nabx = (g.wx1 - 1) / kBlock - g.abx0 + 1;
+    g.naby = (g.wy1 - 1) / kBlock - g.aby0 + 1;
+    return g;
 }
 
-// Re-evaluates the priorities within 2r+1 (Chebyshev) of the filled target
-// (px, py): that is where the hole, the confidences and the gray values read
-// by a priority evaluation changed.  Expects the neighbourhood (already
-// updated by the copy) in LDS.  Gradients are computed once per pixel, then
-// each front pixel of the window evaluates its terms from LDS, and one wave
-// per 8x8 block refreshes the affected block maxima.
+// Re-evaluates the priorities of the refresh window from the LDS copy of the
+// neighbourhood (already updated by the copy): gradients once per pixel, then
+// each front pixel's (C, D).  New terms go to global memory (for later
+// iterations) and to LDS; then one wave per touched block recomputes its
+// maximum, writes it, and folds it into the thread's running argmax.
 template <int R>
-__device__ void refresh_near(const JobDev &d, int px, int py, LdsStage<R> &L) {
+__device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, LdsStage<R> &L, int64_t &key,
+                             int64_t &idx) {
     using S = Stage<R>;
     const int ox = px - S::half, oy = py - S::half;
     const LdsView<R> v{L, ox, oy};
+    if (threadIdx.x == 0) L.nfront = 0;
     // gradients on the inner (side - 2)^2 square
     constexpr int gs = S::side - 2, gn = gs * gs;
     for (int t = threadIdx.x; t < gn; t += blockDim.x) {
@@ -384,19 +415,91 @@ __device__ void refresh_near(const JobDev &d, int px, int py, LdsStage<R> &L) {
         L.gxy[i] = gxy;
     }
     __syncthreads();
-    constexpr int reach = 2 * R + 1;
-    const int wx0 = max(px - reach, 0), wx1 = min(px + reach + 1, d.W);
-    const int wy0 = max(py - reach, 0), wy1 = min(py + reach + 1, d.H);
-    const int ww = wx1 - wx0, nwin = ww * (wy1 - wy0);
+    // Window pixels off the front get (C, D) = (-1, 0) at once; front pixels
+    // go to a compact list so the costly evaluations fill whole waves.
+    const int ww = g.wx1 - g.wx0, nwin = ww * (g.wy1 - g.wy0);
+    constexpr int WIN = LdsStage<R>::WIN;
     for (int t = threadIdx.x; t < nwin; t += blockDim.x) {
-        const int x = wx0 + t % ww, y = wy0 + t / ww;
-        d.pcd[(int64_t)y * d.W + x] = pixel_terms<R>(v, d, x, y);
+        const int x = g.wx0 + t % ww, y = g.wy0 + t / ww;
+        const int wi = (y - (py - 2 * R - 1)) * WIN + (x - (px - 2 * R - 1));
+        if (on_front(v, x, y)) {
+            L.front[atomicAdd(&L.nfront, 1)] = (int16_t)wi;
+        } else {
+            const double2 cd = make_double2(-1.0, 0.0);
+            d.pcd[(int64_t)y * d.W + x] = cd;
+            L.wcd[wi] = cd;
+            const int b = (y / kBlock - g.aby0) * g.nabx + (x / kBlock - g.abx0);
+            L.bkey[b * 64 + (y & 7) * 8 + (x & 7)] = -1;
+        }
     }
     __syncthreads();
-    const int bx0 = wx0 / kBlock, by0 = wy0 / kBlock;
-    const int nbx = (wx1 - 1) / kBlock - bx0 + 1, nb = nbx * ((wy1 - 1) / kBlock - by0 + 1);
-    for (int b = threadIdx.x >> 6; b < nb; b += blockDim.x >> 6) refresh_block_wave(d, bx0 + b % nbx, by0 + b / nbx);
+    const int nfront = L.nfront;
+    for (int f = threadIdx.x; f < nfront; f += blockDim.x) {
+        const int wi = L.front[f];
+        const int x = px - 2 * R - 1 + wi % WIN, y = py - 2 * R - 1 + wi / WIN;
+        double2 cd;
+        priority_terms<R>(v, x, y, d.norm1, d.norm2, &cd.x, &cd.y);
+        d.pcd[(int64_t)y * d.W + x] = cd;
+        L.wcd[wi] = cd;
+        const int b = (y / kBlock - g.aby0) * g.nabx + (x / kBlock - g.abx0);
+        L.bkey[b * 64 + (y & 7) * 8 + (x & 7)] = key_of(cd);
+    }
     __syncthreads();
+    const int lane = threadIdx.x & 63, nb = g.nabx * g.naby;
+    for (int b = threadIdx.x >> 6; b < nb; b += blockDim.x >> 6) {
+        const int bx = g.abx0 + b % g.nabx, by = g.aby0 + b / g.nabx;
+        const int x = bx * kBlock + (lane & 7), y = by * kBlock + (lane >> 3);
+        int64_t bk = L.bkey[b * 64 + lane], bi = (int64_t)y * d.W + x;
+        if (!in_img(d, x, y)) {
+            bk = -1;
+            bi = INT64_MAX;
+        }
+        wave_argmax(bk, bi);
+        if (lane == 0) {
+            d.blk[by * d.nbw + bx].key = bk;
+            d.blk[by * d.nbw + bx].idx = bi;
+            if (better(bk, bi, key, idx)) {
+                key = bk;
+                idx = bi;
+            }
+        }
+    }
+}
+
+// Stages the next target (nx, ny) from the LDS neighbourhood of the filled
+// target (px, py); valid when the whole patch lies inside it.
+template <int R>
+__device__ __forceinline__ void stage_target_lds(const LdsStage<R> &L, int px, int py, int tx, int ty, TargetStage *tg, Scratch &s) {
+    using S = Stage<R>;
+    constexpr int P = 2 * R + 1;
+    if (threadIdx.x < 16) s.mbits[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t kk = 0, t2 = 0;
+    for (int t = threadIdx.x; t < kMaxOffsets + 15; t += blockDim.x) {
+        uint32_t pix = 0;
+        if (t < P * P) {
+            const int dx = t / P - R, dy = t % P - R;
+            const int i = (ty + dy - py + S::half) * S::side + (tx + dx - px + S::half);
+            if (L.st[i] == 0) {
+                pix = L.img[i] & 0x00ffffffu;
+                const int Rr = pix & 255, G = (pix >> 8) & 255, B = (pix >> 16) & 255;
+                kk += 1;
+                t2 += Rr * Rr + G * G + B * B;
+                atomicOr(&s.mbits[t >> 5], 1u << (t & 31));
+            }
+        }
+        tg->tpix[t] = pix;
+    }
+    kk = block_sum_i64(kk, s.k);
+    t2 = block_sum_i64(t2, s.k);
+    if (threadIdx.x < 16) tg->mbits[threadIdx.x] = s.mbits[threadIdx.x];
+    if (threadIdx.x == 0) {
+        tg->tx = tx;
+        tg->ty = ty;
+        tg->r = R;
+        tg->k = (int32_t)kk;
+        tg->t2 = (uint32_t)t2;
+    }
 }
 
 }  // namespace
@@ -525,12 +628,115 @@ __global__ __launch_bounds__(256) void k_prio_init(JobDev d) {
     refresh_block_wave(d, bx, by);   // same wave: its own writes are visible
 }
 
+// Issues every global load the commit needs that does not depend on the
+// search result -- the target's neighbourhood, the cached keys of the touched
+// blocks, the block maxima of the priority range and the search partials --
+// before consuming any of them, so together they cost about one memory round
+// trip.  Leaves the neighbourhood and the block keys in LDS, the running
+// argmax over the untouched blocks in (key, idx), and returns the minimum
+// search key of this thread's partials.
+template <int R>
+__device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, LdsStage<R> &L, int64_t &key,
+                           int64_t &idx) {
+    using S = Stage<R>;
+    constexpr int T = kCommitThreads;
+    constexpr int NIT = (S::n + T - 1) / T;
+    constexpr int KIT = (LdsStage<R>::NBA * LdsStage<R>::NBA * 64 + T - 1) / T;
+    constexpr int BIT = 16, PIT = 8;
+    const int ox = px - S::half, oy = py - S::half;
+    const int nkeys = g.nabx * g.naby * 64;
+    const int bw = d.pbx1 - d.pbx0, nb = bw * (d.pby1 - d.pby0);
+    const int ntiles = d.ntx * d.nty;
+    const int tid = threadIdx.x;
+
+    uint8_t h[NIT], gv[NIT];
+    double c[NIT];
+    uint32_t im[NIT];
+    double2 cd[KIT];
+    BlockBest bb[BIT];
+    uint64_t pv[PIT];
+    // ---- issue (all unconditional, from clamped addresses)
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+        const int t = min(tid + k * T, S::n - 1);
+        const int x = min(max(ox + t % S::side, 0), d.W - 1), y = min(max(oy + t / S::side, 0), d.H - 1);
+        const int64_t i = (int64_t)y * d.W + x;
+        h[k] = d.hole[i];
+        gv[k] = d.gray[i];
+        c[k] = d.conf[i];
+        im[k] = d.img[i];
+    }
+#pragma unroll
+    for (int k = 0; k < KIT; ++k) {
+        const int t = min(tid + k * T, nkeys - 1);
+        const int b = t >> 6, lane = t & 63;
+        const int x = min((g.abx0 + b % g.nabx) * kBlock + (lane & 7), d.W - 1);
+        const int y = min((g.aby0 + b / g.nabx) * kBlock + (lane >> 3), d.H - 1);
+        cd[k] = d.pcd[(int64_t)y * d.W + x];
+    }
+#pragma unroll
+    for (int k = 0; k < BIT; ++k) {
+        const int t = min(tid + k * T, nb - 1);
+        bb[k] = d.blk[(d.pby0 + t / bw) * d.nbw + d.pbx0 + t % bw];
+    }
+#pragma unroll
+    for (int k = 0; k < PIT; ++k) pv[k] = d.partials[min(tid + k * T, ntiles - 1)];
+
+    // ---- consume
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+        const int t = tid + k * T;
+        if (t < S::n) {
+            const int x = ox + t % S::side, y = oy + t / S::side;
+            const bool in = in_img(d, x, y);
+            L.st[t] = !in ? 2 : (h[k] ? 1 : 0);
+            L.gray[t] = gv[k];
+            L.conf[t] = c[k];
+            L.img[t] = im[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KIT; ++k) {
+        const int t = tid + k * T;
+        if (t < nkeys) {
+            const int b = t >> 6, lane = t & 63;
+            const int x = (g.abx0 + b % g.nabx) * kBlock + (lane & 7), y = (g.aby0 + b / g.nabx) * kBlock + (lane >> 3);
+            L.bkey[t] = in_img(d, x, y) ? key_of(cd[k]) : -1;
+        }
+    }
+    auto take_block = [&](int t, const BlockBest &b) {
+        const int bx = d.pbx0 + t % bw, by = d.pby0 + t / bw;
+        const bool touched = bx >= g.abx0 && bx < g.abx0 + g.nabx && by >= g.aby0 && by < g.aby0 + g.naby;
+        if (t < nb && !touched && better(b.key, b.idx, key, idx)) {
+            key = b.key;
+            idx = b.idx;
+        }
+    };
+#pragma unroll
+    for (int k = 0; k < BIT; ++k) take_block(tid + k * T, bb[k]);
+    uint64_t best = ~0ull;
+#pragma unroll
+    for (int k = 0; k < PIT; ++k) best = pv[k] < best ? pv[k] : best;   // clamped repeats are harmless
+
+    // ---- tails of very large holes / rectangles
+    for (int t = tid + BIT * T; t < nb; t += T) take_block(t, d.blk[(d.pby0 + t / bw) * d.nbw + d.pbx0 + t % bw]);
+    for (int t = tid + PIT * T; t < ntiles; t += T) best = d.partials[t] < best ? d.partials[t] : best;
+    return best;
+}
+
 // One fill iteration after the search: reduce the search partials, copy the
 // source patch into the target's hole pixels (they take the target's
 // confidence), log, refresh priorities near the patch, select and stage the
-// next target.  With no staged target it only selects and stages.  The
-// target's neighbourhood is staged in LDS while the partials are reduced, and
-// the copy updates both global memory and that LDS copy.
+// next target.  With no staged target (right after create) it only selects
+// and stages.
+//
+// Latency is the cost here, so every global load that does not depend on
+// the search result is issued at once up front: the search partials, the
+// target's neighbourhood (into LDS), the cached keys of the 8x8 blocks the
+// refresh touches, and the argmax over all other blocks.  After the copy the
+// rest runs out of LDS; the next target is staged from LDS when its patch
+// lies inside the staged neighbourhood (the common case: the front moves
+// locally).
 template <int R>
 __device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L) {
     IterState *st = d.st;
@@ -538,71 +744,101 @@ __device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L) {
     const int64_t iter = st->iter, limit = st->iter_limit, rem0 = st->remaining, p = st->p_idx;
     const double C = st->C, D = st->D, Pr = st->Pr;
     if (done || err) return;
-    if (pending) {
-        if (iter >= limit) return;
-        constexpr int P = 2 * R + 1;
-        const int W = d.W;
-        const int px = (int)(p % W), py = (int)(p / W);
-        const int known_k = d.tgt->k;
-        stage_neighbourhood<R>(d, px, py, L);
-        const int ntiles = d.ntx * d.nty;
-        uint64_t best = ~0ull;
-        for (int t = threadIdx.x; t < ntiles; t += blockDim.x) {
-            const uint64_t v = d.partials[t];
-            best = v < best ? v : best;
-        }
-        best = block_min_u64(best, s.u);   // also orders the LDS staging
-        if (best == ~0ull) {
-            if (threadIdx.x == 0) st->error = INPAINT_NO_CANDIDATE;
-            return;
-        }
-        const int64_t q = (int64_t)(best & 0xffffffffu);
-        const uint32_t ssd = (uint32_t)(best >> 32);
-        const int qx = (int)(q % W), qy = (int)(q / W);
-        int64_t filled = 0;
-        if (threadIdx.x < P * P) {
-            const int dx = (int)threadIdx.x % P - R, dy = (int)threadIdx.x / P - R;
-            const int x = px + dx, y = py + dy;
-            const int li = (dy + Stage<R>::half) * Stage<R>::side + (dx + Stage<R>::half);
-            if (L.st[li] == 1) {
-                const int64_t dst = (int64_t)y * W + x, src = (int64_t)(qy + dy) * W + (qx + dx);
-                const uint32_t pix = d.img[src];
-                const uint8_t g = d.gray[src];
-                d.img[dst] = pix;
-                d.gray[dst] = g;
-                d.conf[dst] = C;
-                d.hole[dst] = 0;
-                L.st[li] = 0;
-                L.gray[li] = g;
-                L.conf[li] = C;
-                filled = 1;
-            }
-        }
-        filled = block_sum_i64(filled, s.k);
-        const int64_t remaining = rem0 - filled;
-        if (threadIdx.x == 0) {
-            StepRec rec;
-            rec.target_index = p;
-            rec.source_index = q;
-            rec.ssd = ssd;
-            rec.known_k = known_k;
-            rec.n_filled = (int32_t)filled;
-            rec.reserved = 0;
-            rec.priority = Pr;
-            rec.confidence = C;
-            rec.data_term = D;
-            rec.remaining = remaining;
-            if (iter < d.log_cap) d.log[iter] = rec;
-            st->last = rec;
-            st->remaining = remaining;
-            st->iter = iter + 1;
-            st->pending = 0;
-            if (remaining == 0) st->done = 1;
-        }
-        if (remaining == 0) return;
-        refresh_near<R>(d, px, py, L);
+    if (!pending) {
+        select_and_stage(d, s);
+        return;
     }
-    select_and_stage(d, s);
+    if (iter >= limit) return;
+    constexpr int P = 2 * R + 1;
+    const int W = d.W;
+    const int px = (int)(p % W), py = (int)(p / W);
+    const int known_k = d.tgt->k;
+    const Refresh g = refresh_geometry<R>(d, px, py);
+
+    // ---- independent loads
+    int64_t key = -1, idx = INT64_MAX;
+    uint64_t best = gather<R>(d, px, py, g, L, key, idx);
+    best = block_min_u64(best, s.u);   // its barriers also publish the LDS stores
+    if (best == ~0ull) {
+        if (threadIdx.x == 0) st->error = INPAINT_NO_CANDIDATE;
+        return;
+    }
+
+    // ---- copy the source patch
+    const int64_t q = (int64_t)(best & 0xffffffffu);
+    const uint32_t ssd = (uint32_t)(best >> 32);
+    const int qx = (int)(q % W), qy = (int)(q / W);
+    int64_t filled = 0;
+    for (int t = threadIdx.x; t < P * P; t += blockDim.x) {
+        const int dx = t % P - R, dy = t / P - R;
+        const int li = (dy + Stage<R>::half) * Stage<R>::side + (dx + Stage<R>::half);
+        if (L.st[li] == 1) {
+            const int64_t dst = (int64_t)(py + dy) * W + (px + dx), src = (int64_t)(qy + dy) * W + (qx + dx);
+            const uint32_t pix = d.img[src];
+            const uint8_t gv = d.gray[src];
+            d.img[dst] = pix;
+            d.gray[dst] = gv;
+            d.conf[dst] = C;
+            d.hole[dst] = 0;
+            L.st[li] = 0;
+            L.img[li] = pix;
+            L.gray[li] = gv;
+            L.conf[li] = C;
+            filled += 1;
+        }
+    }
+    filled = block_sum_i64(filled, s.k);
+    const int64_t remaining = rem0 - filled;
+    if (threadIdx.x == 0) {
+        StepRec rec;
+        rec.target_index = p;
+        rec.source_index = q;
+        rec.ssd = ssd;
+        rec.known_k = known_k;
+        rec.n_filled = (int32_t)filled;
+        rec.reserved = 0;
+        rec.priority = Pr;
+        rec.confidence = C;
+        rec.data_term = D;
+        rec.remaining = remaining;
+        if (iter < d.log_cap) d.log[iter] = rec;
+        st->last = rec;
+        st->remaining = remaining;
+        st->iter = iter + 1;
+        st->pending = 0;
+        if (remaining == 0) st->done = 1;
+    }
+    if (remaining == 0) return;
+
+    // ---- priorities near the patch, block maxima, argmax
+    refresh_near<R>(d, px, py, g, L, key, idx);
+    block_argmax(key, idx, s.k, s.i);
+    if (key < 0) {
+        // No front pixel although the hole is not empty: cannot happen for a
+        // valid state; flag it instead of looping.
+        if (threadIdx.x == 0) st->error = INPAINT_DEVICE;
+        return;
+    }
+
+    // ---- stage the next target
+    const int tx = (int)(idx % W), ty = (int)(idx / W);
+    const int adx = abs(tx - px), ady = abs(ty - py);
+    if (adx <= 2 * R + 2 && ady <= 2 * R + 2)
+        stage_target_lds<R>(L, px, py, tx, ty, d.tgt, s);
+    else
+        stage_target(d, tx, ty, R, d.tgt, s);
+    if (threadIdx.x == 0) {
+        double2 cd;
+        if (adx <= 2 * R + 1 && ady <= 2 * R + 1)
+            cd = L.wcd[(ty - (py - 2 * R - 1)) * LdsStage<R>::WIN + (tx - (px - 2 * R - 1))];
+        else
+            cd = d.pcd[idx];
+        st->p_idx = idx;
+        st->C = cd.x;
+        st->D = cd.y;
+        st->Pr = cd.x * cd.y;
+        st->pending = 1;
+    }
 }
 
 template <int R>

@@ -16,7 +16,7 @@ constexpr int kMaskWords = (kMaxOffsets + 31) / 32;    // 10
 constexpr int kBlock = 8;                              // priority block side (one wave)
 constexpr int kTileW = 64;                             // search tile width (one wave)
 constexpr int kSearchWaves = 4;                        // waves per search work-group
-constexpr int kCommitThreads = 1024;
+constexpr int kCommitThreads = 256;   // one work-group per image; 512 VGPRs per thread
 
 // Target patch as the search kernels read it.  Offset o = (dx, dy) has slot
 // (dx + r) * P + (dy + r) (column-major, so one column's P values are

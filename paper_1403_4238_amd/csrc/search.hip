@@ -65,6 +65,10 @@ __device__ __forceinline__ void search_tile(const JobDev &d, const TargetStage *
     const int x = tx0 + lane;
     const int yb = ty0 + wave * NY;
 
+    // Validity of this thread's candidates and the tile staging (the tile
+    // plus its halo: rows ty0-R .., columns tx0-R ..) are loaded together;
+    // one barrier then publishes the LDS tile and tells whether any
+    // candidate of the tile is valid.
     uint32_t vmask = 0;
     if (x < rx1) {
 #pragma unroll
@@ -73,12 +77,6 @@ __device__ __forceinline__ void search_tile(const JobDev &d, const TargetStage *
             if (y < ry1 && d.vrad[(int64_t)y * W + x] >= R) vmask |= 1u << i;
         }
     }
-    if (!__syncthreads_or(vmask != 0)) {
-        if (tid == 0) out[tile] = ~0ull;
-        return;
-    }
-
-    // Stage the tile and its halo (rows ty0-R .., columns tx0-R ..).
     for (int i = tid; i < G::LDS_WORDS; i += kSearchWaves * 64) {
         const int ly = i / G::LW, lx = i - ly * G::LW;
         const int gx = tx0 - R + lx, gy = ty0 - R + ly;
@@ -86,7 +84,10 @@ __device__ __forceinline__ void search_tile(const JobDev &d, const TargetStage *
         if ((unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H) v = d.img[(int64_t)gy * W + gx];
         lds[i] = v;
     }
-    __syncthreads();
+    if (!__syncthreads_or(vmask != 0)) {
+        if (tid == 0) out[tile] = ~0ull;
+        return;
+    }
 
     uint32_t A[NY], B[NY];
 #pragma unroll
