@@ -53,6 +53,7 @@ def parse():
                     help="timed form (search-kernel events need a non-graph form)")
     ap.add_argument("--iters-per-check", type=int, default=32)
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--path", default="simt", choices=["simt", "mfma"], help="exemplar-search kernel")
     ap.add_argument("--no-other-form", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -68,12 +69,13 @@ def make_job(a):
     return synth.small()
 
 
-def timed_removals(job, n_steps, n_warmup, form, iters_per_check, tile_rows, timing=True):
+def timed_removals(job, n_steps, n_warmup, form, iters_per_check, tile_rows, timing=True, path="simt"):
     """Runs n_warmup + n_steps removals; times the last n_steps together."""
     import torch
     from paper_1403_4238_amd import binding as B
     ctxs = [B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, rect=job.rect,
-                        form=form, iters_per_check=iters_per_check, tile_rows=tile_rows)
+                        form=form, iters_per_check=iters_per_check, tile_rows=tile_rows,
+                        path=B.PATH_MFMA if path == "mfma" else B.PATH_SIMT)
             for _ in range(n_warmup + n_steps)]
     for c in ctxs[:n_warmup]:
         c.run()
@@ -297,7 +299,7 @@ def main():
     if a.workload == "serve":
         return serve_bench(a)
     job = make_job(a)
-    res = timed_removals(job, a.steps, a.warmup, a.form, a.iters_per_check, a.tile_rows)
+    res = timed_removals(job, a.steps, a.warmup, a.form, a.iters_per_check, a.tile_rows, path=a.path)
     n_steps = a.steps
     evals = sum(res["iters"]) * res["candidates"]
     value = evals / res["seconds"]
@@ -321,7 +323,7 @@ def main():
         for form in ("plain", "graph"):
             if form == a.form:
                 continue
-            o = timed_removals(job, 1, 0, form, a.iters_per_check, a.tile_rows, timing=False)
+            o = timed_removals(job, 1, 0, form, a.iters_per_check, a.tile_rows, timing=False, path=a.path)
             others[form] = {"ms_per_removal": round(1000 * o["seconds"], 2),
                             "patch_evals_per_s": round(sum(o["iters"]) * o["candidates"] / o["seconds"], 1)}
 

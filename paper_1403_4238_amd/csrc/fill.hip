@@ -268,7 +268,69 @@ struct Scratch {
     int64_t i[16];
     uint64_t u[16];
     uint32_t mbits[16];
+    uint32_t tp[kMaxOffsets + 15];   // the staged target words (column-major slots)
 };
+
+// Writes the int8-MFMA B operands of the target just staged in s.tp /
+// s.mbits (see MfmaFrags), plus T2' = sum of |t - 128|^2, k and the row mask.
+__device__ void build_mfma_frags(int r, Scratch &s, MfmaFrags *f) {
+    const int P = 2 * r + 1;
+    auto known = [&](int slot) { return (s.mbits[slot >> 5] >> (slot & 31)) & 1u; };
+    const int nvec = 4 * P * 64;   // c: 2P x 64, l: P x 64, h: P x 64
+    for (int v = threadIdx.x; v < nvec; v += blockDim.x) {
+        const int lane = v & 63, q = v >> 6, n = lane & 15, g = lane >> 4;
+        int32_t w[4];
+        if (q < 2 * P) {                       // cross term, (dy, h) = (q / 2, q % 2)
+            const int dy = q >> 1, hh = q & 1;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int dxr = 16 * hh + 4 * g + j - n;
+                const int slot = dxr * P + dy;
+                w[j] = (dxr >= 0 && dxr < P && known(slot)) ? (int32_t)(s.tp[slot] ^ 0x00808080u) : 0;
+            }
+            int32_t *dst = f->c[dy][hh][lane];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dst[j] = w[j];
+        } else {                               // square-term selectors, low (l) or high (h) byte
+            const int qq = q - 2 * P, dy = qq % P, high = qq / P;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                uint32_t m = 0;
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int dxr = 8 * g + 2 * j + b - n;
+                    if (dxr >= 0 && dxr < P && known(dxr * P + dy)) m |= 1u << (16 * b + 8 * high);
+                }
+                w[j] = (int32_t)m;
+            }
+            int32_t *dst = high ? f->h[dy][lane] : f->l[dy][lane];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dst[j] = w[j];
+        }
+    }
+    if (threadIdx.x < 64) {
+        int t2 = 0, kk = 0;
+        uint32_t rows = 0;
+        for (int sl = threadIdx.x; sl < P * P; sl += 64)
+            if (known(sl)) {
+                const uint32_t w = s.tp[sl];
+                const int a = (int)(w & 255) - 128, b = (int)((w >> 8) & 255) - 128, c = (int)((w >> 16) & 255) - 128;
+                t2 += a * a + b * b + c * c;
+                kk += 1;
+                rows |= 1u << (sl % P);
+            }
+        for (int off = 32; off > 0; off >>= 1) {
+            t2 += __shfl_xor(t2, off);
+            kk += __shfl_xor(kk, off);
+            rows |= __shfl_xor(rows, off);
+        }
+        if (threadIdx.x == 0) {
+            f->t2p = t2;
+            f->k = kk;
+            f->rowmask = rows;
+        }
+    }
+}
 
 __device__ __forceinline__ void wave_argmax(int64_t &key, int64_t &idx) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -300,7 +362,8 @@ __device__ void refresh_block_wave(const JobDev &d, int bx, int by) {
 // Stages the target patch at (tx, ty) with radius r into *tg: known mask,
 // RGBX words and T2 = sum of squared known target values, in column-major
 // slot order (dx + r) * P + (dy + r).
-__device__ void stage_target(const JobDev &d, int tx, int ty, int r, TargetStage *tg, Scratch &s) {
+__device__ void stage_target(const JobDev &d, int tx, int ty, int r, TargetStage *tg, Scratch &s,
+                             MfmaFrags *frag) {
     const int P = 2 * r + 1;
     const GlobalView v{d};
     if (threadIdx.x < 16) s.mbits[threadIdx.x] = 0;
@@ -320,6 +383,7 @@ __device__ void stage_target(const JobDev &d, int tx, int ty, int r, TargetStage
             }
         }
         tg->tpix[t] = pix;
+        s.tp[t] = pix;
     }
     kk = block_sum_i64(kk, s.k);
     t2 = block_sum_i64(t2, s.k);
@@ -331,6 +395,7 @@ __device__ void stage_target(const JobDev &d, int tx, int ty, int r, TargetStage
         tg->k = (int32_t)kk;
         tg->t2 = (uint32_t)t2;
     }
+    if (frag) build_mfma_frags(r, s, frag);
 }
 
 // Argmax over the priority blocks, then stages the winner as the next target.
@@ -353,7 +418,7 @@ __device__ void select_and_stage(const JobDev &d, Scratch &s) {
         return;
     }
     const int px = (int)(idx % d.W), py = (int)(idx / d.W);
-    stage_target(d, px, py, d.r, d.tgt, s);
+    stage_target(d, px, py, d.r, d.tgt, s, d.mfma ? d.frag : nullptr);
     if (threadIdx.x == 0) {
         const double2 cd = d.pcd[idx];
         st->p_idx = idx;
@@ -469,7 +534,8 @@ __device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, 
 // Stages the next target (nx, ny) from the LDS neighbourhood of the filled
 // target (px, py); valid when the whole patch lies inside it.
 template <int R>
-__device__ __forceinline__ void stage_target_lds(const LdsStage<R> &L, int px, int py, int tx, int ty, TargetStage *tg, Scratch &s) {
+__device__ __forceinline__ void stage_target_lds(const LdsStage<R> &L, int px, int py, int tx, int ty, TargetStage *tg,
+                                                 Scratch &s, MfmaFrags *frag) {
     using S = Stage<R>;
     constexpr int P = 2 * R + 1;
     if (threadIdx.x < 16) s.mbits[threadIdx.x] = 0;
@@ -489,6 +555,7 @@ __device__ __forceinline__ void stage_target_lds(const LdsStage<R> &L, int px, i
             }
         }
         tg->tpix[t] = pix;
+        s.tp[t] = pix;
     }
     kk = block_sum_i64(kk, s.k);
     t2 = block_sum_i64(t2, s.k);
@@ -500,6 +567,7 @@ __device__ __forceinline__ void stage_target_lds(const LdsStage<R> &L, int px, i
         tg->k = (int32_t)kk;
         tg->t2 = (uint32_t)t2;
     }
+    if (frag) build_mfma_frags(R, s, frag);
 }
 
 }  // namespace
@@ -824,9 +892,9 @@ __device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L) {
     const int tx = (int)(idx % W), ty = (int)(idx / W);
     const int adx = abs(tx - px), ady = abs(ty - py);
     if (adx <= 2 * R + 2 && ady <= 2 * R + 2)
-        stage_target_lds<R>(L, px, py, tx, ty, d.tgt, s);
+        stage_target_lds<R>(L, px, py, tx, ty, d.tgt, s, d.mfma ? d.frag : nullptr);
     else
-        stage_target(d, tx, ty, R, d.tgt, s);
+        stage_target(d, tx, ty, R, d.tgt, s, d.mfma ? d.frag : nullptr);
     if (threadIdx.x == 0) {
         double2 cd;
         if (adx <= 2 * R + 1 && ady <= 2 * R + 1)
@@ -864,7 +932,7 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit_batched(const JobDev 
 
 __global__ __launch_bounds__(kCommitThreads) void k_stage_query(JobDev d, int tx, int ty, int r) {
     __shared__ Scratch s;
-    stage_target(d, tx, ty, r, d.qtgt, s);
+    stage_target(d, tx, ty, r, d.qtgt, s, d.mfma && r <= kMfmaMaxRadius ? d.qfrag : nullptr);
 }
 
 __global__ __launch_bounds__(kCommitThreads) void k_reduce_partials(const uint64_t *partials, int n,

@@ -17,6 +17,8 @@ constexpr int kBlock = 8;                              // priority block side (o
 constexpr int kTileW = 64;                             // search tile width (one wave)
 constexpr int kSearchWaves = 4;                        // waves per search work-group
 constexpr int kCommitThreads = 256;   // one work-group per image; 512 VGPRs per thread
+constexpr int kMfmaMaxRadius = 6;     // int8-MFMA search: patches up to 13x13
+constexpr int kMfmaTileRows = 16;     // MFMA search tile: 64 x 64 candidates
 
 // Target patch as the search kernels read it.  Offset o = (dx, dy) has slot
 // (dx + r) * P + (dy + r) (column-major, so one column's P values are
@@ -28,6 +30,25 @@ struct alignas(256) TargetStage {
     uint32_t pad0[3];
     uint32_t mbits[16];
     uint32_t tpix[kMaxOffsets + 15];
+};
+
+// B operands of the int8-MFMA search for one staged target, in the exact
+// per-lane register layout of v_mfma_i32_16x16x64_i8 (16 bytes per lane):
+// lane (n = lane % 16, g = lane / 16) of
+//   c[dy][h]: target words t ^ 0x00808080 of patch pixels x = 16h + 4g + j,
+//             j = 0..3, of row dy, for candidate column n (banded Toeplitz);
+//   l[dy], h[dy]: 0/1 bytes selecting the low / high byte of |s'|^2 of
+//             pixels x = 8g + j, j = 0..7, where the target pixel is known.
+// Built once per target by the commit kernel; every search wave loads them.
+constexpr int kMfmaMaxPatch = 13;
+struct alignas(256) MfmaFrags {
+    int32_t c[kMfmaMaxPatch][2][64][4];
+    int32_t l[kMfmaMaxPatch][64][4];
+    int32_t h[kMfmaMaxPatch][64][4];
+    int32_t t2p;        // sum over known pixels of |t - 128|^2
+    int32_t k;          // known pixels
+    uint32_t rowmask;   // bit dy set if patch row dy has a known pixel
+    int32_t pad[61];
 };
 
 // One fill-iteration record, same layout as inpaint_step_info.
@@ -80,6 +101,10 @@ struct JobDev {
     uint64_t *partials;  // one (ssd << 32 | index) per search tile
     TargetStage *tgt;    // staged target of the fill loop
     TargetStage *qtgt;   // staged target of inpaint_find_exemplar
+    uint32_t *srcw;      // MFMA: original RGBX ^ 0x80808080 per pixel (static)
+    uint16_t *srcq;      // MFMA: (|s'|^2 low byte - 128, high byte - 128) per pixel (static)
+    MfmaFrags *frag;     // MFMA B operands of tgt (when mfma)
+    MfmaFrags *qfrag;    // MFMA B operands of qtgt (when mfma)
     IterState *st;
     StepRec *log;
     InitInfo *info;
@@ -89,6 +114,8 @@ struct JobDev {
     int32_t nbw;                  // blocks per image row
     int32_t tile_rows;            // candidate rows per thread in the search
     int32_t ntx, nty;             // search tiles over the rect
+    int32_t mfma;                 // 1: the search runs on the matrix cores
+    int32_t pad_;
     double norm1, norm2;          // 255 * |n| for |n|^2 = 1 and 2
 };
 
@@ -107,6 +134,11 @@ hipError_t launch_commit(const JobDev &d, hipStream_t s);
 hipError_t launch_search(const JobDev &d, bool query, int r, int rx0, int ry0, int rx1, int ry1,
                          int tile_rows, int ntx, int nty, hipStream_t s,
                          hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+bool mfma_supported(int r);
+// int8-MFMA form of the search; same tiling as launch_search with tile_rows 16.
+hipError_t launch_search_mfma(const JobDev &d, bool query, int r, int rx0, int ry0, int rx1, int ry1, int ntx, int nty,
+                              hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+hipError_t launch_mfma_planes(const JobDev &d, hipStream_t s);
 hipError_t launch_stage_query(const JobDev &d, int tx, int ty, int r, hipStream_t s);
 hipError_t launch_reduce_partials(const JobDev &d, int ntiles, uint64_t *out, hipStream_t s);
 hipError_t launch_commit_batched(const JobDev *slots, const int32_t *ids, const int32_t *n, int grid, int r,

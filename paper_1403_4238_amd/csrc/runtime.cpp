@@ -31,7 +31,8 @@ constexpr int kDefaultTileRows = 8;
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t img, gray, hole, vrad, conf, pcd, blk, partials, tgt, qtgt, st, info, key, log, total;
+    uint64_t img, gray, hole, vrad, conf, pcd, blk, partials, tgt, qtgt, frag, qfrag, srcw, srcq, st, info, key, log,
+        total;
     int64_t log_cap;
     int max_tiles;
 };
@@ -63,6 +64,11 @@ Layout make_layout(int W, int H, const inpaint_params &p) {
     L.partials = take(8ull * L.max_tiles);
     L.tgt = take(sizeof(TargetStage));
     L.qtgt = take(sizeof(TargetStage));
+    const bool mfma = p.path == INPAINT_PATH_MFMA;
+    L.frag = mfma ? take(sizeof(MfmaFrags)) : 0;
+    L.qfrag = mfma ? take(sizeof(MfmaFrags)) : 0;
+    L.srcw = mfma ? take(4 * n) : 0;
+    L.srcq = mfma ? take(2 * n) : 0;
     L.st = take(sizeof(IterState));
     L.info = take(sizeof(InitInfo));
     L.key = take(8);
@@ -109,6 +115,7 @@ struct inpaint_ctx {
     int64_t hole0 = 0;
     int64_t candidates = 0;
     inpaint_rect rect{};      // image-clipped search rect (reported)
+    bool mfma = false;        // search on the matrix cores
     int32_t sticky = 0;
     std::string err;
     IterState *h_state = nullptr;   // pinned mirror of the device state
@@ -208,6 +215,14 @@ static int32_t check_params(int32_t W, int32_t H, const inpaint_params *p, std::
         *why = "tile_rows must be 0, 4, 8 or 16";
         return INPAINT_INVALID_ARGUMENT;
     }
+    if (p->path == INPAINT_PATH_MFMA && !mfma_supported(p->patch_radius)) {
+        *why = "the int8-MFMA search supports patch radius 1..6";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    if (p->path == INPAINT_PATH_MFMA && p->tile_rows != 0 && p->tile_rows != kMfmaTileRows) {
+        *why = "the int8-MFMA search uses tile_rows 16";
+        return INPAINT_INVALID_ARGUMENT;
+    }
     for (int i = 0; i < 3; ++i)
         if (p->reserved[i] != 0) {
             *why = "reserved fields must be zero";
@@ -296,6 +311,11 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     d.partials = (uint64_t *)(ws + L.partials);
     d.tgt = (TargetStage *)(ws + L.tgt);
     d.qtgt = (TargetStage *)(ws + L.qtgt);
+    d.mfma = p->path == INPAINT_PATH_MFMA ? 1 : 0;
+    d.frag = d.mfma ? (MfmaFrags *)(ws + L.frag) : nullptr;
+    d.qfrag = d.mfma ? (MfmaFrags *)(ws + L.qfrag) : nullptr;
+    d.srcw = d.mfma ? (uint32_t *)(ws + L.srcw) : nullptr;
+    d.srcq = d.mfma ? (uint16_t *)(ws + L.srcq) : nullptr;
     d.st = (IterState *)(ws + L.st);
     d.info = (InitInfo *)(ws + L.info);
     d.log = (StepRec *)(ws + L.log);
@@ -319,6 +339,7 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     if (e == hipSuccess)
         e = hipMemcpy2DAsync(stage_mask, W, mask, mask_stride, W, H, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_init(d, stage_rgb, ch, stage_mask, hdist, s);
+    if (e == hipSuccess && d.mfma) e = launch_mfma_planes(d, s);
     if (e == hipSuccess) e = hipMemcpyAsync(c->h_key, d.info, sizeof(InitInfo), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return create_fail(c, INPAINT_DEVICE, std::string("init: ") + hipGetErrorString(e));
@@ -346,7 +367,8 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     d.ry0 = k[1];
     d.rx1 = std::max(k[2], k[0]);
     d.ry1 = std::max(k[3], k[1]);
-    set_tiles(d, p->tile_rows ? p->tile_rows : kDefaultTileRows);
+    c->mfma = p->path == INPAINT_PATH_MFMA;
+    set_tiles(d, c->mfma ? kMfmaTileRows : (p->tile_rows ? p->tile_rows : kDefaultTileRows));
 
     // Priority blocks: the hole's bbox grown by 2r+1 (how far a fill can
     // change a priority), in 32x32 blocks.
@@ -409,7 +431,10 @@ int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t tx, int32_t ty, int32_t 
     hipStream_t s = ctx->stream;
     uint64_t *dkey = (uint64_t *)(ctx->ws + ctx->L.key);
     HIP_OR_FAIL(ctx, launch_stage_query(q, tx, ty, r, s), "stage");
-    HIP_OR_FAIL(ctx, launch_search(q, true, r, q.rx0, q.ry0, q.rx1, q.ry1, q.tile_rows, q.ntx, q.nty, s), "search");
+    if (ctx->mfma && mfma_supported(r))
+        HIP_OR_FAIL(ctx, launch_search_mfma(q, true, r, q.rx0, q.ry0, q.rx1, q.ry1, q.ntx, q.nty, s), "search");
+    else
+        HIP_OR_FAIL(ctx, launch_search(q, true, r, q.rx0, q.ry0, q.rx1, q.ry1, q.tile_rows, q.ntx, q.nty, s), "search");
     HIP_OR_FAIL(ctx, launch_reduce_partials(q, q.ntx * q.nty, dkey, s), "reduce");
     HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_key, dkey, 8, hipMemcpyDeviceToHost, s), "copy");
     HIP_OR_FAIL(ctx, hipStreamSynchronize(s), "sync");
@@ -437,8 +462,11 @@ static hipError_t ensure_events(inpaint_ctx *ctx, size_t n) {
 static hipError_t enqueue_iteration(inpaint_ctx *ctx, hipStream_t s, int slot = -1) {
     const JobDev &d = ctx->d;
     hipError_t e = hipSuccess;
-    e = launch_search(d, false, d.r, d.rx0, d.ry0, d.rx1, d.ry1, d.tile_rows, d.ntx, d.nty, s,
-                      slot >= 0 ? ctx->ev0[slot] : nullptr, slot >= 0 ? ctx->ev1[slot] : nullptr);
+    hipEvent_t e0 = slot >= 0 ? ctx->ev0[slot] : nullptr, e1 = slot >= 0 ? ctx->ev1[slot] : nullptr;
+    if (ctx->mfma)
+        e = launch_search_mfma(d, false, d.r, d.rx0, d.ry0, d.rx1, d.ry1, d.ntx, d.nty, s, e0, e1);
+    else
+        e = launch_search(d, false, d.r, d.rx0, d.ry0, d.rx1, d.ry1, d.tile_rows, d.ntx, d.nty, s, e0, e1);
     if (e == hipSuccess) e = launch_commit(d, s);
     return e;
 }

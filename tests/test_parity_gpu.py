@@ -297,3 +297,82 @@ def test_search_timing_hooks(form):
     with pytest.raises(B.InpaintError) as e:
         gg.run()
     assert e.value.status == B.INVALID_ARGUMENT
+
+
+# ------------------------------------------------------- int8-MFMA search
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 6])
+def test_mfma_find_exemplar_matches_oracle(r):
+    job = synth.small()
+    o = oracle.Oracle(job.rgb, job.mask, 4)
+    g = B.Inpainter(job.rgb, job.mask, 4, path=B.PATH_MFMA)
+    rng = np.random.default_rng(100 + r)
+    front = o.front()
+    targets = [(int(i % 128), int(i // 128)) for i in front[:: max(len(front) // 5, 1)]]
+    targets += [(int(rng.integers(0, 128)), int(rng.integers(0, 96))) for _ in range(3)] + [(0, 0), (127, 95)]
+    for (x, y) in targets:
+        for rect in [(0, 0, 128, 96), (9, 5, 71, 50)]:
+            try:
+                want = o.find_exemplar(x, y, r, rect)[:2]
+            except oracle.OracleError as e:
+                assert e.status == oracle.NO_CANDIDATE
+                continue
+            assert g.find_exemplar(x, y, r, rect) == want, (r, x, y, rect)
+
+
+def test_mfma_extreme_pixel_values():
+    # Saturated channels (0 and 255) exercise the offset-by-128 int8 range ends.
+    rng = np.random.default_rng(77)
+    W, H = 90, 70
+    rgb = (rng.integers(0, 2, size=(H, W, 3)) * 255).astype(np.uint8)
+    rgb[::7, ::5] = 128
+    mask = np.zeros((H, W), np.uint8)
+    mask[30:41, 40:52] = 1
+    job = synth.Job("saturated", rgb, mask, 4)
+    _full_run_parity(job, "saturated mfma", path=B.PATH_MFMA)
+
+
+@pytest.mark.parametrize("seed,W,H,r", [(11, 40, 31, 3), (12, 67, 45, 5), (13, 130, 41, 6), (14, 50, 50, 1)])
+def test_mfma_full_run(seed, W, H, r):
+    rng = np.random.default_rng(seed)
+    rgb = rng.integers(0, 256, size=(H, W, 3)).astype(np.uint8)
+    mask = np.zeros((H, W), np.uint8)
+    mask[H // 3:H // 3 + max(H // 5, 2), W // 3:W // 3 + max(W // 6, 2)] = 1
+    mask[0:max(H // 8, 1), W - max(W // 7, 2):] = 1
+    _full_run_parity(synth.Job(f"mfma{seed}", rgb, mask, r), f"mfma{seed}", path=B.PATH_MFMA)
+
+
+def test_mfma_small_workload_and_window():
+    job = synth.small()
+    _full_run_parity(job, "small mfma", path=B.PATH_MFMA)
+    j2 = synth.Job("small-win", job.rgb, job.mask, 4, synth.SEARCH_ALPHA, (1, 2))
+    _full_run_parity(j2, "small-win mfma", path=B.PATH_MFMA)
+
+
+def test_mfma_rejects_large_radius():
+    job = synth.small()
+    with pytest.raises(B.InpaintError) as e:
+        B.Inpainter(job.rgb, job.mask, 7, path=B.PATH_MFMA)
+    assert e.value.status == B.INVALID_ARGUMENT
+
+
+@pytest.mark.parametrize("patch,window", [(9, False), (13, True)])
+def test_mfma_hd_first_iterations_live_oracle(patch, window):
+    job = synth.hd(patch=patch, window=window)
+    o, g = _pair(job, path=B.PATH_MFMA)
+    want = o.run(max_iters=2)
+    _, _, got = g.run(max_iters=2, log_cap=4)
+    assert_logs_equal(got, want, f"mfma hd p{patch}")
+
+
+@pytest.mark.parametrize("key", ["hd9", "hd13w"])
+def test_mfma_hd_full_run_matches_stored_oracle(key):
+    gold = load_golden(key)
+    if gold is None:
+        pytest.skip(f"stored oracle result for {key} not generated")
+    job = synth.hd(patch=int(key[2:].rstrip("w")), window=key.endswith("w"))
+    g = B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, form="graph",
+                    iters_per_check=32, path=B.PATH_MFMA)
+    st, n, log = g.run(log_cap=gold["iterations"] + 8)
+    assert st == B.DONE
+    assert_matches_golden(gold, log, g.read_image(), key + " mfma")
