@@ -32,8 +32,14 @@ sys.path.insert(0, ROOT)
 # MI355X (gfx950) public figures used for the roofline.
 CUS, LANES_PER_CU_CYCLE, CLOCK_HZ = 256, 64, 2.4e9
 VALU_LANE_OPS = CUS * LANES_PER_CU_CYCLE * CLOCK_HZ          # 39.32e12 lane-instructions/s
-TERMS_PER_VALU_OP = 1.5   # dot4 form: 2 VALU ops (cross dot4 + square add) per 3 RGB terms
-TERM_PEAK = VALU_LANE_OPS * TERMS_PER_VALU_OP                # 58.98e12 terms/s
+# A term is one (offset, channel, candidate) product of the cross term.  The
+# least VALU work for it is one v_dot4_u32_u8 per (known offset, candidate),
+# i.e. 3 RGB terms per lane-instruction (the square term costs O(column runs)
+# by running sums and is not counted).
+TERMS_PER_VALU_OP = 3.0
+TERM_PEAK = VALU_LANE_OPS * TERMS_PER_VALU_OP                # 117.96e12 terms/s
+# int8 MFMA, dense: 5.0 POP/s = 2.5e15 multiply-accumulates (terms) per second.
+MFMA_TERM_PEAK = 2.5e15
 HBM_PEAK_GBS = 8000.0
 
 
@@ -310,6 +316,7 @@ def main():
     avg_kernel_ms = res["kernel_ms"] / max(res["searches"], 1)
     terms_per_launch = terms_per_removal / max(len(log), 1)
     achieved = terms_per_launch / (avg_kernel_ms * 1e-3)
+    peak = MFMA_TERM_PEAK if a.path == "mfma" else TERM_PEAK
     # HBM bytes a search must move at least: the RGBX words of the candidate
     # windows' rows once (the frame is read through L2 / MALL every search).
     rx0, ry0, rx1, ry1 = res["rect"]
@@ -339,7 +346,8 @@ def main():
         "config": {
             "workload": f"{job.name}: {job.width}x{job.height} RGB u8, hole {int(job.mask.sum())} px, "
                         f"{2 * r + 1}x{2 * r + 1} patch, "
-                        f"{'alpha=1 window' if a.window else 'full search'}, SIMT dot4 search, "
+                        f"{'alpha=1 window' if a.window else 'full search'}, "
+                        f"{'int8-MFMA' if a.path == 'mfma' else 'SIMT dot4'} search, "
                         f"{a.form} form" + (f" ({a.iters_per_check} iterations per host check)"
                                              if a.form != "plain" else ""),
             "width": job.width, "height": job.height, "patch": 2 * r + 1,
@@ -351,9 +359,10 @@ def main():
         "iterations_per_s": round(sum(res["iters"]) / res["seconds"], 1),
         "parity": golden_check(job, a, log, res["image"]),
         "roofline": {
-            "bound": "alu", "kernel": f"k_search<R={r},NY={a.tile_rows or 8}>",
-            "achieved": round(achieved / 1e12, 3), "peak": round(TERM_PEAK / 1e12, 2),
-            "unit": "Tterm/s", "frac": round(achieved / TERM_PEAK, 4),
+            "bound": "mfma" if a.path == "mfma" else "alu",
+            "kernel": f"k_search_mfma<R={r}>" if a.path == "mfma" else f"k_search<R={r},NY={a.tile_rows or 8}>",
+            "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 2),
+            "unit": "Tterm/s", "frac": round(achieved / peak, 4),
             "traffic": None,
             "avg_launch_us": round(1000 * avg_kernel_ms, 3), "launches_timed": res["searches"],
             "terms_per_launch": round(terms_per_launch),

@@ -268,6 +268,8 @@ struct Scratch {
     int64_t i[16];
     uint64_t u[16];
     uint32_t mbits[16];
+    uint32_t sbits[16];
+    uint32_t ebits[16];
     uint32_t tp[kMaxOffsets + 15];   // the staged target words (column-major slots)
 };
 
@@ -332,6 +334,27 @@ __device__ void build_mfma_frags(int r, Scratch &s, MfmaFrags *f) {
     }
 }
 
+// Publishes the known mask of a staged target (s.mbits, final) and its
+// column-run boundaries: a known slot starts a run when the slot above it in
+// its column is unknown or outside the patch, and ends one when the slot
+// below is.  One thread per slot; called by the whole work-group.
+__device__ void write_mask_bits(Scratch &s, int P, TargetStage *tg) {
+    auto known = [&](int slot) { return (s.mbits[slot >> 5] >> (slot & 31)) & 1u; };
+    for (int slot = threadIdx.x; slot < P * P; slot += blockDim.x) {
+        if (!known(slot)) continue;
+        const int dyi = slot % P;
+        const uint32_t bit = 1u << (slot & 31);
+        if (dyi == 0 || !known(slot - 1)) atomicOr(&s.sbits[slot >> 5], bit);
+        if (dyi == P - 1 || !known(slot + 1)) atomicOr(&s.ebits[slot >> 5], bit);
+    }
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        tg->mbits[threadIdx.x] = s.mbits[threadIdx.x];
+        tg->sbits[threadIdx.x] = s.sbits[threadIdx.x];
+        tg->ebits[threadIdx.x] = s.ebits[threadIdx.x];
+    }
+}
+
 __device__ __forceinline__ void wave_argmax(int64_t &key, int64_t &idx) {
     for (int off = 32; off > 0; off >>= 1) {
         const int64_t k2 = __shfl_xor(key, off);
@@ -366,7 +389,11 @@ __device__ void stage_target(const JobDev &d, int tx, int ty, int r, TargetStage
                              MfmaFrags *frag) {
     const int P = 2 * r + 1;
     const GlobalView v{d};
-    if (threadIdx.x < 16) s.mbits[threadIdx.x] = 0;
+    if (threadIdx.x < 16) {
+        s.mbits[threadIdx.x] = 0;
+        s.sbits[threadIdx.x] = 0;
+        s.ebits[threadIdx.x] = 0;
+    }
     __syncthreads();
     int64_t kk = 0, t2 = 0;
     for (int t = threadIdx.x; t < kMaxOffsets + 15; t += blockDim.x) {
@@ -387,7 +414,7 @@ __device__ void stage_target(const JobDev &d, int tx, int ty, int r, TargetStage
     }
     kk = block_sum_i64(kk, s.k);
     t2 = block_sum_i64(t2, s.k);
-    if (threadIdx.x < 16) tg->mbits[threadIdx.x] = s.mbits[threadIdx.x];
+    write_mask_bits(s, P, tg);
     if (threadIdx.x == 0) {
         tg->tx = tx;
         tg->ty = ty;
@@ -538,7 +565,11 @@ __device__ __forceinline__ void stage_target_lds(const LdsStage<R> &L, int px, i
                                                  Scratch &s, MfmaFrags *frag) {
     using S = Stage<R>;
     constexpr int P = 2 * R + 1;
-    if (threadIdx.x < 16) s.mbits[threadIdx.x] = 0;
+    if (threadIdx.x < 16) {
+        s.mbits[threadIdx.x] = 0;
+        s.sbits[threadIdx.x] = 0;
+        s.ebits[threadIdx.x] = 0;
+    }
     __syncthreads();
     int64_t kk = 0, t2 = 0;
     for (int t = threadIdx.x; t < kMaxOffsets + 15; t += blockDim.x) {
@@ -559,7 +590,7 @@ __device__ __forceinline__ void stage_target_lds(const LdsStage<R> &L, int px, i
     }
     kk = block_sum_i64(kk, s.k);
     t2 = block_sum_i64(t2, s.k);
-    if (threadIdx.x < 16) tg->mbits[threadIdx.x] = s.mbits[threadIdx.x];
+    write_mask_bits(s, P, tg);
     if (threadIdx.x == 0) {
         tg->tx = tx;
         tg->ty = ty;
@@ -662,6 +693,24 @@ __global__ __launch_bounds__(256) void k_init_vrad(JobDev d, const uint8_t *hdis
     int v = dist - 1;
     v = v < 0 ? 0 : (v > kMaxRadius ? kMaxRadius : v);
     d.vrad[i] = (uint8_t)v;
+}
+
+// Static search planes: the original image (hole pixels zero) and vrad in
+// the zero-padded layout the search stages from.
+__global__ __launch_bounds__(256) void k_init_padded(JobDev d) {
+    const int pitch = d.pitch;
+    const int64_t n = (int64_t)pitch * padded_rows(d.H);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int x = (int)(i % pitch) - kPadL, y = (int)(i / pitch) - kPadT;
+    uint32_t pix = 0;
+    uint8_t vr = 0;
+    if (x >= 0 && x < d.W && y >= 0 && y < d.H) {
+        pix = d.img[(int64_t)y * d.W + x];
+        vr = d.vrad[(int64_t)y * d.W + x];
+    }
+    d.srcp[i] = pix;
+    d.vradp[i] = vr;
 }
 
 // Number of valid source centres in the search rectangle.
@@ -977,6 +1026,8 @@ hipError_t launch_init(const JobDev &d, const uint8_t *stage_rgb, int channels,
     hipLaunchKernelGGL(k_init_hdist, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, hdist);
     hipLaunchKernelGGL(k_init_vrad, dim3(blocks_for(n, 256)), dim3(256), 0, s, d,
                        (const uint8_t *)hdist);
+    const int64_t np = (int64_t)d.pitch * padded_rows(d.H);
+    hipLaunchKernelGGL(k_init_padded, dim3(blocks_for(np, 256)), dim3(256), 0, s, d);
     return hipGetLastError();
 }
 

@@ -20,15 +20,33 @@ constexpr int kCommitThreads = 256;   // one work-group per image; 512 VGPRs per
 constexpr int kMfmaMaxRadius = 6;     // int8-MFMA search: patches up to 13x13
 constexpr int kMfmaTileRows = 16;     // MFMA search tile: 64 x 64 candidates
 
+// Padding of the static search planes (srcp, vradp, srcw, srcq) around the
+// image, in pixels: every staged search window -- a tile of up to 64 x 64
+// candidates, its halo of up to kMaxRadius and the alignment of its start --
+// lies inside the padded plane, so the search loads need no bounds checks.
+// The pitch is a multiple of 8 pixels, so rows of every plane start on a
+// 16-byte boundary.
+constexpr int kPadL = 8, kPadT = 8, kPadR = 84, kPadB = 72;
+__host__ __device__ inline int padded_pitch(int W) { return (kPadL + W + kPadR + 7) / 8 * 8; }
+__host__ __device__ inline int padded_rows(int H) { return kPadT + H + kPadB; }
+// First tile column of the MFMA search over a rect starting at rx0: moved
+// left (by at most 7) so that every tile's staged window, which starts r
+// columns left of the tile, starts on an 8-pixel boundary of the padded
+// planes.  Columns left of rx0 are not candidates.
+__host__ __device__ inline int mfma_tile_x0(int rx0, int r) { return rx0 - ((rx0 - r + kPadL) & 7); }
+
 // Target patch as the search kernels read it.  Offset o = (dx, dy) has slot
 // (dx + r) * P + (dy + r) (column-major, so one column's P values are
 // contiguous).  tpix holds the target's RGBX word (X = 0) where the pixel is
-// known and 0 elsewhere; bit `slot` of mbits is 1 where known.
+// known and 0 elsewhere; bit `slot` of mbits is 1 where known.  sbits
+// (ebits) mark the first (last) slot of each run of known slots in a column.
 struct alignas(256) TargetStage {
     int32_t tx, ty, r, k;
     uint32_t t2;                 // sum over known pixels of R^2 + G^2 + B^2
     uint32_t pad0[3];
     uint32_t mbits[16];
+    uint32_t sbits[16];
+    uint32_t ebits[16];
     uint32_t tpix[kMaxOffsets + 15];
 };
 
@@ -101,8 +119,10 @@ struct JobDev {
     uint64_t *partials;  // one (ssd << 32 | index) per search tile
     TargetStage *tgt;    // staged target of the fill loop
     TargetStage *qtgt;   // staged target of inpaint_find_exemplar
-    uint32_t *srcw;      // MFMA: original RGBX ^ 0x80808080 per pixel (static)
-    uint16_t *srcq;      // MFMA: (|s'|^2 low byte - 128, high byte - 128) per pixel (static)
+    uint32_t *srcw;      // MFMA: original RGBX ^ 0x80808080, padded plane (static)
+    uint16_t *srcq;      // MFMA: (|s'|^2 low byte - 128, high byte - 128), padded plane (static)
+    uint32_t *srcp;      // original RGBX in the padded plane, zero outside the image (static)
+    uint8_t *vradp;      // vrad in the padded plane, zero outside the image (static)
     MfmaFrags *frag;     // MFMA B operands of tgt (when mfma)
     MfmaFrags *qfrag;    // MFMA B operands of qtgt (when mfma)
     IterState *st;
@@ -115,7 +135,7 @@ struct JobDev {
     int32_t tile_rows;            // candidate rows per thread in the search
     int32_t ntx, nty;             // search tiles over the rect
     int32_t mfma;                 // 1: the search runs on the matrix cores
-    int32_t pad_;
+    int32_t pitch;                // row pitch of srcp / vradp in pixels (multiple of 4)
     double norm1, norm2;          // 255 * |n| for |n|^2 = 1 and 2
 };
 

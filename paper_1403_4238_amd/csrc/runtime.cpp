@@ -31,8 +31,8 @@ constexpr int kDefaultTileRows = 8;
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t img, gray, hole, vrad, conf, pcd, blk, partials, tgt, qtgt, frag, qfrag, srcw, srcq, st, info, key, log,
-        total;
+    uint64_t img, gray, hole, vrad, conf, pcd, blk, partials, tgt, qtgt, frag, qfrag, srcw, srcq, srcp, vradp, st, info,
+        key, log, total;
     int64_t log_cap;
     int max_tiles;
 };
@@ -60,15 +60,19 @@ Layout make_layout(int W, int H, const inpaint_params &p) {
     L.pcd = take(16 * n);  // also the upload staging area during create (<= 6n bytes)
     const uint64_t nblk = (uint64_t)((W + kBlock - 1) / kBlock) * ((H + kBlock - 1) / kBlock);
     L.blk = take(sizeof(BlockBest) * nblk);
-    L.max_tiles = ((W + kTileW - 1) / kTileW) * ((H + search_tile_h(4) - 1) / search_tile_h(4));
+    // (+7: the MFMA tiling may start up to 7 columns left of the rect)
+    L.max_tiles = ((W + 7 + kTileW - 1) / kTileW) * ((H + search_tile_h(4) - 1) / search_tile_h(4));
     L.partials = take(8ull * L.max_tiles);
     L.tgt = take(sizeof(TargetStage));
     L.qtgt = take(sizeof(TargetStage));
     const bool mfma = p.path == INPAINT_PATH_MFMA;
     L.frag = mfma ? take(sizeof(MfmaFrags)) : 0;
     L.qfrag = mfma ? take(sizeof(MfmaFrags)) : 0;
-    L.srcw = mfma ? take(4 * n) : 0;
-    L.srcq = mfma ? take(2 * n) : 0;
+    const uint64_t np = (uint64_t)padded_pitch(W) * padded_rows(H);
+    L.srcw = mfma ? take(4 * np) : 0;
+    L.srcq = mfma ? take(2 * np) : 0;
+    L.srcp = take(4 * np);
+    L.vradp = take(np);
     L.st = take(sizeof(IterState));
     L.info = take(sizeof(InitInfo));
     L.key = take(8);
@@ -249,10 +253,13 @@ static void kernel_rect(int W, int H, int r, const inpaint_rect &img_rect, int *
     k[3] = std::min(img_rect.y1, H - r);
 }
 
-static void set_tiles(JobDev &d, int tile_rows) {
+// Search tiles over the kernel rect; mfma_r > 0 selects the MFMA tiling of
+// that radius (64 x 64 tiles from an aligned first column).
+static void set_tiles(JobDev &d, int tile_rows, int mfma_r = 0) {
     d.tile_rows = tile_rows;
     const int rw = std::max(d.rx1 - d.rx0, 0), rh = std::max(d.ry1 - d.ry0, 0);
-    d.ntx = (rw + kTileW - 1) / kTileW;
+    const int tx0 = mfma_r > 0 ? mfma_tile_x0(d.rx0, mfma_r) : d.rx0;
+    d.ntx = (std::max(d.rx1 - tx0, 0) + kTileW - 1) / kTileW;
     d.nty = (rh + search_tile_h(tile_rows) - 1) / search_tile_h(tile_rows);
     if (rw == 0 || rh == 0) d.ntx = d.nty = 0;
 }
@@ -316,6 +323,9 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     d.qfrag = d.mfma ? (MfmaFrags *)(ws + L.qfrag) : nullptr;
     d.srcw = d.mfma ? (uint32_t *)(ws + L.srcw) : nullptr;
     d.srcq = d.mfma ? (uint16_t *)(ws + L.srcq) : nullptr;
+    d.srcp = (uint32_t *)(ws + L.srcp);
+    d.vradp = ws + L.vradp;
+    d.pitch = padded_pitch(W);
     d.st = (IterState *)(ws + L.st);
     d.info = (InitInfo *)(ws + L.info);
     d.log = (StepRec *)(ws + L.log);
@@ -368,7 +378,7 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     d.rx1 = std::max(k[2], k[0]);
     d.ry1 = std::max(k[3], k[1]);
     c->mfma = p->path == INPAINT_PATH_MFMA;
-    set_tiles(d, c->mfma ? kMfmaTileRows : (p->tile_rows ? p->tile_rows : kDefaultTileRows));
+    set_tiles(d, c->mfma ? kMfmaTileRows : (p->tile_rows ? p->tile_rows : kDefaultTileRows), c->mfma ? d.r : 0);
 
     // Priority blocks: the hole's bbox grown by 2r+1 (how far a fill can
     // change a priority), in 32x32 blocks.
@@ -427,7 +437,7 @@ int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t tx, int32_t ty, int32_t 
     q.ry0 = k[1];
     q.rx1 = k[2];
     q.ry1 = k[3];
-    set_tiles(q, d.tile_rows);
+    set_tiles(q, d.tile_rows, ctx->mfma && mfma_supported(r) ? r : 0);
     hipStream_t s = ctx->stream;
     uint64_t *dkey = (uint64_t *)(ctx->ws + ctx->L.key);
     HIP_OR_FAIL(ctx, launch_stage_query(q, tx, ty, r, s), "stage");

@@ -7,19 +7,26 @@
 // exactly in 32-bit integers, as T2 - 2 X(c) + S(c) with
 //     X(c) = sum_o m(o) <t(o), I(c+o)>,   S(c) = sum_o m(o) |I(c+o)|^2,
 // where <.,.> is the dot product of two RGBX words (X = 0 in the target).
-// Each known (offset, candidate) pair costs two v_dot4_u32_u8: one for the
-// cross term and one (shared per source pixel) for the square.
+// The cross term costs one v_dot4_u32_u8 per (known offset, candidate).  The
+// square term is taken from running sums down each patch column: with
+// Q_j = sum_{j' < j} |s_j'|^2 over the source words a lane holds for one
+// column, a run of known offsets dy = a..b adds Q_{i+b+1} - Q_{i+a} to
+// candidate row i, so S costs two adds per (column run, candidate) instead of
+// one per known offset, and the Q_j take one dot4-accumulate each.
 //
 // Work decomposition: a work-group of 4 waves owns a 64-column x (4*NY)-row
-// tile of candidate centres.  The source pixels of the tile plus its r-pixel
-// halo are staged once in LDS as RGBX words.  Lane l of wave w handles the
-// column x0 + l and NY consecutive rows; for each dx it loads the NY + 2r
-// source words of its column once and reuses each for every (dy, candidate)
-// pair that needs it.  The known-offset mask is uniform across the wave, so
-// masked offsets are skipped with scalar branches and cost nothing.  Scores
-// are reduced to one key (ssd << 32 | raster index) per tile: the minimum key
-// is the (ssd, index)-lexicographic minimum, i.e. ties go to the lowest
-// raster index.  No SSD array is ever written.
+// tile of candidate centres.  Candidate windows lie in the original known
+// region, whose pixels never change, so the search reads a static copy of
+// the image in a zero-padded plane: the tile plus its r-pixel halo is staged
+// into LDS with unconditional 16-byte loads, all issued before the first
+// wait, together with the validity radii of the candidates.  Lane l of wave
+// w handles column x0 + l and NY consecutive rows; for each dx it reads the
+// NY + 2r source words of its column once and reuses each for every
+// (dy, candidate) pair that needs it.  The masks are uniform across the
+// wave, so masked offsets are skipped with scalar branches and cost nothing.
+// Scores are reduced to one key (ssd << 32 | raster index) per tile: the
+// minimum key is the (ssd, index)-lexicographic minimum, i.e. ties go to the
+// lowest raster index.  No SSD array is ever written.
 #include <hip/hip_ext.h>
 
 #include "inpaint_dev.h"
@@ -45,82 +52,112 @@ template <int R, int NY>
 struct TileGeom {
     static constexpr int P = 2 * R + 1;
     static constexpr int TH = kSearchWaves * NY;
-    static constexpr int LW = kTileW + 2 * R;
+    static constexpr int NJ = NY + 2 * R;                       // source rows per lane and column
+    static constexpr int LW = (kTileW + 2 * R + 3 + 3) / 4 * 4;  // staged words per row, from a 16-byte boundary
+    static constexpr int LQ = LW / 4;
     static constexpr int LH = TH + 2 * R;
+    static constexpr int NQ = LQ * LH;                           // 16-byte quads per staged tile
+    static constexpr int QIT = (NQ + kSearchWaves * 64 - 1) / (kSearchWaves * 64);
     static constexpr int LDS_WORDS = LW * LH;
+    static constexpr int MW = (P * P + 31) / 32;
 };
 
-// Scores one tile and writes its minimum key to out[tile].
+// Scores one tile and writes its minimum key to out[tile].  `live` (uniform)
+// is false when the fill loop has nothing pending: the tile is then staged
+// but neither scored nor written.
 template <int R, int NY>
-__device__ __forceinline__ void search_tile(const JobDev &d, const TargetStage *tg_generic,
+__device__ __forceinline__ void search_tile(const JobDev &d, const TargetStage *tg_generic, bool live,
                                             int rx0, int ry0, int rx1, int ry1, int ntx, int tile,
-                                            uint64_t *__restrict__ out, uint32_t *lds,
-                                            uint64_t *red) {
+                                            uint64_t *__restrict__ out, uint32_t *lds, uint64_t *red) {
     using G = TileGeom<R, NY>;
     ConstTarget *tg = (ConstTarget *)tg_generic;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tx0 = rx0 + (tile % ntx) * kTileW;
     const int ty0 = ry0 + (tile / ntx) * G::TH;
-    const int W = d.W, H = d.H;
+    const int W = d.W, pitch = d.pitch;
     const int x = tx0 + lane;
     const int yb = ty0 + wave * NY;
 
-    // Validity of this thread's candidates and the tile staging (the tile
-    // plus its halo: rows ty0-R .., columns tx0-R ..) are loaded together;
-    // one barrier then publishes the LDS tile and tells whether any
-    // candidate of the tile is valid.
-    uint32_t vmask = 0;
-    if (x < rx1) {
+    // ---- issue every load of the tile before any wait: the staged window
+    // (padded rows ty0 - R + kPadT .., columns from the 16-byte boundary at
+    // or below tx0 - R + kPadL) and the validity radii of this lane's rows.
+    const int gx0 = tx0 - R + kPadL;
+    const int sh = gx0 & 3;
+    const uint4 *src4 = (const uint4 *)(d.srcp + (int64_t)(ty0 - R + kPadT) * pitch + (gx0 - sh));
+    const int qpitch = pitch >> 2;
+    uint4 q[G::QIT];
 #pragma unroll
-        for (int i = 0; i < NY; ++i) {
-            const int y = yb + i;
-            if (y < ry1 && d.vrad[(int64_t)y * W + x] >= R) vmask |= 1u << i;
-        }
+    for (int k = 0; k < G::QIT; ++k) {
+        const int qi = min(tid + k * kSearchWaves * 64, G::NQ - 1);
+        const int ly = qi / G::LQ, lq = qi - ly * G::LQ;
+        q[k] = src4[ly * qpitch + lq];
     }
-    for (int i = tid; i < G::LDS_WORDS; i += kSearchWaves * 64) {
-        const int ly = i / G::LW, lx = i - ly * G::LW;
-        const int gx = tx0 - R + lx, gy = ty0 - R + ly;
-        uint32_t v = 0;
-        if ((unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H) v = d.img[(int64_t)gy * W + gx];
-        lds[i] = v;
-    }
-    if (!__syncthreads_or(vmask != 0)) {
-        if (tid == 0) out[tile] = ~0ull;
+    const uint8_t *vr = d.vradp + (int64_t)(yb + kPadT) * pitch + (x + kPadL);
+    uint32_t v[NY];
+#pragma unroll
+    for (int i = 0; i < NY; ++i) v[i] = vr[i * pitch];
+
+    // ---- publish: one barrier makes the LDS tile visible and tells whether
+    // any candidate of the tile is valid.
+    uint4 *lds4 = (uint4 *)lds;
+#pragma unroll
+    for (int k = 0; k < G::QIT; ++k) lds4[min(tid + k * kSearchWaves * 64, G::NQ - 1)] = q[k];
+    uint32_t vmask = 0;
+#pragma unroll
+    for (int i = 0; i < NY; ++i)
+        if (x < rx1 && yb + i < ry1 && v[i] >= (uint32_t)R) vmask |= 1u << i;
+    if (!__syncthreads_or(live && vmask != 0)) {
+        if (tid == 0 && live) out[tile] = ~0ull;
         return;
     }
 
-    uint32_t A[NY], B[NY];
+    uint32_t A[NY], S[NY];
 #pragma unroll
     for (int i = 0; i < NY; ++i) {
         A[i] = 0;
-        B[i] = 0;
+        S[i] = 0;
     }
-    uint32_t mb[(G::P * G::P + 31) / 32];
+    uint32_t mb[G::MW], sb[G::MW], eb[G::MW];
 #pragma unroll
-    for (int w = 0; w < (G::P * G::P + 31) / 32; ++w) mb[w] = tg->mbits[w];
-    const uint32_t *colp = lds + wave * NY * G::LW + lane;
+    for (int w = 0; w < G::MW; ++w) {
+        mb[w] = tg->mbits[w];
+        sb[w] = tg->sbits[w];
+        eb[w] = tg->ebits[w];
+    }
+    const uint32_t *colp = lds + wave * NY * G::LW + lane + sh;
 #pragma unroll
     for (int dxi = 0; dxi < G::P; ++dxi) {
         // This column's target words, loaded unconditionally (scalar loads).
         uint32_t tcol[G::P];
 #pragma unroll
         for (int dyi = 0; dyi < G::P; ++dyi) tcol[dyi] = tg->tpix[dxi * G::P + dyi];
-        uint32_t col[NY + 2 * R], sq[NY + 2 * R];
+        uint32_t col[G::NJ], pre[G::NJ + 1];
+        pre[0] = 0;
 #pragma unroll
-        for (int j = 0; j < NY + 2 * R; ++j) {
+        for (int j = 0; j < G::NJ; ++j) {
             col[j] = colp[j * G::LW + dxi];
-            sq[j] = __builtin_amdgcn_udot4(col[j], col[j], 0u, false);
+            pre[j + 1] = __builtin_amdgcn_udot4(col[j], col[j], pre[j], false);
         }
 #pragma unroll
         for (int dyi = 0; dyi < G::P; ++dyi) {
             const int slot = dxi * G::P + dyi;
-            if (mb[slot >> 5] & (1u << (slot & 31))) {
+            const uint32_t bit = 1u << (slot & 31);
+            if (mb[slot >> 5] & bit) {
                 const uint32_t t = tcol[dyi];
 #pragma unroll
-                for (int i = 0; i < NY; ++i) {
-                    A[i] = __builtin_amdgcn_udot4(t, col[i + dyi], A[i], false);
-                    B[i] += sq[i + dyi];
-                }
+                for (int i = 0; i < NY; ++i) A[i] = __builtin_amdgcn_udot4(t, col[i + dyi], A[i], false);
+            }
+            // The empty volatile asm keeps these blocks behind their scalar
+            // branches (instead of being speculated into selects).
+            if (sb[slot >> 5] & bit) {
+                asm volatile("");
+#pragma unroll
+                for (int i = 0; i < NY; ++i) S[i] -= pre[i + dyi];
+            }
+            if (eb[slot >> 5] & bit) {
+                asm volatile("");
+#pragma unroll
+                for (int i = 0; i < NY; ++i) S[i] += pre[i + dyi + 1];
             }
         }
     }
@@ -130,7 +167,7 @@ __device__ __forceinline__ void search_tile(const JobDev &d, const TargetStage *
 #pragma unroll
     for (int i = 0; i < NY; ++i) {
         if (vmask & (1u << i)) {
-            const uint32_t ssd = t2 - 2u * A[i] + B[i];
+            const uint32_t ssd = t2 - 2u * A[i] + S[i];
             const uint64_t key = ((uint64_t)ssd << 32) | (uint32_t)((yb + i) * W + x);
             best = key < best ? key : best;
         }
@@ -158,15 +195,18 @@ template <int R, int NY>
 __global__ __launch_bounds__(kSearchWaves * 64) void k_search(JobDev d, int query, int rx0, int ry0,
                                                               int rx1, int ry1, int ntx, int ntiles) {
     using G = TileGeom<R, NY>;
-    __shared__ uint32_t lds[G::LDS_WORDS];
+    __shared__ __attribute__((aligned(16))) uint32_t lds[G::LDS_WORDS];
     __shared__ uint64_t red[kSearchWaves];
-    if (!query) {
-        const IterState *st = d.st;
-        if (st->done || st->error || !st->pending || st->iter >= st->iter_limit) return;
-    }
     const int tile = xcd_band_tile((int)blockIdx.x, (int)gridDim.x);
     if (tile >= ntiles) return;
-    search_tile<R, NY>(d, query ? d.qtgt : d.tgt, rx0, ry0, rx1, ry1, ntx, tile, d.partials, lds, red);
+    // The state is read here but tested only after the tile loads are
+    // issued, so its latency overlaps theirs.
+    bool live = true;
+    if (!query) {
+        const IterState *st = d.st;
+        live = !(st->done || st->error || !st->pending || st->iter >= st->iter_limit);
+    }
+    search_tile<R, NY>(d, query ? d.qtgt : d.tgt, live, rx0, ry0, rx1, ry1, ntx, tile, d.partials, lds, red);
 }
 
 // Persistent form over many images: work-groups stride over a static list of
@@ -176,7 +216,7 @@ __global__ __launch_bounds__(kSearchWaves * 64) void k_search_batched(const JobD
                                                                       const WorkItem *items,
                                                                       const int32_t *nitems) {
     using G = TileGeom<R, NY>;
-    __shared__ uint32_t lds[G::LDS_WORDS];
+    __shared__ __attribute__((aligned(16))) uint32_t lds[G::LDS_WORDS];
     __shared__ uint64_t red[kSearchWaves];
     const int n = *nitems;
     for (int it = blockIdx.x; it < n; it += gridDim.x) {
@@ -185,7 +225,7 @@ __global__ __launch_bounds__(kSearchWaves * 64) void k_search_batched(const JobD
         const IterState *st = d.st;
         const bool live = st && !st->done && !st->error && st->pending && st->iter < st->iter_limit;
         if (live)
-            search_tile<R, NY>(d, d.tgt, d.rx0, d.ry0, d.rx1, d.ry1, d.ntx, w.tile, d.partials, lds, red);
+            search_tile<R, NY>(d, d.tgt, true, d.rx0, d.ry0, d.rx1, d.ry1, d.ntx, w.tile, d.partials, lds, red);
         __syncthreads();
     }
 }

@@ -20,6 +20,12 @@
 // builds them once per target in the register layout, each wave loads them
 // with coalesced 16-byte reads and keeps them in registers; the A fragments
 // are 16-byte LDS reads from the staged tile.
+//
+// The planes are static (candidate windows lie in the original known
+// region, which never changes) and zero-padded, and the tiling starts on a
+// column that puts every staged window on an 8-pixel boundary: a tile is
+// staged with unconditional 16-byte loads, issued together with the
+// candidates' validity radii and the B fragments before the first wait.
 #include <hip/hip_ext.h>
 
 #include "inpaint_dev.h"
@@ -32,7 +38,6 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaTilesPerWave = 4;                       // 16-row tiles stacked per wave
 constexpr int kMfmaTileH = 16 * kMfmaTilesPerWave;          // 64 rows: the SIMT tiling with 16 rows per thread
-constexpr int kMfmaCols = 80;                               // staged columns (64 + halo, rounded)
 constexpr int kMfmaStrideA = 100;                           // words per staged row (100 % 32 == 4)
 constexpr int kMfmaStrideQ = 272;                           // bytes per |s'|^2 row (68 words, 68 % 32 == 4)
 
@@ -40,6 +45,12 @@ template <int R>
 struct MfmaGeom {
     static constexpr int P = 2 * R + 1;
     static constexpr int ROWS = kMfmaTileH + 2 * R;
+    static constexpr int COLS = kTileW + 2 * R;                 // staged columns that meet nonzero B entries
+    static constexpr int QA = (COLS + 3) / 4;                   // 16-byte quads per row: RGBX words
+    static constexpr int QQ = (2 * COLS + 15) / 16;             // 16-byte quads per row: |s'|^2 byte pairs
+    static constexpr int NA = ROWS * QA, NQ = ROWS * QQ;
+    static constexpr int AIT = (NA + kSearchWaves * 64 - 1) / (kSearchWaves * 64);
+    static constexpr int QIT = (NQ + kSearchWaves * 64 - 1) / (kSearchWaves * 64);
 };
 
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
@@ -61,58 +72,48 @@ __device__ __forceinline__ uint16_t sq_bytes(uint32_t w) {
 
 template <int R>
 struct MfmaLds {
-    uint32_t a[MfmaGeom<R>::ROWS * kMfmaStrideA];            // RGBX ^ 0x80808080
-    uint8_t q[MfmaGeom<R>::ROWS * kMfmaStrideQ + 32];         // (lo', hi') per pixel
+    alignas(16) uint32_t a[MfmaGeom<R>::ROWS * kMfmaStrideA];   // RGBX ^ 0x80808080
+    alignas(16) uint8_t q[MfmaGeom<R>::ROWS * kMfmaStrideQ + 32];  // (lo', hi') per pixel
     uint64_t red[kSearchWaves];
 };
 
 template <int R>
-__device__ __forceinline__ void search_tile_mfma(const JobDev &d, const MfmaFrags *frag, int rx0, int ry0, int rx1,
-                                                 int ry1, int ntx, int tile, uint64_t *out, MfmaLds<R> &L) {
+__device__ __forceinline__ void search_tile_mfma(const JobDev &d, const MfmaFrags *frag, bool live, int rx0, int ry0,
+                                                 int rx1, int ry1, int ntx, int tile, uint64_t *out, MfmaLds<R> &L) {
     using G = MfmaGeom<R>;
     constexpr int P = G::P;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = lane & 15, g = lane >> 4;
-    const int tx0 = rx0 + (tile % ntx) * kTileW;
+    const int tx0 = mfma_tile_x0(rx0, R) + (tile % ntx) * kTileW;
     const int ty0 = ry0 + (tile / ntx) * kMfmaTileH;
-    const int W = d.W, H = d.H;
+    const int W = d.W, pitch = d.pitch;
     const int cx = tx0 + 16 * wave + n;   // this lane's candidate column
 
-    // Validity of this lane's candidates: rows 16 t + 4 g + i of the tile.
-    uint32_t vmask = 0;
-    if (cx < rx1) {
+    // ---- issue: staged window (padded rows ty0 - R + kPadT .., columns
+    // tx0 - R + kPadL .., a multiple of 8), validity radii of this lane's
+    // candidates (rows 16 t + 4 g + i of the tile) and the B fragments.
+    const int64_t org = (int64_t)(ty0 - R + kPadT) * pitch + (tx0 - R + kPadL);
+    const uint4 *wa = (const uint4 *)(d.srcw + org);
+    const uint4 *wq = (const uint4 *)(d.srcq + org);
+    uint4 va[G::AIT], vq[G::QIT];
 #pragma unroll
-        for (int t = 0; t < kMfmaTilesPerWave; ++t)
+    for (int k = 0; k < G::AIT; ++k) {
+        const int i = min(tid + k * kSearchWaves * 64, G::NA - 1);
+        const int ly = i / G::QA, lq = i - ly * G::QA;
+        va[k] = wa[ly * (pitch >> 2) + lq];
+    }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int y = ty0 + 16 * t + 4 * g + i;
-                if (y < ry1 && d.vrad[(int64_t)y * W + cx] >= R) vmask |= 1u << (4 * t + i);
-            }
+    for (int k = 0; k < G::QIT; ++k) {
+        const int i = min(tid + k * kSearchWaves * 64, G::NQ - 1);
+        const int ly = i / G::QQ, lq = i - ly * G::QQ;
+        vq[k] = wq[ly * (pitch >> 3) + lq];
     }
-    // Stage the source tile (+ halo) as offset words and |s'|^2 bytes.
-    // Columns past 64 + 2R are read by the MFMA fragments but meet zero B
-    // entries, so they are left unstaged.
-    constexpr int COLS = kTileW + 2 * R;
-    for (int i = tid; i < G::ROWS * COLS; i += kSearchWaves * 64) {
-        const int ly = i / COLS, lx = i - ly * COLS;
-        const int gx = tx0 - R + lx, gy = ty0 - R + ly;
-        uint32_t v = 0x80808080u;
-        uint16_t q = 0;
-        if ((unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H) {
-            const int64_t gi = (int64_t)gy * W + gx;
-            v = d.srcw[gi];
-            q = d.srcq[gi];
-        }
-        L.a[ly * kMfmaStrideA + lx] = v;
-        *(uint16_t *)&L.q[ly * kMfmaStrideQ + 2 * lx] = q;
-    }
-    if (!__syncthreads_or(vmask != 0)) {
-        if (tid == 0) out[tile] = ~0ull;
-        return;
-    }
-
-    // B operands of this target, built once per target by the commit
-    // kernel in the MFMA register layout: 16 contiguous bytes per lane.
+    const uint8_t *vr = d.vradp + (int64_t)(ty0 + 4 * g + kPadT) * pitch + (cx + kPadL);
+    uint32_t vv[kMfmaTilesPerWave * 4];
+#pragma unroll
+    for (int t = 0; t < kMfmaTilesPerWave; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vv[4 * t + i] = vr[(16 * t + i) * pitch];
     const MfmaFrags *fr = frag;
     v4i bc[P][2], bh[P], bl[P];
 #pragma unroll
@@ -122,6 +123,35 @@ __device__ __forceinline__ void search_tile_mfma(const JobDev &d, const MfmaFrag
         bl[dy] = *(const v4i *)fr->l[dy][lane];
         bh[dy] = *(const v4i *)fr->h[dy][lane];
     }
+
+    // ---- publish the tile; one barrier also tells whether any candidate
+    // of the tile is valid.
+#pragma unroll
+    for (int k = 0; k < G::AIT; ++k) {
+        const int i = min(tid + k * kSearchWaves * 64, G::NA - 1);
+        const int ly = i / G::QA, lq = i - ly * G::QA;
+        *(uint4 *)&L.a[ly * kMfmaStrideA + 4 * lq] = va[k];
+    }
+#pragma unroll
+    for (int k = 0; k < G::QIT; ++k) {
+        const int i = min(tid + k * kSearchWaves * 64, G::NQ - 1);
+        const int ly = i / G::QQ, lq = i - ly * G::QQ;
+        *(uint4 *)&L.q[ly * kMfmaStrideQ + 16 * lq] = vq[k];
+    }
+    uint32_t vmask = 0;
+    const bool colok = cx >= rx0 && cx < rx1;
+#pragma unroll
+    for (int t = 0; t < kMfmaTilesPerWave; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int y = ty0 + 16 * t + 4 * g + i;
+            if (colok && y < ry1 && vv[4 * t + i] >= (uint32_t)R) vmask |= 1u << (4 * t + i);
+        }
+    if (!__syncthreads_or(live && vmask != 0)) {
+        if (tid == 0 && live) out[tile] = ~0ull;
+        return;
+    }
+
     const int t2 = fr->t2p, kk = fr->k;
     const uint32_t rowmask = fr->rowmask;
 
@@ -174,13 +204,15 @@ template <int R>
 __global__ __launch_bounds__(kSearchWaves * 64) void k_search_mfma(JobDev d, int query, int rx0, int ry0, int rx1,
                                                                    int ry1, int ntx, int ntiles) {
     __shared__ MfmaLds<R> L;
-    if (!query) {
-        const IterState *st = d.st;
-        if (st->done || st->error || !st->pending || st->iter >= st->iter_limit) return;
-    }
     const int tile = xcd_band_tile((int)blockIdx.x, (int)gridDim.x);
     if (tile >= ntiles) return;
-    search_tile_mfma<R>(d, query ? d.qfrag : d.frag, rx0, ry0, rx1, ry1, ntx, tile, d.partials, L);
+    // read now, tested after the tile loads are issued
+    bool live = true;
+    if (!query) {
+        const IterState *st = d.st;
+        live = !(st->done || st->error || !st->pending || st->iter >= st->iter_limit);
+    }
+    search_tile_mfma<R>(d, query ? d.qfrag : d.frag, live, rx0, ry0, rx1, ry1, ntx, tile, d.partials, L);
 }
 
 template <int R>
@@ -198,22 +230,31 @@ hipError_t launch_mfma_t(const JobDev &d, bool query, int rx0, int ry0, int rx1,
     return hipGetLastError();
 }
 
-// Static source planes of the MFMA search, from the original image: offset
-// RGBX words and the |s'|^2 byte pair.  Only original known pixels are ever
-// read by a valid candidate, and those never change.
+// Static source planes of the MFMA search in the padded layout, from the
+// original image: offset RGBX words and the |s'|^2 byte pair (zero outside
+// the image).  Only original known pixels are ever read by a valid
+// candidate, and those never change.
 __global__ __launch_bounds__(256) void k_mfma_planes(JobDev d) {
-    const int64_t n = (int64_t)d.W * d.H;
+    const int pitch = d.pitch;
+    const int64_t n = (int64_t)pitch * padded_rows(d.H);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint32_t v = d.img[i];
-    d.srcw[i] = v ^ 0x80808080u;
-    d.srcq[i] = sq_bytes(v);
+    const int x = (int)(i % pitch) - kPadL, y = (int)(i / pitch) - kPadT;
+    uint32_t w = 0;
+    uint16_t q = 0;
+    if (x >= 0 && x < d.W && y >= 0 && y < d.H) {
+        const uint32_t v = d.img[(int64_t)y * d.W + x];
+        w = v ^ 0x80808080u;
+        q = sq_bytes(v);
+    }
+    d.srcw[i] = w;
+    d.srcq[i] = q;
 }
 
 }  // namespace
 
 hipError_t launch_mfma_planes(const JobDev &d, hipStream_t s) {
-    const int64_t n = (int64_t)d.W * d.H;
+    const int64_t n = (int64_t)d.pitch * padded_rows(d.H);
     hipLaunchKernelGGL(k_mfma_planes, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, d);
     return hipGetLastError();
 }

@@ -56,9 +56,11 @@ def test_library_loads_and_host_only_calls(so):
     f.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(inpaint_params), ctypes.POINTER(ctypes.c_uint64)]
     assert f(1920, 1080, ctypes.byref(p), ctypes.byref(b)) == 0
     n = 1920 * 1080
+    npad = ((8 + 1920 + 84 + 7) // 8 * 8) * (8 + 1080 + 72)
     # RGBX + gray + hole + validity + confidence + cached priority terms (C, D),
-    # plus small tables
-    assert 4 * n + 3 * n + 8 * n + 16 * n <= b.value < 4 * n + 3 * n + 8 * n + 16 * n + 2_000_000
+    # the padded static search planes (RGBX + validity), plus small tables
+    base = 4 * n + 3 * n + 8 * n + 16 * n + 5 * npad
+    assert base <= b.value < base + 2_000_000
     p.log_capacity = 1000
     b2 = ctypes.c_uint64()
     assert f(1920, 1080, ctypes.byref(p), ctypes.byref(b2)) == 0
