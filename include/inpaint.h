@@ -60,15 +60,20 @@ extern "C" {
 #define INPAINT_SEARCH_ALPHA 1   /* window around the hole, Eq. 6            */
 #define INPAINT_SEARCH_RECT  2   /* caller-given rectangle of centres        */
 
-/* Execution forms of inpaint_run.  Every form runs the same two kernels per
- * iteration (exemplar search, then commit); they differ in how the host
- * drives them.  Kernels skip their work once the hole is empty or the
+/* Execution forms of inpaint_run.  PLAIN, STREAM and GRAPH run the same two
+ * kernels per iteration (exemplar search, then commit) and differ in how the
+ * host drives them; kernels skip their work once the hole is empty or the
  * iteration limit is reached, so overshooting a batch of iterations is
- * harmless. */
+ * harmless.  PERSISTENT runs up to iters_per_check whole iterations inside
+ * one cooperative dispatch: one work-group commits while the others keep
+ * their search tiles resident in LDS and score every target in turn, with
+ * no kernel boundary between search and commit.  It needs every tile's
+ * work-group co-resident (and the SIMT path with tile_rows 8); otherwise
+ * inpaint_run uses STREAM instead -- inpaint_run_form tells which. */
 #define INPAINT_FORM_PLAIN  0    /* launch one iteration, host check, repeat  */
 #define INPAINT_FORM_STREAM 1    /* enqueue iters_per_check iterations, check */
 #define INPAINT_FORM_GRAPH  2    /* replay a hipGraph of iters_per_check      */
-                                 /*   iterations, check                       */
+#define INPAINT_FORM_PERSISTENT 3 /* one dispatch of iters_per_check, check  */
 
 #define INPAINT_PATH_AUTO 0
 #define INPAINT_PATH_SIMT 1      /* integer dot-product SSD on the VALU      */
@@ -205,6 +210,13 @@ int32_t inpaint_search_info(const inpaint_ctx *ctx, inpaint_rect *rect, int64_t 
  * INVALID_ARGUMENT while timing is on. */
 int32_t inpaint_profile_search(inpaint_ctx *ctx, int32_t enable);
 int32_t inpaint_search_time(inpaint_ctx *ctx, double *total_ms, int64_t *searches);
+
+/* The execution form inpaint_run uses for this context: params.form, except
+ * that PERSISTENT becomes STREAM when its work-groups cannot all be
+ * co-resident.  In the PERSISTENT form the timing above brackets each whole
+ * dispatch (search and commit of up to iters_per_check iterations) and
+ * `searches` counts dispatches. */
+int32_t inpaint_run_form(const inpaint_ctx *ctx, int32_t *form);
 
 /* Releases the context (not the caller's workspace).  Waits for its work. */
 int32_t inpaint_destroy(inpaint_ctx *ctx);

@@ -21,8 +21,9 @@ OK, DONE = 0, 1
 INVALID_ARGUMENT, NO_CANDIDATE, OUT_OF_MEMORY, DEVICE = -1, -2, -3, -4
 SEARCH_FULL, SEARCH_ALPHA, SEARCH_RECT = 0, 1, 2
 PATH_AUTO, PATH_SIMT, PATH_MFMA = 0, 1, 2
-FORM_PLAIN, FORM_STREAM, FORM_GRAPH = 0, 1, 2
-FORMS = {"plain": FORM_PLAIN, "stream": FORM_STREAM, "graph": FORM_GRAPH}
+FORM_PLAIN, FORM_STREAM, FORM_GRAPH, FORM_PERSISTENT = 0, 1, 2, 3
+FORMS = {"plain": FORM_PLAIN, "stream": FORM_STREAM, "graph": FORM_GRAPH, "persistent": FORM_PERSISTENT}
+FORM_NAMES = {v: k for k, v in FORMS.items()}
 
 
 class inpaint_image(ctypes.Structure):
@@ -86,6 +87,7 @@ def lib() -> ctypes.CDLL:
         "inpaint_batch_status": (i32, [vp, i32, P(i32)]),
         "inpaint_profile_search": (i32, [vp, i32]),
         "inpaint_search_time": (i32, [vp, P(ctypes.c_double), P(i64)]),
+        "inpaint_run_form": (i32, [vp, P(i32)]),
         "inpaint_destroy": (i32, [vp]),
         "inpaint_status_string": (ctypes.c_char_p, [i32]),
         "inpaint_last_error": (ctypes.c_char_p, [vp]),
@@ -256,6 +258,12 @@ class Inpainter:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         self._check(lib().inpaint_search_time(self.ctx, ctypes.byref(ms), ctypes.byref(n)), "inpaint_search_time")
         return ms.value, n.value
+
+    def run_form(self) -> str:
+        """The execution form inpaint_run uses ("persistent" may become "stream")."""
+        f = ctypes.c_int32()
+        self._check(lib().inpaint_run_form(self.ctx, ctypes.byref(f)), "inpaint_run_form")
+        return FORM_NAMES[f.value]
 
     def search_info(self):
         rc, n = inpaint_rect(), ctypes.c_int64()

@@ -15,7 +15,7 @@
 // and from the LDS copy of the neighbourhood (per iteration).
 #pragma clang fp contract(off)
 
-#include "inpaint_dev.h"
+#include "search_tile.h"
 
 namespace inpaint {
 
@@ -263,7 +263,31 @@ __device__ int64_t block_sum_i64(int64_t v, int64_t *sh) {
     return v;
 }
 
+// State of the fill loop at the start of an iteration.
+struct Snap {
+    int64_t iter, limit, remaining, p;
+    double C, D, Pr;
+    int32_t done, err, pending, k;
+};
+
+__device__ __forceinline__ Snap load_snap(const IterState *st, const TargetStage *tg) {
+    Snap v;
+    v.iter = st->iter;
+    v.limit = st->iter_limit;
+    v.remaining = st->remaining;
+    v.p = st->p_idx;
+    v.C = st->C;
+    v.D = st->D;
+    v.Pr = st->Pr;
+    v.done = st->done;
+    v.err = st->error;
+    v.pending = st->pending;
+    v.k = tg->k;
+    return v;
+}
+
 struct Scratch {
+    Snap snap;           // loop state broadcast by thread 0
     int64_t k[16];
     int64_t i[16];
     uint64_t u[16];
@@ -355,6 +379,46 @@ __device__ void write_mask_bits(Scratch &s, int P, TargetStage *tg) {
     }
 }
 
+// Persistent fill: writes the target just staged (s.tp and the mask words,
+// published by the staging barriers) into every record of the handshake,
+// go words excluded.
+__device__ void write_records(FillSync *sy, const Scratch &s, int P, int kk, uint32_t t2) {
+    const int n = P * P, mw = (n + 31) / 32;
+    for (int i = threadIdx.x; i < kGoCopies * n; i += blockDim.x) {
+        const int c = i / n, t = i - c * n;
+        sy->rec[c].tpix[t] = s.tp[t];
+    }
+    for (int i = threadIdx.x; i < kGoCopies * mw; i += blockDim.x) {
+        const int c = i / mw, w = i - c * mw;
+        sy->rec[c].mbits[w] = s.mbits[w];
+        sy->rec[c].sbits[w] = s.sbits[w];
+        sy->rec[c].ebits[w] = s.ebits[w];
+    }
+    if (threadIdx.x < kGoCopies) {
+        sy->rec[threadIdx.x].t2 = t2;
+        sy->rec[threadIdx.x].k = (uint32_t)kk;
+    }
+}
+
+// The same from a target staged by an earlier dispatch.
+__device__ void write_records(FillSync *sy, const TargetStage *tg, int P) {
+    const int n = P * P, mw = (n + 31) / 32;
+    for (int i = threadIdx.x; i < kGoCopies * n; i += blockDim.x) {
+        const int c = i / n, t = i - c * n;
+        sy->rec[c].tpix[t] = tg->tpix[t];
+    }
+    for (int i = threadIdx.x; i < kGoCopies * mw; i += blockDim.x) {
+        const int c = i / mw, w = i - c * mw;
+        sy->rec[c].mbits[w] = tg->mbits[w];
+        sy->rec[c].sbits[w] = tg->sbits[w];
+        sy->rec[c].ebits[w] = tg->ebits[w];
+    }
+    if (threadIdx.x < kGoCopies) {
+        sy->rec[threadIdx.x].t2 = tg->t2;
+        sy->rec[threadIdx.x].k = (uint32_t)tg->k;
+    }
+}
+
 __device__ __forceinline__ void wave_argmax(int64_t &key, int64_t &idx) {
     for (int off = 32; off > 0; off >>= 1) {
         const int64_t k2 = __shfl_xor(key, off);
@@ -385,8 +449,8 @@ __device__ void refresh_block_wave(const JobDev &d, int bx, int by) {
 // Stages the target patch at (tx, ty) with radius r into *tg: known mask,
 // RGBX words and T2 = sum of squared known target values, in column-major
 // slot order (dx + r) * P + (dy + r).
-__device__ void stage_target(const JobDev &d, int tx, int ty, int r, TargetStage *tg, Scratch &s,
-                             MfmaFrags *frag) {
+__device__ int stage_target(const JobDev &d, int tx, int ty, int r, TargetStage *tg, Scratch &s,
+                            MfmaFrags *frag, FillSync *recs = nullptr) {
     const int P = 2 * r + 1;
     const GlobalView v{d};
     if (threadIdx.x < 16) {
@@ -423,6 +487,8 @@ __device__ void stage_target(const JobDev &d, int tx, int ty, int r, TargetStage
         tg->t2 = (uint32_t)t2;
     }
     if (frag) build_mfma_frags(r, s, frag);
+    if (recs) write_records(recs, s, P, (int)kk, (uint32_t)t2);
+    return (int)kk;
 }
 
 // Argmax over the priority blocks, then stages the winner as the next target.
@@ -561,8 +627,8 @@ __device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, 
 // Stages the next target (nx, ny) from the LDS neighbourhood of the filled
 // target (px, py); valid when the whole patch lies inside it.
 template <int R>
-__device__ __forceinline__ void stage_target_lds(const LdsStage<R> &L, int px, int py, int tx, int ty, TargetStage *tg,
-                                                 Scratch &s, MfmaFrags *frag) {
+__device__ __forceinline__ int stage_target_lds(const LdsStage<R> &L, int px, int py, int tx, int ty, TargetStage *tg,
+                                                Scratch &s, MfmaFrags *frag, FillSync *recs = nullptr) {
     using S = Stage<R>;
     constexpr int P = 2 * R + 1;
     if (threadIdx.x < 16) {
@@ -599,6 +665,8 @@ __device__ __forceinline__ void stage_target_lds(const LdsStage<R> &L, int px, i
         tg->t2 = (uint32_t)t2;
     }
     if (frag) build_mfma_frags(R, s, frag);
+    if (recs) write_records(recs, s, P, (int)kk, (uint32_t)t2);
+    return (int)kk;
 }
 
 }  // namespace
@@ -752,14 +820,14 @@ __global__ __launch_bounds__(256) void k_prio_init(JobDev d) {
 // trip.  Leaves the neighbourhood and the block keys in LDS, the running
 // argmax over the untouched blocks in (key, idx), and returns the minimum
 // search key of this thread's partials.
-template <int R>
+template <int R, bool PARTIALS>
 __device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, LdsStage<R> &L, int64_t &key,
                            int64_t &idx) {
     using S = Stage<R>;
     constexpr int T = kCommitThreads;
     constexpr int NIT = (S::n + T - 1) / T;
     constexpr int KIT = (LdsStage<R>::NBA * LdsStage<R>::NBA * 64 + T - 1) / T;
-    constexpr int BIT = 16, PIT = 8;
+    constexpr int BIT = PARTIALS ? 16 : 8, PIT = PARTIALS ? 8 : 0;
     const int ox = px - S::half, oy = py - S::half;
     const int nkeys = g.nabx * g.naby * 64;
     const int bw = d.pbx1 - d.pbx0, nb = bw * (d.pby1 - d.pby0);
@@ -771,7 +839,7 @@ __device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, Ld
     uint32_t im[NIT];
     double2 cd[KIT];
     BlockBest bb[BIT];
-    uint64_t pv[PIT];
+    uint64_t pv[PIT > 0 ? PIT : 1];
     // ---- issue (all unconditional, from clamped addresses)
 #pragma unroll
     for (int k = 0; k < NIT; ++k) {
@@ -798,6 +866,7 @@ __device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, Ld
     }
 #pragma unroll
     for (int k = 0; k < PIT; ++k) pv[k] = d.partials[min(tid + k * T, ntiles - 1)];
+    (void)pv;
 
     // ---- consume
 #pragma unroll
@@ -837,47 +906,35 @@ __device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, Ld
 
     // ---- tails of very large holes / rectangles
     for (int t = tid + BIT * T; t < nb; t += T) take_block(t, d.blk[(d.pby0 + t / bw) * d.nbw + d.pbx0 + t % bw]);
-    for (int t = tid + PIT * T; t < ntiles; t += T) best = d.partials[t] < best ? d.partials[t] : best;
+    if (PARTIALS)
+        for (int t = tid + PIT * T; t < ntiles; t += T) best = d.partials[t] < best ? d.partials[t] : best;
     return best;
 }
 
-// One fill iteration after the search: reduce the search partials, copy the
+// The part of a fill iteration that needs the search result `best`: copy the
 // source patch into the target's hole pixels (they take the target's
 // confidence), log, refresh priorities near the patch, select and stage the
-// next target.  With no staged target (right after create) it only selects
-// and stages.
+// next target.  (key, idx) is the running argmax over the untouched blocks
+// from gather(), whose LDS neighbourhood it consumes.  Thread 0 writes the
+// new loop state to *out; the caller publishes it with a barrier.
 //
-// Latency is the cost here, so every global load that does not depend on
-// the search result is issued at once up front: the search partials, the
-// target's neighbourhood (into LDS), the cached keys of the 8x8 blocks the
-// refresh touches, and the argmax over all other blocks.  After the copy the
-// rest runs out of LDS; the next target is staged from LDS when its patch
-// lies inside the staged neighbourhood (the common case: the front moves
-// locally).
+// After the copy everything runs out of LDS; the next target is staged from
+// LDS when its patch lies inside the staged neighbourhood (the common case:
+// the front moves locally).
 template <int R>
-__device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L) {
+__device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const Snap &v, uint64_t best,
+                              const Refresh &g, int64_t key, int64_t idx, Snap *out, FillSync *recs = nullptr) {
     IterState *st = d.st;
-    const int done = st->done, err = st->error, pending = st->pending;
-    const int64_t iter = st->iter, limit = st->iter_limit, rem0 = st->remaining, p = st->p_idx;
-    const double C = st->C, D = st->D, Pr = st->Pr;
-    if (done || err) return;
-    if (!pending) {
-        select_and_stage(d, s);
-        return;
-    }
-    if (iter >= limit) return;
     constexpr int P = 2 * R + 1;
     const int W = d.W;
-    const int px = (int)(p % W), py = (int)(p / W);
-    const int known_k = d.tgt->k;
-    const Refresh g = refresh_geometry<R>(d, px, py);
-
-    // ---- independent loads
-    int64_t key = -1, idx = INT64_MAX;
-    uint64_t best = gather<R>(d, px, py, g, L, key, idx);
-    best = block_min_u64(best, s.u);   // its barriers also publish the LDS stores
+    const int px = (int)(v.p % W), py = (int)(v.p / W);
+    Snap n = v;
     if (best == ~0ull) {
-        if (threadIdx.x == 0) st->error = INPAINT_NO_CANDIDATE;
+        if (threadIdx.x == 0) {
+            st->error = INPAINT_NO_CANDIDATE;
+            n.err = INPAINT_NO_CANDIDATE;
+            *out = n;
+        }
         return;
     }
 
@@ -895,37 +952,44 @@ __device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L) {
             const uint8_t gv = d.gray[src];
             d.img[dst] = pix;
             d.gray[dst] = gv;
-            d.conf[dst] = C;
+            d.conf[dst] = v.C;
             d.hole[dst] = 0;
             L.st[li] = 0;
             L.img[li] = pix;
             L.gray[li] = gv;
-            L.conf[li] = C;
+            L.conf[li] = v.C;
             filled += 1;
         }
     }
     filled = block_sum_i64(filled, s.k);
-    const int64_t remaining = rem0 - filled;
+    const int64_t remaining = v.remaining - filled;
     if (threadIdx.x == 0) {
         StepRec rec;
-        rec.target_index = p;
+        rec.target_index = v.p;
         rec.source_index = q;
         rec.ssd = ssd;
-        rec.known_k = known_k;
+        rec.known_k = v.k;
         rec.n_filled = (int32_t)filled;
         rec.reserved = 0;
-        rec.priority = Pr;
-        rec.confidence = C;
-        rec.data_term = D;
+        rec.priority = v.Pr;
+        rec.confidence = v.C;
+        rec.data_term = v.D;
         rec.remaining = remaining;
-        if (iter < d.log_cap) d.log[iter] = rec;
+        if (v.iter < d.log_cap) d.log[v.iter] = rec;
         st->last = rec;
         st->remaining = remaining;
-        st->iter = iter + 1;
+        st->iter = v.iter + 1;
         st->pending = 0;
         if (remaining == 0) st->done = 1;
+        n.iter = v.iter + 1;
+        n.remaining = remaining;
+        n.pending = 0;
+        n.done = remaining == 0 ? 1 : 0;
     }
-    if (remaining == 0) return;
+    if (remaining == 0) {
+        if (threadIdx.x == 0) *out = n;
+        return;
+    }
 
     // ---- priorities near the patch, block maxima, argmax
     refresh_near<R>(d, px, py, g, L, key, idx);
@@ -933,17 +997,22 @@ __device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L) {
     if (key < 0) {
         // No front pixel although the hole is not empty: cannot happen for a
         // valid state; flag it instead of looping.
-        if (threadIdx.x == 0) st->error = INPAINT_DEVICE;
+        if (threadIdx.x == 0) {
+            st->error = INPAINT_DEVICE;
+            n.err = INPAINT_DEVICE;
+            *out = n;
+        }
         return;
     }
 
     // ---- stage the next target
     const int tx = (int)(idx % W), ty = (int)(idx / W);
     const int adx = abs(tx - px), ady = abs(ty - py);
+    int kk;
     if (adx <= 2 * R + 2 && ady <= 2 * R + 2)
-        stage_target_lds<R>(L, px, py, tx, ty, d.tgt, s, d.mfma ? d.frag : nullptr);
+        kk = stage_target_lds<R>(L, px, py, tx, ty, d.tgt, s, d.mfma ? d.frag : nullptr, recs);
     else
-        stage_target(d, tx, ty, R, d.tgt, s, d.mfma ? d.frag : nullptr);
+        kk = stage_target(d, tx, ty, R, d.tgt, s, d.mfma ? d.frag : nullptr, recs);
     if (threadIdx.x == 0) {
         double2 cd;
         if (adx <= 2 * R + 1 && ady <= 2 * R + 1)
@@ -955,7 +1024,242 @@ __device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L) {
         st->D = cd.y;
         st->Pr = cd.x * cd.y;
         st->pending = 1;
+        n.p = idx;
+        n.C = cd.x;
+        n.D = cd.y;
+        n.Pr = cd.x * cd.y;
+        n.pending = 1;
+        n.k = kk;
+        *out = n;
     }
+}
+
+// One fill iteration after the search: reduce the search partials and
+// finish.  With no staged target (right after create) it only selects and
+// stages.  Latency is the cost here, so every global load that does not
+// depend on the search result is issued at once up front (gather).
+template <int R>
+__device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L) {
+    const Snap v = load_snap(d.st, d.tgt);
+    if (v.done || v.err) return;
+    if (!v.pending) {
+        select_and_stage(d, s);
+        return;
+    }
+    if (v.iter >= v.limit) return;
+    const int px = (int)(v.p % d.W), py = (int)(v.p / d.W);
+    const Refresh g = refresh_geometry<R>(d, px, py);
+    int64_t key = -1, idx = INT64_MAX;
+    uint64_t best = gather<R, true>(d, px, py, g, L, key, idx);
+    best = block_min_u64(best, s.u);   // its barriers also publish the LDS stores
+    commit_finish<R>(d, s, L, v, best, g, key, idx, &s.snap);
+}
+
+// ---- persistent fill: one cooperative dispatch runs many iterations ------
+//
+// Work-group 0 commits; work-group 1 + t owns search tile t for the whole
+// dispatch, staged in LDS once (its source pixels never change).  Per
+// iteration k: the committer publishes go = (epoch, k + 1) once target k is
+// staged; every search group copies the target to LDS, scores its tile and
+// writes its minimum key, tagged with k, to its own slot; meanwhile the committer
+// issues the search-independent loads of the commit (gather).  When every
+// slot carries iteration k's tag it reduces the keys and finishes the
+// iteration.  go carries the launch epoch, so values left by an earlier
+// dispatch never match.  Every wait is bounded: a search group gives up
+// after kSpinLimit polls; the committer then flags a device error and
+// publishes stop, and every group exits.
+
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ uint64_t go_word(uint32_t epoch, uint32_t v) { return ((uint64_t)epoch << 32) | v; }
+
+// Thread 0 of search group t: 1 once target k is staged, 0 on stop or time-out.
+__device__ int wait_go(const FillSync *sy, int t, uint32_t epoch, uint32_t k) {
+    const uint64_t want = go_word(epoch, k + 1), stop = go_word(epoch, 0xffffffffu);
+    const uint64_t *g = &sy->rec[t % kGoCopies].go;
+    for (uint32_t spin = 0; spin < kSpinLimit; ++spin) {
+        const uint64_t v = __hip_atomic_load(g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v == want) return 1;
+        if (v == stop) return 0;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return 0;
+}
+
+// Committer (all threads, after a barrier): writes every copy of the go word.
+__device__ __forceinline__ void publish_go(FillSync *sy, uint64_t word) {
+    if (threadIdx.x < kGoCopies)
+        __hip_atomic_store(&sy->rec[threadIdx.x].go, word, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t slot_tag(uint32_t k) { return k % 255u + 1u; }
+
+__device__ __forceinline__ uint64_t slot_word(uint64_t key, uint32_t tag) {
+    if (key == ~0ull) return (~0ull << 8) | tag;
+    const uint64_t ssd = key >> 32, idx = key & 0xffffffffu;
+    return (ssd << (kSlotIndexBits + 8)) | (idx << 8) | tag;
+}
+
+// Committer (all threads): waits until every search slot carries `tag`, then
+// returns the minimum search key (block-wide, ~0 if no tile had a valid
+// candidate), or sets *ok = 0 on time-out.  Each slot word is self-contained,
+// so plain device-scope loads suffice (no acquire, no cache invalidation).
+__device__ uint64_t collect_slots(const uint64_t *fs, int ntiles, uint32_t tag, Scratch &s, int *ok) {
+    constexpr int T = kCommitThreads;
+    const int per = (ntiles + T - 1) / T;           // slots of this thread: tid + T j
+    uint32_t pend = 0;
+    for (int j = 0; j < per && j < 32; ++j)
+        if ((int)threadIdx.x + T * j < ntiles) pend |= 1u << j;
+    uint64_t best = ~0ull;   // minimum of (word >> 8)
+    int done = 0;
+    for (uint32_t spin = 0; spin < kSpinLimit; ++spin) {
+        for (uint32_t m = pend; m; m &= m - 1) {
+            const int j = __builtin_ctz(m);
+            const uint64_t w = __hip_atomic_load(&fs[threadIdx.x + T * j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((w & 255u) == tag) {
+                pend &= ~(1u << j);
+                best = (w >> 8) < best ? (w >> 8) : best;
+            }
+        }
+        if (!__syncthreads_or(pend != 0)) {
+            done = 1;
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    *ok = done;
+    if (!done) return ~0ull;
+    best = block_min_u64(best, s.u);
+    const uint64_t ssd = best >> kSlotIndexBits, idx = best & ((1ull << kSlotIndexBits) - 1);
+    if (ssd == (1ull << 26) - 1) return ~0ull;
+    return (ssd << 32) | idx;
+}
+
+template <int R>
+struct CommitLds {
+    Scratch s;
+    LdsStage<R> L;
+};
+
+template <int R, int NY>
+struct SearchLds {
+    __attribute__((aligned(16))) uint32_t tile[tile::TileGeom<R, NY>::LDS_WORDS];
+    tile::TargetLds tgt;
+    uint64_t red[kSearchWaves];
+    int32_t flag;
+};
+
+template <int R, int NY>
+union FillLds {
+    CommitLds<R> c;
+    SearchLds<R, NY> s;
+};
+
+template <int R>
+__device__ void fill_commit(const JobDev &d, int ntiles, int n_iters, uint32_t epoch, CommitLds<R> &C) {
+    Scratch &s = C.s;
+    LdsStage<R> &L = C.L;
+    FillSync *sy = d.sync;
+    if (threadIdx.x == 0) s.snap = load_snap(d.st, d.tgt);
+    __syncthreads();
+    Snap v = s.snap;
+    if (!v.done && !v.err && !v.pending) {   // nothing staged yet
+        select_and_stage(d, s);
+        __syncthreads();
+        if (threadIdx.x == 0) s.snap = load_snap(d.st, d.tgt);   // this thread's own writes
+        __syncthreads();
+        v = s.snap;
+    }
+    if (!v.done && !v.err && v.pending) write_records(sy, d.tgt, 2 * R + 1);
+    for (int i = threadIdx.x; i < ntiles; i += blockDim.x)
+        __hip_atomic_store(&d.fslot[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t k = 0;; ++k) {
+        const bool stop = v.done || v.err || !v.pending || v.iter >= v.limit || (int)k >= n_iters;
+        // Every wave's writes (records, state, slot resets) reach device
+        // scope before go.  (Release only: nothing this group reads is
+        // written by another group except through device-scope loads.)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        publish_go(sy, go_word(epoch, stop ? 0xffffffffu : k + 1));
+        if (stop) break;
+
+        // search-independent loads of the commit, overlapping the search
+        const int px = (int)(v.p % d.W), py = (int)(v.p / d.W);
+        const Refresh g = refresh_geometry<R>(d, px, py);
+        int64_t key = -1, idx = INT64_MAX;
+        gather<R, false>(d, px, py, g, L, key, idx);
+
+        // (its barriers also publish the gathered LDS neighbourhood)
+        int ok = 0;
+        const uint64_t best = collect_slots(d.fslot, ntiles, slot_tag(k), s, &ok);
+        if (!ok) {
+            if (threadIdx.x == 0) d.st->error = INPAINT_DEVICE;
+            v.err = INPAINT_DEVICE;
+            continue;      // publishes stop
+        }
+        commit_finish<R>(d, s, L, v, best, g, key, idx, &s.snap, sy);
+        __syncthreads();
+        v = s.snap;
+    }
+}
+
+// Copies record `rec` (published by the go word just observed) into LDS.
+// Every word is read with a device-scope load, which bypasses the caches
+// that could hold an older copy; the committer wrote the record back before
+// its release of the go word, and these loads issue after that word was
+// seen.  So no cache invalidation (an agent-scope acquire) is needed here,
+// which would otherwise run once per work-group per iteration.
+template <int R>
+__device__ __forceinline__ void load_record(const FillRec *rec, tile::TargetLds *t) {
+    constexpr int P = 2 * R + 1, MW = (P * P + 31) / 32;
+    for (int i = threadIdx.x; i < P * P; i += blockDim.x)
+        t->tpix[i] = __hip_atomic_load(&rec->tpix[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < MW) {
+        t->mbits[threadIdx.x] = __hip_atomic_load(&rec->mbits[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t->sbits[threadIdx.x] = __hip_atomic_load(&rec->sbits[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t->ebits[threadIdx.x] = __hip_atomic_load(&rec->ebits[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x == 0) t->t2 = __hip_atomic_load(&rec->t2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int R, int NY>
+__device__ void fill_search(const JobDev &d, int ntiles, uint32_t epoch, SearchLds<R, NY> &S) {
+    // The tile stays in this group's LDS for the whole dispatch, so the
+    // order of tiles over the XCDs does not matter here.
+    const int t = (int)blockIdx.x - 1;
+    int tx0, ty0;
+    tile::tile_origin<R, NY>(d.rx0, d.ry0, d.ntx, t, &tx0, &ty0);
+    const uint32_t vmask = tile::stage_tile<R, NY>(d, tx0, ty0, d.rx1, d.ry1, S.tile);
+    const bool anyv = __syncthreads_or(vmask != 0);
+    FillSync *sy = d.sync;
+    for (uint32_t k = 0;; ++k) {
+        if (threadIdx.x == 0) S.flag = wait_go(sy, t, epoch, k);
+        __syncthreads();
+        if (!S.flag) break;
+        uint64_t best = ~0ull;
+        if (anyv) {
+            load_record<R>(&sy->rec[t % kGoCopies], &S.tgt);
+            __syncthreads();
+            const tile::LdsTarget view{&S.tgt};
+            best = tile::wave_min_u64(tile::score_tile<R, NY>(d, view, tx0, ty0, vmask, S.tile));
+            if ((threadIdx.x & 63) == 0) S.red[threadIdx.x >> 6] = best;
+            __syncthreads();
+            if (threadIdx.x == 0)
+                for (int w = 0; w < kSearchWaves; ++w) best = S.red[w] < best ? S.red[w] : best;
+        }
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&d.fslot[t], slot_word(best, slot_tag(k)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fill(JobDev d, int ntiles, int n_iters, uint32_t epoch) {
+    __shared__ FillLds<R, kFillTileRows> lds;
+    if (blockIdx.x == 0)
+        fill_commit<R>(d, ntiles, n_iters, epoch, lds.c);
+    else
+        fill_search<R, kFillTileRows>(d, ntiles, epoch, lds.s);
 }
 
 template <int R>
@@ -1073,6 +1377,36 @@ hipError_t launch_commit_batched(const JobDev *slots, const int32_t *ids, const 
     INPAINT_RADIUS_SWITCH(r, CALL)
 #undef CALL
     return hipGetLastError();
+}
+
+static const void *fill_kernel(int r) {
+    switch (r) {
+        case 1: return (const void *)k_fill<1>;
+        case 2: return (const void *)k_fill<2>;
+        case 3: return (const void *)k_fill<3>;
+        case 4: return (const void *)k_fill<4>;
+        case 5: return (const void *)k_fill<5>;
+        case 6: return (const void *)k_fill<6>;
+        case 7: return (const void *)k_fill<7>;
+        case 8: return (const void *)k_fill<8>;
+        default: return nullptr;
+    }
+}
+
+hipError_t fill_blocks_per_cu(int r, int *blocks) {
+    const void *f = fill_kernel(r);
+    if (!f) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, kCommitThreads, 0);
+}
+
+int fill_grid(int ntiles) { return 1 + ntiles; }
+
+hipError_t launch_fill(const JobDev &d, int ntiles, int n_iters, uint32_t epoch, hipStream_t s) {
+    const void *f = fill_kernel(d.r);
+    if (!f) return hipErrorInvalidValue;
+    JobDev dd = d;
+    void *args[] = {&dd, &ntiles, &n_iters, &epoch};
+    return hipLaunchCooperativeKernel(f, dim3(fill_grid(ntiles)), dim3(kCommitThreads), args, 0, s);
 }
 
 hipError_t launch_stage_query(const JobDev &d, int tx, int ty, int r, hipStream_t s) {

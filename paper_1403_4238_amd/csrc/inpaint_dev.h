@@ -19,6 +19,7 @@ constexpr int kSearchWaves = 4;                        // waves per search work-
 constexpr int kCommitThreads = 256;   // one work-group per image; 512 VGPRs per thread
 constexpr int kMfmaMaxRadius = 6;     // int8-MFMA search: patches up to 13x13
 constexpr int kMfmaTileRows = 16;     // MFMA search tile: 64 x 64 candidates
+constexpr int kFillTileRows = 8;      // persistent fill: candidate rows per search thread
 
 // Padding of the static search planes (srcp, vradp, srcw, srcq) around the
 // image, in pixels: every staged search window -- a tile of up to 64 x 64
@@ -92,6 +93,30 @@ struct alignas(256) IterState {
     StepRec last;        // record of the last committed iteration
 };
 
+// Handshake of the persistent fill kernel (one per job).  The committer
+// publishes each staged target in kGoCopies identical records, each with a
+// go word: (epoch << 32) | (k + 1) once target k of the dispatch is staged,
+// (epoch << 32) | 0xffffffff to stop.  Search work-group t polls and reads
+// record t % kGoCopies, so a thousand work-groups do not all hit the same
+// lines; each reports in its own slot word, so no address takes more than
+// one writer.
+constexpr int kGoCopies = 32;
+struct alignas(256) FillRec {
+    uint64_t go;
+    uint32_t t2, k;
+    uint32_t mbits[kMaskWords], sbits[kMaskWords], ebits[kMaskWords];
+    uint32_t tpix[kMaxOffsets];
+};
+struct FillSync {
+    FillRec rec[kGoCopies];
+};
+// Slot word of a search work-group: its minimum key for one iteration and
+// the iteration's tag in one 64-bit word (so one plain device-scope store
+// publishes both): bits 38..63 SSD, 8..37 raster index, 0..7 tag
+// (k mod 255) + 1, 0 = not reported.  A tile with no valid candidate
+// reports SSD and index all ones.  Needs SSD < 2^26 (true for P <= 17) and
+// images below 2^30 pixels.
+constexpr int kSlotIndexBits = 30;
 // Per-block maximum of the priority keys: larger key wins, ties go to the
 // lower raster index.  key = bit pattern of the (non-negative) priority
 // P = C * D for front pixels, -1 elsewhere.
@@ -126,6 +151,8 @@ struct JobDev {
     MfmaFrags *frag;     // MFMA B operands of tgt (when mfma)
     MfmaFrags *qfrag;    // MFMA B operands of qtgt (when mfma)
     IterState *st;
+    FillSync *sync;
+    uint64_t *fslot;     // one slot word per search tile
     StepRec *log;
     InitInfo *info;
     int32_t W, H, r, log_cap;
@@ -166,6 +193,11 @@ hipError_t launch_commit_batched(const JobDev *slots, const int32_t *ids, const 
 hipError_t launch_count_active(const JobDev *slots, int nslots, int64_t *out, int32_t *status, hipStream_t s);
 hipError_t launch_search_batched(const JobDev *slots, const WorkItem *items, const int32_t *nitems,
                                  int r, int tile_rows, int grid, hipStream_t s);
+// Persistent fill (cooperative): runs up to n_iters iterations of the job in
+// one dispatch; needs fill_grid(ntiles) co-resident work-groups.
+hipError_t fill_blocks_per_cu(int r, int *blocks);
+int fill_grid(int ntiles);
+hipError_t launch_fill(const JobDev &d, int ntiles, int n_iters, uint32_t epoch, hipStream_t s);
 
 inline int search_tile_h(int tile_rows) { return kSearchWaves * tile_rows; }
 

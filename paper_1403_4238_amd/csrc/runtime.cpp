@@ -31,8 +31,8 @@ constexpr int kDefaultTileRows = 8;
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t img, gray, hole, vrad, conf, pcd, blk, partials, tgt, qtgt, frag, qfrag, srcw, srcq, srcp, vradp, st, info,
-        key, log, total;
+    uint64_t img, gray, hole, vrad, conf, pcd, blk, partials, tgt, qtgt, frag, qfrag, srcw, srcq, srcp, vradp, st, sync,
+        fslot, info, key, log, total;
     int64_t log_cap;
     int max_tiles;
 };
@@ -74,6 +74,8 @@ Layout make_layout(int W, int H, const inpaint_params &p) {
     L.srcp = take(4 * np);
     L.vradp = take(np);
     L.st = take(sizeof(IterState));
+    L.sync = take(sizeof(FillSync));
+    L.fslot = take(8 * (uint64_t)L.max_tiles);
     L.info = take(sizeof(InitInfo));
     L.key = take(8);
     L.log_cap = log_capacity(W, H, p);
@@ -120,6 +122,8 @@ struct inpaint_ctx {
     int64_t candidates = 0;
     inpaint_rect rect{};      // image-clipped search rect (reported)
     bool mfma = false;        // search on the matrix cores
+    int32_t run_form = INPAINT_FORM_PLAIN;   // form inpaint_run uses
+    uint32_t epoch = 0;       // persistent dispatches so far
     int32_t sticky = 0;
     std::string err;
     IterState *h_state = nullptr;   // pinned mirror of the device state
@@ -203,7 +207,7 @@ static int32_t check_params(int32_t W, int32_t H, const inpaint_params *p, std::
         *why = "unknown path";
         return INPAINT_INVALID_ARGUMENT;
     }
-    if (p->form < INPAINT_FORM_PLAIN || p->form > INPAINT_FORM_GRAPH) {
+    if (p->form < INPAINT_FORM_PLAIN || p->form > INPAINT_FORM_PERSISTENT) {
         *why = "unknown form";
         return INPAINT_INVALID_ARGUMENT;
     }
@@ -233,6 +237,23 @@ static int32_t check_params(int32_t W, int32_t H, const inpaint_params *p, std::
             return INPAINT_INVALID_ARGUMENT;
         }
     return INPAINT_OK;
+}
+
+// Whether the persistent fill can run this job: SIMT search with its tile
+// shape, a device with cooperative launch, and every work-group of the
+// dispatch co-resident.
+static bool persistent_fits(const inpaint_ctx *c) {
+    const JobDev &d = c->d;
+    const int ntiles = d.ntx * d.nty;
+    // (the committer scans at most 32 slots per thread)
+    if (c->mfma || d.tile_rows != kFillTileRows || ntiles <= 0 || ntiles > 32 * kCommitThreads) return false;
+    if ((int64_t)d.W * d.H > (1ll << kSlotIndexBits)) return false;   // slot word index field
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
+    if (fill_blocks_per_cu(d.r, &per_cu) != hipSuccess) return false;
+    return (int64_t)fill_grid(ntiles) <= (int64_t)per_cu * cus;
 }
 
 int32_t inpaint_workspace_bytes(int32_t W, int32_t H, const inpaint_params *p, uint64_t *bytes) {
@@ -327,6 +348,8 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     d.vradp = ws + L.vradp;
     d.pitch = padded_pitch(W);
     d.st = (IterState *)(ws + L.st);
+    d.sync = (FillSync *)(ws + L.sync);
+    d.fslot = (uint64_t *)(ws + L.fslot);
     d.info = (InitInfo *)(ws + L.info);
     d.log = (StepRec *)(ws + L.log);
     d.W = W;
@@ -403,11 +426,15 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     h.iter = 0;
     h.iter_limit = INT64_MAX;
     e = hipMemcpyAsync(d.st, &h, sizeof(IterState), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.sync, 0, sizeof(FillSync), s);
+    if (e == hipSuccess) e = hipMemsetAsync(d.fslot, 0, 8 * (size_t)L.max_tiles, s);
     if (e == hipSuccess) e = launch_prio_init(d, s);
     if (e == hipSuccess) e = launch_commit(d, s);  // selects and stages the first target
     if (e == hipSuccess) e = c->pull_state();
     if (e != hipSuccess) return create_fail(c, INPAINT_DEVICE, std::string("first select: ") + hipGetErrorString(e));
     if (c->h_state->error) return create_fail(c, INPAINT_DEVICE, "device error during the first selection");
+    c->run_form = p->form;
+    if (p->form == INPAINT_FORM_PERSISTENT && !persistent_fits(c)) c->run_form = INPAINT_FORM_STREAM;
     *out = c;
     return INPAINT_OK;
 }
@@ -548,7 +575,7 @@ int32_t inpaint_run(inpaint_ctx *ctx, int64_t max_iters, int64_t *iters_done, in
     const int64_t limit = max_iters < 0 ? INT64_MAX : start + max_iters;
     hipStream_t s = ctx->stream;
     HIP_OR_FAIL(ctx, ctx->set_limit(limit), "limit");
-    const int form = ctx->p.form;
+    const int form = ctx->run_form;
     const int G = form == INPAINT_FORM_PLAIN ? 1 : ctx->p.iters_per_check;
     if (form == INPAINT_FORM_GRAPH) {
         if (ctx->prof) return ctx->fail(INPAINT_INVALID_ARGUMENT, "search timing is not available in the graph form");
@@ -560,6 +587,12 @@ int32_t inpaint_run(inpaint_ctx *ctx, int64_t max_iters, int64_t *iters_done, in
         const int64_t before = ctx->h_state->iter;
         if (form == INPAINT_FORM_GRAPH) {
             HIP_OR_FAIL(ctx, hipGraphLaunch(ctx->graph, s), "graph launch");
+        } else if (form == INPAINT_FORM_PERSISTENT) {
+            const int n = (int)std::min<int64_t>(G, limit - before);
+            const JobDev &d = ctx->d;
+            if (ctx->prof) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0[0], s), "event");
+            HIP_OR_FAIL(ctx, launch_fill(d, d.ntx * d.nty, n, ++ctx->epoch, s), "persistent launch");
+            if (ctx->prof) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1[0], s), "event");
         } else {
             // Stop enqueueing at the iteration limit; past the end of the
             // hole the kernels are no-ops.
@@ -569,7 +602,7 @@ int32_t inpaint_run(inpaint_ctx *ctx, int64_t max_iters, int64_t *iters_done, in
         }
         HIP_OR_FAIL(ctx, ctx->pull_state(), "state");
         if (check_device_state(ctx) != INPAINT_OK) return INPAINT_DEVICE;
-        if (ctx->prof) collect_times(ctx, ctx->h_state->iter - before);
+        if (ctx->prof) collect_times(ctx, form == INPAINT_FORM_PERSISTENT ? 1 : ctx->h_state->iter - before);
         if (ctx->h_state->done || ctx->h_state->iter >= limit) break;
     }
     const int64_t ran = ctx->h_state->iter - start;
@@ -657,6 +690,12 @@ int32_t inpaint_search_time(inpaint_ctx *ctx, double *total_ms, int64_t *searche
     if (!ctx) return INPAINT_INVALID_ARGUMENT;
     if (total_ms) *total_ms = ctx->prof_ms;
     if (searches) *searches = ctx->prof_n;
+    return INPAINT_OK;
+}
+
+int32_t inpaint_run_form(const inpaint_ctx *ctx, int32_t *form) {
+    if (!ctx || !form) return INPAINT_INVALID_ARGUMENT;
+    *form = ctx->run_form;
     return INPAINT_OK;
 }
 

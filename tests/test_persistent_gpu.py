@@ -1,0 +1,113 @@
+"""The persistent fill form (one cooperative dispatch runs many iterations)
+against the CPU oracle and the other forms, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1403_4238_amd import synth
+
+from _util import assert_logs_equal, assert_matches_golden, load_golden
+
+pytestmark = pytest.mark.gpu
+
+B = pytest.importorskip("paper_1403_4238_amd.binding")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build()
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    B.lib()
+
+
+def _full(job, n=32, **kw):
+    o = oracle.Oracle(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, rect=job.rect)
+    g = B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, rect=job.rect,
+                    form="persistent", iters_per_check=n, **kw)
+    want = o.run()
+    st, cnt, got = g.run(log_cap=len(want) + 8)
+    assert st == B.DONE and cnt == len(want)
+    assert_logs_equal(got, want, job.name)
+    rgb_o, _, hole_o, conf_o = o.read()
+    hole_g, conf_g = g.read_state()
+    assert (g.read_image() == rgb_o).all(), f"{job.name}: final image differs"
+    assert (hole_g == hole_o).all() and hole_g.sum() == 0
+    assert (conf_g.view(np.int64) == conf_o.view(np.int64)).all(), f"{job.name}: confidence differs"
+    return g
+
+
+@pytest.mark.parametrize("n", [1, 5, 64])
+def test_small_job_matches_oracle(n):
+    g = _full(synth.small(), n)
+    assert g.run_form() == "persistent"
+
+
+def test_equals_plain_form_and_partial_runs():
+    job = synth.small()
+    plain = B.Inpainter(job.rgb, job.mask, 4, form="plain")
+    _, n1, want = plain.run(log_cap=100)
+    g = B.Inpainter(job.rgb, job.mask, 4, form="persistent", iters_per_check=7)
+    recs = [g.step(), g.step()]
+    st, n, more = g.run(max_iters=9, log_cap=16)
+    assert st == B.OK and n == 9
+    st, n2, rest = g.run(log_cap=100)
+    assert st == B.DONE and 2 + n + n2 == n1
+    got = np.concatenate([np.array(recs, dtype=B.STEP_DTYPE), more, rest])
+    assert_logs_equal(got, want, "step+persistent")
+    assert (plain.read_image() == g.read_image()).all()
+    assert g.run()[0] == B.DONE
+
+
+@pytest.mark.parametrize("seed,W,H,r", [(21, 90, 70, 1), (22, 120, 80, 2), (23, 150, 96, 3), (24, 130, 100, 5),
+                                        (25, 160, 120, 8), (26, 97, 61, 4)])
+def test_random_jobs_all_radii(seed, W, H, r):
+    rng = np.random.default_rng(seed)
+    rgb = rng.integers(0, 256, size=(H, W, 3)).astype(np.uint8)
+    rgb[:, : W // 2] //= 4   # some structure: a darker half
+    mask = np.zeros((H, W), np.uint8)
+    mask[H // 3:H // 3 + max(H // 5, 2), W // 3:W // 3 + max(W // 6, 2)] = 1
+    mask[0:max(H // 9, 1), W - max(W // 8, 2):] = 1
+    g = _full(synth.Job(f"persist{seed}", rgb, mask, r), n=16)
+    assert g.run_form() in ("persistent", "stream")
+
+
+def test_window_and_rect_searches():
+    job = synth.small()
+    _full(synth.Job("small-win", job.rgb, job.mask, 4, synth.SEARCH_ALPHA, (1, 2)))
+    _full(synth.Job("small-rect", job.rgb, job.mask, 3, synth.SEARCH_RECT, (0, 1), (5, 3, 100, 70)))
+
+
+def test_timing_counts_dispatches():
+    job = synth.small()
+    g = B.Inpainter(job.rgb, job.mask, 4, form="persistent", iters_per_check=8)
+    g.profile_search(True)
+    st, n, log = g.run(log_cap=100)
+    ms, cnt = g.search_time()
+    assert st == B.DONE and cnt == (n + 7) // 8 and ms > 0.0
+    assert_logs_equal(log, oracle.Oracle(job.rgb, job.mask, 4).run(), "timed persistent")
+
+
+def test_mfma_context_falls_back_to_stream():
+    job = synth.small()
+    g = B.Inpainter(job.rgb, job.mask, 4, form="persistent", path=B.PATH_MFMA)
+    assert g.run_form() == "stream"
+    st, n, log = g.run(log_cap=100)
+    assert st == B.DONE
+    assert_logs_equal(log, oracle.Oracle(job.rgb, job.mask, 4).run(), "mfma fallback")
+
+
+@pytest.mark.parametrize("key", ["hd9", "hd13w"])
+def test_hd_full_run_matches_stored_oracle(key):
+    gold = load_golden(key)
+    if gold is None:
+        pytest.skip(f"stored oracle result for {key} not generated")
+    job = synth.hd(patch=int(key[2:].rstrip("w")), window=key.endswith("w"))
+    assert job.sha256() == gold["input_sha256"]
+    g = B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, form="persistent",
+                    iters_per_check=32)
+    st, n, log = g.run(log_cap=gold["iterations"] + 8)
+    assert st == B.DONE
+    assert_matches_golden(gold, log, g.read_image(), key + " persistent")
+    if key == "hd9":
+        assert g.run_form() == "persistent"
