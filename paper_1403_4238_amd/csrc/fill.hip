@@ -62,7 +62,8 @@ struct GlobalView {
 };
 
 // The LDS copy of a square neighbourhood: status 0 known, 1 hole, 2 outside
-// the image; confidences; gradients precomputed per pixel.
+// the image; confidences of known pixels (+0.0 for the others); gradients
+// precomputed per pixel.
 template <int R>
 struct LdsStage {
     static constexpr int WIN = 4 * R + 3;          // refresh window side
@@ -87,16 +88,9 @@ struct LdsView {
     __device__ int at(int x, int y) const { return (y - oy) * side + (x - ox); }
     __device__ bool known(int x, int y) const { return s.st[at(x, y)] == 0; }
     __device__ int hole_or_out(int x, int y) const { return s.st[at(x, y)] != 0 ? 1 : 0; }
-    __device__ double conf(int x, int y) const { return s.conf[at(x, y)]; }
-    // C of a known pixel, +0.0 for any other.  Both LDS reads are
-    // unconditional (every staged address is valid) and the value is masked
-    // with integer operations, so no branch (and no serialised LDS round
-    // trip) is generated per offset.
-    __device__ double conf_known(int x, int y) const {
-        const int i = at(x, y);
-        const uint64_t mask = s.st[i] == 0 ? ~0ull : 0ull;
-        return __longlong_as_double((long long)((uint64_t)__double_as_longlong(s.conf[i]) & mask));
-    }
+    // C of a known pixel, +0.0 for any other (the staged array holds +0.0
+    // for pixels that are not known).
+    __device__ double conf_known(int x, int y) const { return s.conf[at(x, y)]; }
     __device__ int grad(int x, int y, int *gx, int *gy) const {
         const int i = at(x, y);
         const int v = s.gxy[i];
@@ -156,6 +150,67 @@ __device__ void priority_terms(const V &v, int px, int py, double norm1, double 
             gx = take ? ax : gx;
             gy = take ? ay : gy;
         }
+    const int nx = v.hole_or_out(px + 1, py) - v.hole_or_out(px - 1, py);
+    const int ny = v.hole_or_out(px, py + 1) - v.hole_or_out(px, py - 1);
+    const int kn = nx * nx + ny * ny;
+    if (kn == 0) {
+        *D = 0.0;
+    } else {
+        int a = gx * ny - gy * nx;
+        if (a < 0) a = -a;
+        *D = (0.5 * (double)a) / (kn == 1 ? norm1 : norm2);
+    }
+}
+
+// Eq. 2 on the LDS neighbourhood, same operation order as priority_terms.
+// The patch is read one row ahead of the arithmetic: each row's P
+// confidences, gradient magnitudes and packed gradients are loaded together
+// while the previous row is summed, so the serial FP64 chain of the
+// confidence sum does not wait for an LDS round trip every few terms.
+template <int R>
+__device__ void priority_terms_lds(const LdsView<R> &v, int px, int py, double norm1, double norm2, double *C,
+                                   double *D) {
+    constexpr int P = 2 * R + 1, side = LdsView<R>::side;
+    const int base = v.at(px - R, py - R);
+    const double *cf = v.s.conf + base;
+    const int *mg = v.s.mag + base;
+    const int *gp = v.s.gxy + base;
+    double c0[P], c1[P];
+    int m0[P], m1[P], g0[P], g1[P];
+#pragma unroll
+    for (int dx = 0; dx < P; ++dx) {
+        c0[dx] = cf[dx];
+        m0[dx] = mg[dx];
+        g0[dx] = gp[dx];
+    }
+    double sum = 0.0;
+    int best = -1, bxy = 0;
+    // (rolled: unrolled, the compiler hoists every row's loads at once)
+#pragma unroll 1
+    for (int dy = 0; dy < P; ++dy) {
+        // the row after the last one is still inside the staged square
+#pragma unroll
+        for (int dx = 0; dx < P; ++dx) {
+            c1[dx] = cf[(dy + 1) * side + dx];
+            m1[dx] = mg[(dy + 1) * side + dx];
+            g1[dx] = gp[(dy + 1) * side + dx];
+        }
+#pragma unroll
+        for (int dx = 0; dx < P; ++dx) {
+            sum = sum + c0[dx];
+            const bool take = m0[dx] > best;   // first in raster order on ties
+            best = take ? m0[dx] : best;
+            bxy = take ? g0[dx] : bxy;
+        }
+#pragma unroll
+        for (int dx = 0; dx < P; ++dx) {
+            c0[dx] = c1[dx];
+            m0[dx] = m1[dx];
+            g0[dx] = g1[dx];
+        }
+    }
+    *C = sum / (double)(P * P);
+    const int gx = (int)(int16_t)(bxy & 0xffff), gy = bxy >> 16;
     const int nx = v.hole_or_out(px + 1, py) - v.hole_or_out(px - 1, py);
     const int ny = v.hole_or_out(px, py + 1) - v.hole_or_out(px, py - 1);
     const int kn = nx * nx + ny * ny;
@@ -476,8 +531,11 @@ __device__ int stage_target(const JobDev &d, int tx, int ty, int r, TargetStage 
         tg->tpix[t] = pix;
         s.tp[t] = pix;
     }
-    kk = block_sum_i64(kk, s.k);
-    t2 = block_sum_i64(t2, s.k);
+    {   // one reduction for both (t2 < 2^32 for any patch)
+        const int64_t both = block_sum_i64((kk << 32) + t2, s.k);
+        kk = both >> 32;
+        t2 = both & 0xffffffffll;
+    }
     write_mask_bits(s, P, tg);
     if (threadIdx.x == 0) {
         tg->tx = tx;
@@ -545,6 +603,28 @@ __device__ Refresh refresh_geometry(const JobDev &d, int px, int py) {
     return g;
 }
 
+// Gradients of the LDS neighbourhood on the stage-local square [lo, hi)^2
+// (1 <= lo, hi <= side - 1): the central-difference gradient of the gray
+// image at known pixels whose four neighbours are known (magnitude and
+// packed components), magnitude -1 elsewhere.
+template <int R>
+__device__ void grad_pass(LdsStage<R> &L, int lo, int hi) {
+    constexpr int side = Stage<R>::side;
+    const int w = hi - lo, n = w * w;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const int i = (lo + t / w) * side + lo + t % w;
+        int mag = -1, gxy = 0;
+        if (L.st[i] == 0 && L.st[i + 1] == 0 && L.st[i - 1] == 0 && L.st[i + side] == 0 && L.st[i - side] == 0) {
+            const int gx = (int)L.gray[i + 1] - (int)L.gray[i - 1];
+            const int gy = (int)L.gray[i + side] - (int)L.gray[i - side];
+            mag = gx * gx + gy * gy;
+            gxy = (gx & 0xffff) | (gy << 16);
+        }
+        L.mag[i] = mag;
+        L.gxy[i] = gxy;
+    }
+}
+
 // Re-evaluates the priorities of the refresh window from the LDS copy of the
 // neighbourhood (already updated by the copy): gradients once per pixel, then
 // each front pixel's (C, D).  New terms go to global memory (for later
@@ -557,21 +637,9 @@ __device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, 
     const int ox = px - S::half, oy = py - S::half;
     const LdsView<R> v{L, ox, oy};
     if (threadIdx.x == 0) L.nfront = 0;
-    // gradients on the inner (side - 2)^2 square
-    constexpr int gs = S::side - 2, gn = gs * gs;
-    for (int t = threadIdx.x; t < gn; t += blockDim.x) {
-        const int x = ox + 1 + t % gs, y = oy + 1 + t / gs;
-        const int i = v.at(x, y);
-        int mag = -1, gxy = 0;
-        if (v.known(x, y) && v.known(x + 1, y) && v.known(x - 1, y) && v.known(x, y + 1) && v.known(x, y - 1)) {
-            const int gx = (int)L.gray[i + 1] - (int)L.gray[i - 1];
-            const int gy = (int)L.gray[i + S::side] - (int)L.gray[i - S::side];
-            mag = gx * gx + gy * gy;
-            gxy = (gx & 0xffff) | (gy << 16);
-        }
-        L.mag[i] = mag;
-        L.gxy[i] = gxy;
-    }
+    // The copy changed gradients only within one pixel of the patch; the
+    // rest of the square was evaluated before it (grad_pass on the whole).
+    grad_pass<R>(L, S::half - R - 1, S::half + R + 2);
     __syncthreads();
     // Window pixels off the front get (C, D) = (-1, 0) at once; front pixels
     // go to a compact list so the costly evaluations fill whole waves.
@@ -596,24 +664,44 @@ __device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, 
         const int wi = L.front[f];
         const int x = px - 2 * R - 1 + wi % WIN, y = py - 2 * R - 1 + wi / WIN;
         double2 cd;
-        priority_terms<R>(v, x, y, d.norm1, d.norm2, &cd.x, &cd.y);
+        priority_terms_lds<R>(v, x, y, d.norm1, d.norm2, &cd.x, &cd.y);
         d.pcd[(int64_t)y * d.W + x] = cd;
         L.wcd[wi] = cd;
         const int b = (y / kBlock - g.aby0) * g.nabx + (x / kBlock - g.abx0);
         L.bkey[b * 64 + (y & 7) * 8 + (x & 7)] = key_of(cd);
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, nb = g.nabx * g.naby;
-    for (int b = threadIdx.x >> 6; b < nb; b += blockDim.x >> 6) {
+    // Block maxima: 16 threads per touched block, 4 keys each, then a
+    // 16-lane reduction ((key, index) pairs are totally ordered, so any
+    // reduction order gives the same maximum); the block's first thread
+    // writes it and folds it into its running argmax.
+    const int sub = threadIdx.x & 15, nb = g.nabx * g.naby;
+    for (int b0 = 0; b0 < nb; b0 += blockDim.x >> 4) {
+        const int b = b0 + (threadIdx.x >> 4);
         const int bx = g.abx0 + b % g.nabx, by = g.aby0 + b / g.nabx;
-        const int x = bx * kBlock + (lane & 7), y = by * kBlock + (lane >> 3);
-        int64_t bk = L.bkey[b * 64 + lane], bi = (int64_t)y * d.W + x;
-        if (!in_img(d, x, y)) {
-            bk = -1;
-            bi = INT64_MAX;
+        int64_t bk = -1, bi = INT64_MAX;
+        if (b < nb) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int e = sub + 16 * j;
+                const int x = bx * kBlock + (e & 7), y = by * kBlock + (e >> 3);
+                const int64_t k = in_img(d, x, y) ? L.bkey[b * 64 + e] : -1;
+                const int64_t i = in_img(d, x, y) ? (int64_t)y * d.W + x : INT64_MAX;
+                if (better(k, i, bk, bi)) {
+                    bk = k;
+                    bi = i;
+                }
+            }
         }
-        wave_argmax(bk, bi);
-        if (lane == 0) {
+        for (int off = 8; off > 0; off >>= 1) {
+            const int64_t k2 = __shfl_xor(bk, off);
+            const int64_t i2 = __shfl_xor(bi, off);
+            if (better(k2, i2, bk, bi)) {
+                bk = k2;
+                bi = i2;
+            }
+        }
+        if (b < nb && sub == 0) {
             d.blk[by * d.nbw + bx].key = bk;
             d.blk[by * d.nbw + bx].idx = bi;
             if (better(bk, bi, key, idx)) {
@@ -654,8 +742,11 @@ __device__ __forceinline__ int stage_target_lds(const LdsStage<R> &L, int px, in
         tg->tpix[t] = pix;
         s.tp[t] = pix;
     }
-    kk = block_sum_i64(kk, s.k);
-    t2 = block_sum_i64(t2, s.k);
+    {   // one reduction for both (t2 < 2^32 for any patch)
+        const int64_t both = block_sum_i64((kk << 32) + t2, s.k);
+        kk = both >> 32;
+        t2 = both & 0xffffffffll;
+    }
     write_mask_bits(s, P, tg);
     if (threadIdx.x == 0) {
         tg->tx = tx;
@@ -877,7 +968,7 @@ __device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, Ld
             const bool in = in_img(d, x, y);
             L.st[t] = !in ? 2 : (h[k] ? 1 : 0);
             L.gray[t] = gv[k];
-            L.conf[t] = c[k];
+            L.conf[t] = (in && !h[k]) ? c[k] : 0.0;   // C of known pixels, +0.0 elsewhere
             L.img[t] = im[k];
         }
     }
@@ -1052,6 +1143,7 @@ __device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L) {
     int64_t key = -1, idx = INT64_MAX;
     uint64_t best = gather<R, true>(d, px, py, g, L, key, idx);
     best = block_min_u64(best, s.u);   // its barriers also publish the LDS stores
+    grad_pass<R>(L, 1, Stage<R>::side - 1);
     commit_finish<R>(d, s, L, v, best, g, key, idx, &s.snap);
 }
 
@@ -1188,6 +1280,8 @@ __device__ void fill_commit(const JobDev &d, int ntiles, int n_iters, uint32_t e
         const Refresh g = refresh_geometry<R>(d, px, py);
         int64_t key = -1, idx = INT64_MAX;
         gather<R, false>(d, px, py, g, L, key, idx);
+        __syncthreads();
+        grad_pass<R>(L, 1, Stage<R>::side - 1);
 
         // (its barriers also publish the gathered LDS neighbourhood)
         int ok = 0;
