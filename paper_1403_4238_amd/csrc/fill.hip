@@ -349,6 +349,7 @@ struct Scratch {
     uint32_t mbits[16];
     uint32_t sbits[16];
     uint32_t ebits[16];
+    int64_t bmk[64], bmi[64];        // maxima of the blocks a refresh touched
     uint32_t tp[kMaxOffsets + 15];   // the staged target words (column-major slots)
 };
 
@@ -410,27 +411,6 @@ __device__ void build_mfma_frags(int r, Scratch &s, MfmaFrags *f) {
             f->k = kk;
             f->rowmask = rows;
         }
-    }
-}
-
-// Publishes the known mask of a staged target (s.mbits, final) and its
-// column-run boundaries: a known slot starts a run when the slot above it in
-// its column is unknown or outside the patch, and ends one when the slot
-// below is.  One thread per slot; called by the whole work-group.
-__device__ void write_mask_bits(Scratch &s, int P, TargetStage *tg) {
-    auto known = [&](int slot) { return (s.mbits[slot >> 5] >> (slot & 31)) & 1u; };
-    for (int slot = threadIdx.x; slot < P * P; slot += blockDim.x) {
-        if (!known(slot)) continue;
-        const int dyi = slot % P;
-        const uint32_t bit = 1u << (slot & 31);
-        if (dyi == 0 || !known(slot - 1)) atomicOr(&s.sbits[slot >> 5], bit);
-        if (dyi == P - 1 || !known(slot + 1)) atomicOr(&s.ebits[slot >> 5], bit);
-    }
-    __syncthreads();
-    if (threadIdx.x < 16) {
-        tg->mbits[threadIdx.x] = s.mbits[threadIdx.x];
-        tg->sbits[threadIdx.x] = s.sbits[threadIdx.x];
-        tg->ebits[threadIdx.x] = s.ebits[threadIdx.x];
     }
 }
 
@@ -504,49 +484,87 @@ __device__ void refresh_block_wave(const JobDev &d, int bx, int by) {
 // Stages the target patch at (tx, ty) with radius r into *tg: known mask,
 // RGBX words and T2 = sum of squared known target values, in column-major
 // slot order (dx + r) * P + (dy + r).
-__device__ int stage_target(const JobDev &d, int tx, int ty, int r, TargetStage *tg, Scratch &s,
-                            MfmaFrags *frag, FillSync *recs = nullptr) {
-    const int P = 2 * r + 1;
-    const GlobalView v{d};
-    if (threadIdx.x < 16) {
-        s.mbits[threadIdx.x] = 0;
-        s.sbits[threadIdx.x] = 0;
-        s.ebits[threadIdx.x] = 0;
-    }
-    __syncthreads();
-    int64_t kk = 0, t2 = 0;
-    for (int t = threadIdx.x; t < kMaxOffsets + 15; t += blockDim.x) {
+// Target staging core: slot(t, &pix) says whether patch slot t (column-major,
+// (dx + r) * P + (dy + r)) is known and gives its RGB word.  One pass over
+// the slots writes the words and takes the known mask with a wave ballot per
+// 64 slots (no atomics), then one barrier; the column-run bits follow from
+// the mask words: a known slot starts a run when the slot above it in its
+// column is unknown or outside the patch, and ends one when the slot below
+// is.  Returns the known count k; T2 = sum of squared known values.
+template <class F>
+__device__ int stage_slots(int r, int tx, int ty, TargetStage *tg, Scratch &s, MfmaFrags *frag, FillSync *recs,
+                           F slot) {
+    const int P = 2 * r + 1, n = P * P, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t t2 = 0;
+    for (int base = 0; base < n; base += blockDim.x) {
+        const int t = base + threadIdx.x;
         uint32_t pix = 0;
-        if (t < P * P) {
-            const int dx = t / P - r, dy = t % P - r;
-            const int x = tx + dx, y = ty + dy;
-            if (v.known(x, y)) {
-                pix = d.img[(int64_t)y * d.W + x] & 0x00ffffffu;
-                const int R = pix & 255, G = (pix >> 8) & 255, B = (pix >> 16) & 255;
-                kk += 1;
-                t2 += R * R + G * G + B * B;
-                atomicOr(&s.mbits[t >> 5], 1u << (t & 31));
-            }
+        const bool kn = t < n && slot(t, &pix);
+        if (t < n) {
+            tg->tpix[t] = pix;
+            s.tp[t] = pix;
         }
-        tg->tpix[t] = pix;
-        s.tp[t] = pix;
+        if (kn) {
+            const uint32_t R = pix & 255, G = (pix >> 8) & 255, B = (pix >> 16) & 255;
+            t2 += R * R + G * G + B * B;
+        }
+        const uint64_t bal = __ballot(kn);
+        const int w0 = (base >> 5) + 2 * wave;
+        if (lane == 0 && w0 < 16) {
+            s.mbits[w0] = (uint32_t)bal;
+            if (w0 + 1 < 16) s.mbits[w0 + 1] = (uint32_t)(bal >> 32);
+        }
     }
-    {   // one reduction for both (t2 < 2^32 for any patch)
-        const int64_t both = block_sum_i64((kk << 32) + t2, s.k);
-        kk = both >> 32;
-        t2 = both & 0xffffffffll;
+    for (int off = 32; off > 0; off >>= 1) t2 += __shfl_xor(t2, off);
+    if (lane == 0) s.u[wave] = t2;
+    __syncthreads();
+    const int mw = (n + 31) / 32, nw = blockDim.x >> 6;
+    uint32_t T2 = 0;
+    for (int w = 0; w < nw; ++w) T2 += (uint32_t)s.u[w];
+    int kk = 0;
+    for (int w = 0; w < mw; ++w) kk += __popc(s.mbits[w]);
+    if ((int)threadIdx.x < mw) {
+        const int w = threadIdx.x;
+        const uint32_t m = s.mbits[w];
+        const uint32_t up = (m << 1) | (w > 0 ? s.mbits[w - 1] >> 31 : 0u);        // slot - 1 known
+        const uint32_t dn = (m >> 1) | (w + 1 < mw ? s.mbits[w + 1] << 31 : 0u);   // slot + 1 known
+        uint32_t cs = 0, ce = 0;   // slots at the top / bottom of their column
+        int rr = (32 * w) % P;
+        for (int b = 0; b < 32; ++b) {
+            if (rr == 0) cs |= 1u << b;
+            if (rr == P - 1) ce |= 1u << b;
+            rr = rr + 1 == P ? 0 : rr + 1;
+        }
+        const uint32_t sb = m & (cs | ~up), eb = m & (ce | ~dn);
+        s.sbits[w] = sb;
+        s.ebits[w] = eb;
+        tg->mbits[w] = m;
+        tg->sbits[w] = sb;
+        tg->ebits[w] = eb;
     }
-    write_mask_bits(s, P, tg);
     if (threadIdx.x == 0) {
         tg->tx = tx;
         tg->ty = ty;
         tg->r = r;
-        tg->k = (int32_t)kk;
-        tg->t2 = (uint32_t)t2;
+        tg->k = kk;
+        tg->t2 = T2;
     }
+    if (frag || recs) __syncthreads();   // s.sbits / s.ebits
     if (frag) build_mfma_frags(r, s, frag);
-    if (recs) write_records(recs, s, P, (int)kk, (uint32_t)t2);
-    return (int)kk;
+    if (recs) write_records(recs, s, P, kk, T2);
+    return kk;
+}
+
+__device__ int stage_target(const JobDev &d, int tx, int ty, int r, TargetStage *tg, Scratch &s,
+                            MfmaFrags *frag, FillSync *recs = nullptr) {
+    const int P = 2 * r + 1;
+    const GlobalView v{d};
+    return stage_slots(r, tx, ty, tg, s, frag, recs, [&](int t, uint32_t *pix) {
+        const int x = tx + t / P - r, y = ty + t % P - r;
+        if (!v.known(x, y)) return false;
+        *pix = d.img[(int64_t)y * d.W + x] & 0x00ffffffu;
+        return true;
+    });
 }
 
 // Argmax over the priority blocks, then stages the winner as the next target.
@@ -631,14 +649,14 @@ __device__ void grad_pass(LdsStage<R> &L, int lo, int hi) {
 // iterations) and to LDS; then one wave per touched block recomputes its
 // maximum, writes it, and folds it into the thread's running argmax.
 template <int R>
-__device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, LdsStage<R> &L, int64_t &key,
-                             int64_t &idx) {
+__device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, LdsStage<R> &L, Scratch &s) {
     using S = Stage<R>;
     const int ox = px - S::half, oy = py - S::half;
     const LdsView<R> v{L, ox, oy};
     if (threadIdx.x == 0) L.nfront = 0;
     // The copy changed gradients only within one pixel of the patch; the
     // rest of the square was evaluated before it (grad_pass on the whole).
+    __syncthreads();   // the copied pixels
     grad_pass<R>(L, S::half - R - 1, S::half + R + 2);
     __syncthreads();
     // Window pixels off the front get (C, D) = (-1, 0) at once; front pixels
@@ -674,7 +692,7 @@ __device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, 
     // Block maxima: 16 threads per touched block, 4 keys each, then a
     // 16-lane reduction ((key, index) pairs are totally ordered, so any
     // reduction order gives the same maximum); the block's first thread
-    // writes it and folds it into its running argmax.
+    // writes it to global memory and to s.bmk / s.bmi.
     const int sub = threadIdx.x & 15, nb = g.nabx * g.naby;
     for (int b0 = 0; b0 < nb; b0 += blockDim.x >> 4) {
         const int b = b0 + (threadIdx.x >> 4);
@@ -704,10 +722,8 @@ __device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, 
         if (b < nb && sub == 0) {
             d.blk[by * d.nbw + bx].key = bk;
             d.blk[by * d.nbw + bx].idx = bi;
-            if (better(bk, bi, key, idx)) {
-                key = bk;
-                idx = bi;
-            }
+            s.bmk[b] = bk;
+            s.bmi[b] = bi;
         }
     }
 }
@@ -719,45 +735,12 @@ __device__ __forceinline__ int stage_target_lds(const LdsStage<R> &L, int px, in
                                                 Scratch &s, MfmaFrags *frag, FillSync *recs = nullptr) {
     using S = Stage<R>;
     constexpr int P = 2 * R + 1;
-    if (threadIdx.x < 16) {
-        s.mbits[threadIdx.x] = 0;
-        s.sbits[threadIdx.x] = 0;
-        s.ebits[threadIdx.x] = 0;
-    }
-    __syncthreads();
-    int64_t kk = 0, t2 = 0;
-    for (int t = threadIdx.x; t < kMaxOffsets + 15; t += blockDim.x) {
-        uint32_t pix = 0;
-        if (t < P * P) {
-            const int dx = t / P - R, dy = t % P - R;
-            const int i = (ty + dy - py + S::half) * S::side + (tx + dx - px + S::half);
-            if (L.st[i] == 0) {
-                pix = L.img[i] & 0x00ffffffu;
-                const int Rr = pix & 255, G = (pix >> 8) & 255, B = (pix >> 16) & 255;
-                kk += 1;
-                t2 += Rr * Rr + G * G + B * B;
-                atomicOr(&s.mbits[t >> 5], 1u << (t & 31));
-            }
-        }
-        tg->tpix[t] = pix;
-        s.tp[t] = pix;
-    }
-    {   // one reduction for both (t2 < 2^32 for any patch)
-        const int64_t both = block_sum_i64((kk << 32) + t2, s.k);
-        kk = both >> 32;
-        t2 = both & 0xffffffffll;
-    }
-    write_mask_bits(s, P, tg);
-    if (threadIdx.x == 0) {
-        tg->tx = tx;
-        tg->ty = ty;
-        tg->r = R;
-        tg->k = (int32_t)kk;
-        tg->t2 = (uint32_t)t2;
-    }
-    if (frag) build_mfma_frags(R, s, frag);
-    if (recs) write_records(recs, s, P, (int)kk, (uint32_t)t2);
-    return (int)kk;
+    return stage_slots(R, tx, ty, tg, s, frag, recs, [&](int t, uint32_t *pix) {
+        const int i = (ty + t % P - R - py + S::half) * S::side + (tx + t / P - R - px + S::half);
+        if (L.st[i] != 0) return false;
+        *pix = L.img[i] & 0x00ffffffu;
+        return true;
+    });
 }
 
 }  // namespace
@@ -918,7 +901,7 @@ __device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, Ld
     constexpr int T = kCommitThreads;
     constexpr int NIT = (S::n + T - 1) / T;
     constexpr int KIT = (LdsStage<R>::NBA * LdsStage<R>::NBA * 64 + T - 1) / T;
-    constexpr int BIT = PARTIALS ? 16 : 8, PIT = PARTIALS ? 8 : 0;
+    constexpr int BIT = PARTIALS ? 16 : 4, PIT = PARTIALS ? 8 : 0;
     const int ox = px - S::half, oy = py - S::half;
     const int nkeys = g.nabx * g.naby * 64;
     const int bw = d.pbx1 - d.pbx0, nb = bw * (d.pby1 - d.pby0);
@@ -1011,10 +994,11 @@ __device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, Ld
 //
 // After the copy everything runs out of LDS; the next target is staged from
 // LDS when its patch lies inside the staged neighbourhood (the common case:
-// the front moves locally).
+// the front moves locally).  (key0, idx0) is the argmax over the blocks the
+// refresh does not touch (block-uniform).
 template <int R>
 __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const Snap &v, uint64_t best,
-                              const Refresh &g, int64_t key, int64_t idx, Snap *out, FillSync *recs = nullptr) {
+                              const Refresh &g, int64_t key0, int64_t idx0, Snap *out, FillSync *recs = nullptr) {
     IterState *st = d.st;
     constexpr int P = 2 * R + 1;
     const int W = d.W;
@@ -1033,7 +1017,8 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
     const int64_t q = (int64_t)(best & 0xffffffffu);
     const uint32_t ssd = (uint32_t)(best >> 32);
     const int qx = (int)(q % W), qy = (int)(q / W);
-    int64_t filled = 0;
+    // the hole pixels of the target patch: its in-image pixels minus the known k
+    const int64_t filled = (int64_t)(min(px + R + 1, W) - max(px - R, 0)) * (min(py + R + 1, d.H) - max(py - R, 0)) - v.k;
     for (int t = threadIdx.x; t < P * P; t += blockDim.x) {
         const int dx = t % P - R, dy = t / P - R;
         const int li = (dy + Stage<R>::half) * Stage<R>::side + (dx + Stage<R>::half);
@@ -1049,10 +1034,8 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
             L.img[li] = pix;
             L.gray[li] = gv;
             L.conf[li] = v.C;
-            filled += 1;
         }
     }
-    filled = block_sum_i64(filled, s.k);
     const int64_t remaining = v.remaining - filled;
     if (threadIdx.x == 0) {
         StepRec rec;
@@ -1082,9 +1065,22 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
         return;
     }
 
-    // ---- priorities near the patch, block maxima, argmax
-    refresh_near<R>(d, px, py, g, L, key, idx);
-    block_argmax(key, idx, s.k, s.i);
+    // ---- priorities near the patch, block maxima, argmax: wave 0 reduces
+    // the touched blocks' maxima and (key0, idx0)
+    refresh_near<R>(d, px, py, g, L, s);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x, nb = g.nabx * g.naby;
+        int64_t k2 = lane < nb ? s.bmk[lane] : (lane == 63 ? key0 : -1);
+        int64_t i2 = lane < nb ? s.bmi[lane] : (lane == 63 ? idx0 : INT64_MAX);
+        wave_argmax(k2, i2);
+        if (lane == 0) {
+            s.k[0] = k2;
+            s.i[0] = i2;
+        }
+    }
+    __syncthreads();
+    const int64_t key = s.k[0], idx = s.i[0];
     if (key < 0) {
         // No front pixel although the hole is not empty: cannot happen for a
         // valid state; flag it instead of looping.
@@ -1144,6 +1140,7 @@ __device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L) {
     uint64_t best = gather<R, true>(d, px, py, g, L, key, idx);
     best = block_min_u64(best, s.u);   // its barriers also publish the LDS stores
     grad_pass<R>(L, 1, Stage<R>::side - 1);
+    block_argmax(key, idx, s.k, s.i);
     commit_finish<R>(d, s, L, v, best, g, key, idx, &s.snap);
 }
 
@@ -1282,6 +1279,7 @@ __device__ void fill_commit(const JobDev &d, int ntiles, int n_iters, uint32_t e
         gather<R, false>(d, px, py, g, L, key, idx);
         __syncthreads();
         grad_pass<R>(L, 1, Stage<R>::side - 1);
+        block_argmax(key, idx, s.k, s.i);
 
         // (its barriers also publish the gathered LDS neighbourhood)
         int ok = 0;
