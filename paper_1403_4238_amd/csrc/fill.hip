@@ -15,7 +15,7 @@
 // and from the LDS copy of the neighbourhood (per iteration).
 #pragma clang fp contract(off)
 
-#include "search_tile.h"
+#include "search_mfma_tile.h"
 
 namespace inpaint {
 
@@ -1170,7 +1170,7 @@ __device__ int wait_go(const FillSync *sy, int t, uint32_t epoch, uint32_t k) {
         const uint64_t v = __hip_atomic_load(g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (v == want) return 1;
         if (v == stop) return 0;
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
     }
     return 0;
 }
@@ -1214,7 +1214,7 @@ __device__ uint64_t collect_slots(const uint64_t *fs, int ntiles, uint32_t tag, 
             done = 1;
             break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
     }
     *ok = done;
     if (!done) return ~0ull;
@@ -1245,9 +1245,14 @@ union FillLds {
 };
 
 template <int R>
-__device__ void fill_commit(const JobDev &d, int ntiles, int n_iters, uint32_t epoch, CommitLds<R> &C) {
+__device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t epoch, CommitLds<R> &C) {
     Scratch &s = C.s;
     LdsStage<R> &L = C.L;
+    // The search groups build their MFMA operands themselves; the commit
+    // writes the fragments of the staged target once, at the end.
+    JobDev d = d0;
+    d.mfma = 0;
+    bool staged = false;
     FillSync *sy = d.sync;
     if (threadIdx.x == 0) s.snap = load_snap(d.st, d.tgt);
     __syncthreads();
@@ -1264,10 +1269,12 @@ __device__ void fill_commit(const JobDev &d, int ntiles, int n_iters, uint32_t e
         __hip_atomic_store(&d.fslot[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (uint32_t k = 0;; ++k) {
         const bool stop = v.done || v.err || !v.pending || v.iter >= v.limit || (int)k >= n_iters;
-        // Every wave's writes (records, state, slot resets) reach device
-        // scope before go.  (Release only: nothing this group reads is
-        // written by another group except through device-scope loads.)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // Every wave's writes (records, state, slot resets) reach this
+        // XCD's L2; then wave 0's release of go writes the L2 back, so they
+        // reach device scope before go does.  (Nothing this group reads is
+        // written by another group except through device-scope loads, so no
+        // acquire is needed.)
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         publish_go(sy, go_word(epoch, stop ? 0xffffffffu : k + 1));
         if (stop) break;
@@ -1292,7 +1299,10 @@ __device__ void fill_commit(const JobDev &d, int ntiles, int n_iters, uint32_t e
         commit_finish<R>(d, s, L, v, best, g, key, idx, &s.snap, sy);
         __syncthreads();
         v = s.snap;
+        staged = true;
     }
+    // s.tp / s.mbits hold the last target staged here
+    if (d0.mfma && staged && v.pending && !v.done && !v.err) build_mfma_frags(R, s, d0.frag);
 }
 
 // Copies record `rec` (published by the go word just observed) into LDS.
@@ -1343,6 +1353,65 @@ __device__ void fill_search(const JobDev &d, int ntiles, uint32_t epoch, SearchL
             __hip_atomic_store(&d.fslot[t], slot_word(best, slot_tag(k)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
     }
+}
+
+template <int R>
+struct SearchLdsMfma {
+    mtile::MfmaTile<R> tile;
+    tile::TargetLds tgt;
+    mtile::FragTables<R> ft;
+    uint64_t red[kSearchWaves];
+    int32_t flag;
+};
+
+template <int R>
+union FillLdsMfma {
+    CommitLds<R> c;
+    SearchLdsMfma<R> s;
+};
+
+// Search group of the MFMA form: one 64 x 64 tile of the MFMA tiling, staged
+// once; per target it builds the B-operand tables in LDS from the record and
+// scores the tile on the matrix cores.
+template <int R>
+__device__ void fill_search_mfma(const JobDev &d, uint32_t epoch, SearchLdsMfma<R> &S) {
+    const int t = (int)blockIdx.x - 1;
+    int tx0, ty0;
+    mtile::tile_origin<R>(d.rx0, d.ry0, d.ntx, t, &tx0, &ty0);
+    const uint32_t vmask = mtile::stage_tile<R>(d, tx0, ty0, d.rx0, d.rx1, d.ry1, S.tile);
+    const bool anyv = __syncthreads_or(vmask != 0);
+    FillSync *sy = d.sync;
+    for (uint32_t k = 0;; ++k) {
+        if (threadIdx.x == 0) S.flag = wait_go(sy, t, epoch, k);
+        __syncthreads();
+        if (!S.flag) break;
+        uint64_t best = ~0ull;
+        if (anyv) {
+            load_record<R>(&sy->rec[t % kGoCopies], &S.tgt);
+            __syncthreads();
+            mtile::build_tables<R>(&S.tgt, &S.ft);
+            __syncthreads();
+            mtile::BFrags<R> b;
+            mtile::load_frags<R>(&S.ft, b);
+            best = tile::wave_min_u64(mtile::score_tile<R>(d, b, tx0, ty0, vmask, S.tile));
+            if ((threadIdx.x & 63) == 0) S.red[threadIdx.x >> 6] = best;
+            __syncthreads();
+            if (threadIdx.x == 0)
+                for (int w = 0; w < kSearchWaves; ++w) best = S.red[w] < best ? S.red[w] : best;
+        }
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&d.fslot[t], slot_word(best, slot_tag(k)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_fill_mfma(JobDev d, int ntiles, int n_iters, uint32_t epoch) {
+    __shared__ FillLdsMfma<R> lds;
+    if (blockIdx.x == 0)
+        fill_commit<R>(d, ntiles, n_iters, epoch, lds.c);
+    else
+        fill_search_mfma<R>(d, epoch, lds.s);
 }
 
 template <int R>
@@ -1471,7 +1540,18 @@ hipError_t launch_commit_batched(const JobDev *slots, const int32_t *ids, const 
     return hipGetLastError();
 }
 
-static const void *fill_kernel(int r) {
+static const void *fill_kernel(int r, bool mfma) {
+    if (mfma) {
+        switch (r) {
+            case 1: return (const void *)k_fill_mfma<1>;
+            case 2: return (const void *)k_fill_mfma<2>;
+            case 3: return (const void *)k_fill_mfma<3>;
+            case 4: return (const void *)k_fill_mfma<4>;
+            case 5: return (const void *)k_fill_mfma<5>;
+            case 6: return (const void *)k_fill_mfma<6>;
+            default: return nullptr;
+        }
+    }
     switch (r) {
         case 1: return (const void *)k_fill<1>;
         case 2: return (const void *)k_fill<2>;
@@ -1485,8 +1565,8 @@ static const void *fill_kernel(int r) {
     }
 }
 
-hipError_t fill_blocks_per_cu(int r, int *blocks) {
-    const void *f = fill_kernel(r);
+hipError_t fill_blocks_per_cu(int r, bool mfma, int *blocks) {
+    const void *f = fill_kernel(r, mfma);
     if (!f) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, kCommitThreads, 0);
 }
@@ -1494,7 +1574,7 @@ hipError_t fill_blocks_per_cu(int r, int *blocks) {
 int fill_grid(int ntiles) { return 1 + ntiles; }
 
 hipError_t launch_fill(const JobDev &d, int ntiles, int n_iters, uint32_t epoch, hipStream_t s) {
-    const void *f = fill_kernel(d.r);
+    const void *f = fill_kernel(d.r, d.mfma != 0);
     if (!f) return hipErrorInvalidValue;
     JobDev dd = d;
     void *args[] = {&dd, &ntiles, &n_iters, &epoch};

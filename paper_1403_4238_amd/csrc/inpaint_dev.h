@@ -100,7 +100,7 @@ struct alignas(256) IterState {
 // record t % kGoCopies, so a thousand work-groups do not all hit the same
 // lines; each reports in its own slot word, so no address takes more than
 // one writer.
-constexpr int kGoCopies = 32;
+constexpr int kGoCopies = 16;
 struct alignas(256) FillRec {
     uint64_t go;
     uint32_t t2, k;
@@ -195,7 +195,7 @@ hipError_t launch_search_batched(const JobDev *slots, const WorkItem *items, con
                                  int r, int tile_rows, int grid, hipStream_t s);
 // Persistent fill (cooperative): runs up to n_iters iterations of the job in
 // one dispatch; needs fill_grid(ntiles) co-resident work-groups.
-hipError_t fill_blocks_per_cu(int r, int *blocks);
+hipError_t fill_blocks_per_cu(int r, bool mfma, int *blocks);
 int fill_grid(int ntiles);
 hipError_t launch_fill(const JobDev &d, int ntiles, int n_iters, uint32_t epoch, hipStream_t s);
 

@@ -239,20 +239,20 @@ static int32_t check_params(int32_t W, int32_t H, const inpaint_params *p, std::
     return INPAINT_OK;
 }
 
-// Whether the persistent fill can run this job: SIMT search with its tile
-// shape, a device with cooperative launch, and every work-group of the
-// dispatch co-resident.
+// Whether the persistent fill can run this job: the SIMT search with its
+// tile shape or the MFMA search, a device with cooperative launch, and every
+// work-group of the dispatch co-resident.
 static bool persistent_fits(const inpaint_ctx *c) {
     const JobDev &d = c->d;
     const int ntiles = d.ntx * d.nty;
     // (the committer scans at most 32 slots per thread)
-    if (c->mfma || d.tile_rows != kFillTileRows || ntiles <= 0 || ntiles > 32 * kCommitThreads) return false;
+    if ((!c->mfma && d.tile_rows != kFillTileRows) || ntiles <= 0 || ntiles > 32 * kCommitThreads) return false;
     if ((int64_t)d.W * d.H > (1ll << kSlotIndexBits)) return false;   // slot word index field
     int dev = 0, coop = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
-    if (fill_blocks_per_cu(d.r, &per_cu) != hipSuccess) return false;
+    if (fill_blocks_per_cu(d.r, c->mfma, &per_cu) != hipSuccess) return false;
     return (int64_t)fill_grid(ntiles) <= (int64_t)per_cu * cus;
 }
 

@@ -1,0 +1,265 @@
+// Exact int8-MFMA exemplar-search tile on gfx950 (see search_mfma.hip for
+// the arithmetic): staging of a 64 x 64 candidate tile, the B operands of a
+// target, and the scoring loop, shared by the one-search-per-launch kernel
+// and the persistent fill kernel.
+#pragma once
+
+#include "search_tile.h"
+
+namespace inpaint {
+namespace mtile {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaTilesPerWave = 4;                       // 16-row tiles stacked per wave
+constexpr int kMfmaTileH = 16 * kMfmaTilesPerWave;          // 64 rows
+constexpr int kMfmaStrideA = 100;                           // words per staged row (100 % 32 == 4)
+constexpr int kMfmaStrideQ = 272;                           // bytes per |s'|^2 row (68 words, 68 % 32 == 4)
+
+template <int R>
+struct MfmaGeom {
+    static constexpr int P = 2 * R + 1;
+    static constexpr int ROWS = kMfmaTileH + 2 * R;
+    static constexpr int COLS = kTileW + 2 * R;                 // staged columns that meet nonzero B entries
+    static constexpr int QA = (COLS + 3) / 4;                   // 16-byte quads per row: RGBX words
+    static constexpr int QQ = (2 * COLS + 15) / 16;             // 16-byte quads per row: |s'|^2 byte pairs
+    static constexpr int NA = ROWS * QA, NQ = ROWS * QQ;
+    static constexpr int AIT = (NA + kSearchWaves * 64 - 1) / (kSearchWaves * 64);
+    static constexpr int QIT = (NQ + kSearchWaves * 64 - 1) / (kSearchWaves * 64);
+};
+
+// |s'|^2 of an RGBX word, split into (low byte - 128, high byte - 128) int8s
+// packed as a 16-bit value (low byte first).
+__device__ __forceinline__ uint16_t sq_bytes(uint32_t w) {
+    const int r = (int)(w & 255) - 128, g = (int)((w >> 8) & 255) - 128, b = (int)((w >> 16) & 255) - 128;
+    const int q = r * r + g * g + b * b;              // 0 .. 49152
+    const int lo = (q & 255) - 128, hi = (q >> 8) - 128;
+    return (uint16_t)((uint8_t)lo | ((uint32_t)(uint8_t)hi << 8));
+}
+
+template <int R>
+struct MfmaTile {
+    alignas(16) uint32_t a[MfmaGeom<R>::ROWS * kMfmaStrideA];      // RGBX ^ 0x80808080
+    alignas(16) uint8_t q[MfmaGeom<R>::ROWS * kMfmaStrideQ + 32];  // (lo', hi') per pixel
+};
+
+// The B operands of one target in the v_mfma_i32_16x16x64_i8 register
+// layout (see MfmaFrags) plus T2' = sum of |t - 128|^2, k and the mask of
+// patch rows holding a known pixel.
+template <int R>
+struct BFrags {
+    static constexpr int P = 2 * R + 1;
+    v4i c[P][2], l[P], h[P];
+    int t2p, k;
+    uint32_t rowmask;
+};
+
+// From the fragments the commit kernel wrote.
+template <int R>
+__device__ __forceinline__ void load_frags(const MfmaFrags *fr, BFrags<R> &b) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int dy = 0; dy < 2 * R + 1; ++dy) {
+        b.c[dy][0] = *(const v4i *)fr->c[dy][0][lane];
+        b.c[dy][1] = *(const v4i *)fr->c[dy][1][lane];
+        b.l[dy] = *(const v4i *)fr->l[dy][lane];
+        b.h[dy] = *(const v4i *)fr->h[dy][lane];
+    }
+    b.t2p = fr->t2p;
+    b.k = fr->k;
+    b.rowmask = fr->rowmask;
+}
+
+// Per-target tables a work-group builds in LDS from a TargetLds, from which
+// every wave reads its B operands with a few aligned LDS loads.  With
+// T(dy, x) the target word (RGB ^ 0x808080) at patch column x of row dy
+// where known, 0 elsewhere (also outside 0 <= x < P), and M(dy, x) its 0/1
+// known flag: tc[s][dy][i] = T(dy, i - 16 - s), so the four words lane
+// (n, g) needs, T(dy, 16 h + 4 g - n + j), start 16-byte aligned in copy
+// s = n mod 4; lw[dy][i] = M(dy, i - 16) | M(dy, i - 15) << 16.
+template <int R>
+struct FragTables {
+    static constexpr int P = 2 * R + 1;
+    alignas(16) uint32_t tc[4][P][48];
+    uint32_t lw[P][48];
+    int t2p[kSearchWaves], k[kSearchWaves];
+    uint32_t rowmask[kSearchWaves];
+};
+
+template <int R>
+__device__ __forceinline__ void build_tables(const tile::TargetLds *t, FragTables<R> *ft) {
+    constexpr int P = 2 * R + 1;
+    auto known = [&](int x, int dy) { return x >= 0 && x < P && ((t->mbits[(x * P + dy) >> 5] >> ((x * P + dy) & 31)) & 1u); };
+    for (int e = threadIdx.x; e < 4 * P * 48; e += blockDim.x) {
+        const int s = e / (P * 48), dy = (e / 48) % P, i = e % 48;
+        const int x = i - 16 - s;
+        ft->tc[s][dy][i] = known(x, dy) ? (t->tpix[x * P + dy] ^ 0x00808080u) : 0u;
+    }
+    for (int e = threadIdx.x; e < P * 48; e += blockDim.x) {
+        const int dy = e / 48, i = e % 48;
+        ft->lw[dy][i] = (known(i - 16, dy) ? 1u : 0u) | (known(i - 15, dy) ? 1u << 16 : 0u);
+    }
+    // T2', k and the row mask: one slot per thread, reduced per wave
+    int t2 = 0, kk = 0;
+    uint32_t rows = 0;
+    for (int sl = threadIdx.x; sl < P * P; sl += blockDim.x)
+        if ((t->mbits[sl >> 5] >> (sl & 31)) & 1u) {
+            const uint32_t w = t->tpix[sl];
+            const int a = (int)(w & 255) - 128, b = (int)((w >> 8) & 255) - 128, c = (int)((w >> 16) & 255) - 128;
+            t2 += a * a + b * b + c * c;
+            kk += 1;
+            rows |= 1u << (sl % P);
+        }
+    for (int off = 32; off > 0; off >>= 1) {
+        t2 += __shfl_xor(t2, off);
+        kk += __shfl_xor(kk, off);
+        rows |= __shfl_xor(rows, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        ft->t2p[threadIdx.x >> 6] = t2;
+        ft->k[threadIdx.x >> 6] = kk;
+        ft->rowmask[threadIdx.x >> 6] = rows;
+    }
+}
+
+// After a barrier that publishes the tables.
+template <int R>
+__device__ __forceinline__ void load_frags(const FragTables<R> *ft, BFrags<R> &b) {
+    constexpr int P = 2 * R + 1;
+    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4, s = n & 3;
+#pragma unroll
+    for (int dy = 0; dy < P; ++dy) {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) b.c[dy][hh] = *(const v4i *)&ft->tc[s][dy][16 * hh + 4 * g + 16 - 4 * (n >> 2)];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t w = ft->lw[dy][8 * g + 2 * j - n + 16];
+            b.l[dy][j] = (int)w;
+            b.h[dy][j] = (int)(w << 8);
+        }
+    }
+    int t2 = 0, kk = 0;
+    uint32_t rows = 0;
+#pragma unroll
+    for (int w = 0; w < kSearchWaves; ++w) {
+        t2 += ft->t2p[w];
+        kk += ft->k[w];
+        rows |= ft->rowmask[w];
+    }
+    b.t2p = __builtin_amdgcn_readfirstlane(t2);
+    b.k = __builtin_amdgcn_readfirstlane(kk);
+    b.rowmask = __builtin_amdgcn_readfirstlane(rows);
+}
+
+// First tile column and row of tile `tile` of the MFMA tiling of the rect.
+template <int R>
+__device__ __forceinline__ void tile_origin(int rx0, int ry0, int ntx, int tile, int *tx0, int *ty0) {
+    *tx0 = mfma_tile_x0(rx0, R) + (tile % ntx) * kTileW;
+    *ty0 = ry0 + (tile / ntx) * kMfmaTileH;
+}
+
+// Issues every load of the tile at (tx0, ty0) -- staged window (padded rows
+// ty0 - R + kPadT .., columns tx0 - R + kPadL .., a multiple of 8) and the
+// validity radii of this lane's candidates (rows 16 t + 4 g + i of the tile,
+// column tx0 + 16 wave + n) -- then writes the window to LDS.  Returns the
+// lane's validity bits (bit 4 t + i); the caller publishes with a barrier.
+template <int R>
+__device__ __forceinline__ uint32_t stage_tile(const JobDev &d, int tx0, int ty0, int rx0, int rx1, int ry1,
+                                               MfmaTile<R> &L) {
+    using G = MfmaGeom<R>;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 15, g = lane >> 4;
+    const int pitch = d.pitch;
+    const int cx = tx0 + 16 * wave + n;
+    const int64_t org = (int64_t)(ty0 - R + kPadT) * pitch + (tx0 - R + kPadL);
+    const uint4 *wa = (const uint4 *)(d.srcw + org);
+    const uint4 *wq = (const uint4 *)(d.srcq + org);
+    uint4 va[G::AIT], vq[G::QIT];
+#pragma unroll
+    for (int k = 0; k < G::AIT; ++k) {
+        const int i = min(tid + k * kSearchWaves * 64, G::NA - 1);
+        const int ly = i / G::QA, lq = i - ly * G::QA;
+        va[k] = wa[ly * (pitch >> 2) + lq];
+    }
+#pragma unroll
+    for (int k = 0; k < G::QIT; ++k) {
+        const int i = min(tid + k * kSearchWaves * 64, G::NQ - 1);
+        const int ly = i / G::QQ, lq = i - ly * G::QQ;
+        vq[k] = wq[ly * (pitch >> 3) + lq];
+    }
+    const uint8_t *vr = d.vradp + (int64_t)(ty0 + 4 * g + kPadT) * pitch + (cx + kPadL);
+    uint32_t vv[kMfmaTilesPerWave * 4];
+#pragma unroll
+    for (int t = 0; t < kMfmaTilesPerWave; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vv[4 * t + i] = vr[(16 * t + i) * pitch];
+
+#pragma unroll
+    for (int k = 0; k < G::AIT; ++k) {
+        const int i = min(tid + k * kSearchWaves * 64, G::NA - 1);
+        const int ly = i / G::QA, lq = i - ly * G::QA;
+        *(uint4 *)&L.a[ly * kMfmaStrideA + 4 * lq] = va[k];
+    }
+#pragma unroll
+    for (int k = 0; k < G::QIT; ++k) {
+        const int i = min(tid + k * kSearchWaves * 64, G::NQ - 1);
+        const int ly = i / G::QQ, lq = i - ly * G::QQ;
+        *(uint4 *)&L.q[ly * kMfmaStrideQ + 16 * lq] = vq[k];
+    }
+    uint32_t vmask = 0;
+    const bool colok = cx >= rx0 && cx < rx1;
+#pragma unroll
+    for (int t = 0; t < kMfmaTilesPerWave; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int y = ty0 + 16 * t + 4 * g + i;
+            if (colok && y < ry1 && vv[4 * t + i] >= (uint32_t)R) vmask |= 1u << (4 * t + i);
+        }
+    return vmask;
+}
+
+// Scores this lane's candidates of a staged tile and returns their minimum
+// key (~0 if none is valid).
+template <int R>
+__device__ __forceinline__ uint64_t score_tile(const JobDev &d, const BFrags<R> &b, int tx0, int ty0, uint32_t vmask,
+                                               const MfmaTile<R> &L) {
+    constexpr int P = 2 * R + 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = lane & 15, g = lane >> 4;
+    const int W = d.W, cx = tx0 + 16 * wave + n;
+    const int t2 = b.t2p, kk = b.k;
+    const uint32_t rowmask = b.rowmask;
+    uint64_t best = ~0ull;
+#pragma unroll
+    for (int t = 0; t < kMfmaTilesPerWave; ++t) {
+        // four independent accumulation chains keep the MFMA pipeline busy
+        v4i c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0}, ch = {0, 0, 0, 0}, cl = {0, 0, 0, 0};
+#pragma unroll
+        for (int dy = 0; dy < P; ++dy) {
+            if (!((rowmask >> dy) & 1u)) continue;   // uniform: patch row without a known pixel
+            const int ly = 16 * t + n + dy;                   // A row = candidate row n of the tile
+            const v4i a0 = *(const v4i *)&L.a[ly * kMfmaStrideA + 16 * wave + 4 * g];
+            const v4i a1 = *(const v4i *)&L.a[ly * kMfmaStrideA + 16 * wave + 16 + 4 * g];
+            const v4i aq = *(const v4i *)&L.q[ly * kMfmaStrideQ + 32 * wave + 16 * g];
+            c0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b.c[dy][0], c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b.c[dy][1], c1, 0, 0, 0);
+            cl = __builtin_amdgcn_mfma_i32_16x16x64_i8(aq, b.l[dy], cl, 0, 0, 0);
+            ch = __builtin_amdgcn_mfma_i32_16x16x64_i8(aq, b.h[dy], ch, 0, 0, 0);
+        }
+        // C lane (n, g) holds rows 4g + i of column n.
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (vmask & (1u << (4 * t + i))) {
+                const int s2 = 256 * (ch[i] + 128 * kk) + cl[i] + 128 * kk;
+                const uint32_t ssd = (uint32_t)(t2 - 2 * (c0[i] + c1[i]) + s2);
+                const int y = ty0 + 16 * t + 4 * g + i;
+                const uint64_t key = ((uint64_t)ssd << 32) | (uint32_t)(y * W + cx);
+                best = key < best ? key : best;
+            }
+        }
+    }
+    return best;
+}
+
+}  // namespace mtile
+}  // namespace inpaint

@@ -88,26 +88,48 @@ def test_timing_counts_dispatches():
     assert_logs_equal(log, oracle.Oracle(job.rgb, job.mask, 4).run(), "timed persistent")
 
 
-def test_mfma_context_falls_back_to_stream():
+@pytest.mark.parametrize("n", [1, 6, 64])
+def test_mfma_small_job_matches_oracle(n):
+    g = _full(synth.small(), n, path=B.PATH_MFMA)
+    assert g.run_form() == "persistent"
+
+
+@pytest.mark.parametrize("seed,W,H,r", [(31, 90, 70, 1), (32, 150, 96, 3), (33, 130, 100, 5), (34, 140, 90, 6),
+                                        (35, 97, 61, 4)])
+def test_mfma_random_jobs(seed, W, H, r):
+    rng = np.random.default_rng(seed)
+    rgb = rng.integers(0, 256, size=(H, W, 3)).astype(np.uint8)
+    rgb[H // 2:, :] = 255 - rgb[H // 2:, :] // 3   # saturated lower half
+    mask = np.zeros((H, W), np.uint8)
+    mask[H // 3:H // 3 + max(H // 5, 2), W // 3:W // 3 + max(W // 6, 2)] = 1
+    mask[0:max(H // 9, 1), W - max(W // 8, 2):] = 1
+    _full(synth.Job(f"mfmapersist{seed}", rgb, mask, r), n=16, path=B.PATH_MFMA)
+
+
+def test_mfma_then_plain_steps_use_fresh_fragments():
+    # A persistent dispatch leaves the staged target's MFMA operands for the
+    # one-search-per-launch kernels: mixing the forms stays exact.
     job = synth.small()
-    g = B.Inpainter(job.rgb, job.mask, 4, form="persistent", path=B.PATH_MFMA)
-    assert g.run_form() == "stream"
-    st, n, log = g.run(log_cap=100)
-    assert st == B.DONE
-    assert_logs_equal(log, oracle.Oracle(job.rgb, job.mask, 4).run(), "mfma fallback")
+    want = oracle.Oracle(job.rgb, job.mask, 4).run()
+    g = B.Inpainter(job.rgb, job.mask, 4, form="persistent", iters_per_check=5, path=B.PATH_MFMA)
+    st, n1, a = g.run(max_iters=11, log_cap=16)
+    recs = [g.step() for _ in range(3)]
+    st, n2, b = g.run(log_cap=len(want))
+    got = np.concatenate([a, np.array(recs, dtype=B.STEP_DTYPE), b])
+    assert_logs_equal(got, want, "mfma persistent + steps")
 
 
-@pytest.mark.parametrize("key", ["hd9", "hd13w"])
-def test_hd_full_run_matches_stored_oracle(key):
+@pytest.mark.parametrize("key,path", [("hd9", "simt"), ("hd13w", "simt"), ("hd9", "mfma"), ("hd13w", "mfma")])
+def test_hd_full_run_matches_stored_oracle(key, path):
     gold = load_golden(key)
     if gold is None:
         pytest.skip(f"stored oracle result for {key} not generated")
     job = synth.hd(patch=int(key[2:].rstrip("w")), window=key.endswith("w"))
     assert job.sha256() == gold["input_sha256"]
     g = B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, form="persistent",
-                    iters_per_check=32)
+                    iters_per_check=32, path=B.PATH_MFMA if path == "mfma" else B.PATH_SIMT)
     st, n, log = g.run(log_cap=gold["iterations"] + 8)
     assert st == B.DONE
-    assert_matches_golden(gold, log, g.read_image(), key + " persistent")
+    assert_matches_golden(gold, log, g.read_image(), f"{key} persistent {path}")
     if key == "hd9":
         assert g.run_form() == "persistent"
