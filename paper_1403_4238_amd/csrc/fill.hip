@@ -529,12 +529,9 @@ __device__ int stage_slots(int r, int tx, int ty, TargetStage *tg, Scratch &s, M
         const uint32_t up = (m << 1) | (w > 0 ? s.mbits[w - 1] >> 31 : 0u);        // slot - 1 known
         const uint32_t dn = (m >> 1) | (w + 1 < mw ? s.mbits[w + 1] << 31 : 0u);   // slot + 1 known
         uint32_t cs = 0, ce = 0;   // slots at the top / bottom of their column
-        int rr = (32 * w) % P;
-        for (int b = 0; b < 32; ++b) {
-            if (rr == 0) cs |= 1u << b;
-            if (rr == P - 1) ce |= 1u << b;
-            rr = rr + 1 == P ? 0 : rr + 1;
-        }
+        const int base = 32 * w;
+        for (int c = (base + P - 1) / P * P; c < base + 32; c += P) cs |= 1u << (c - base);
+        for (int c = (base + P) / P * P - 1; c < base + 32; c += P) ce |= 1u << (c - base);
         const uint32_t sb = m & (cs | ~up), eb = m & (ce | ~dn);
         s.sbits[w] = sb;
         s.ebits[w] = eb;
@@ -659,22 +656,17 @@ __device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, 
     __syncthreads();   // the copied pixels
     grad_pass<R>(L, S::half - R - 1, S::half + R + 2);
     __syncthreads();
-    // Window pixels off the front get (C, D) = (-1, 0) at once; front pixels
-    // go to a compact list so the costly evaluations fill whole waves.
+    // Front pixels of the window go to a compact list so the costly
+    // evaluations fill whole waves.  Pixels off the front already carry
+    // (C, D) = (-1, 0) in global memory and key -1 in LDS: a hole pixel off
+    // the front has never been on it (the front only gains hole pixels), a
+    // known one was set when it was filled (the copy) or at initialisation.
     const int ww = g.wx1 - g.wx0, nwin = ww * (g.wy1 - g.wy0);
     constexpr int WIN = LdsStage<R>::WIN;
     for (int t = threadIdx.x; t < nwin; t += blockDim.x) {
         const int x = g.wx0 + t % ww, y = g.wy0 + t / ww;
         const int wi = (y - (py - 2 * R - 1)) * WIN + (x - (px - 2 * R - 1));
-        if (on_front(v, x, y)) {
-            L.front[atomicAdd(&L.nfront, 1)] = (int16_t)wi;
-        } else {
-            const double2 cd = make_double2(-1.0, 0.0);
-            d.pcd[(int64_t)y * d.W + x] = cd;
-            L.wcd[wi] = cd;
-            const int b = (y / kBlock - g.aby0) * g.nabx + (x / kBlock - g.abx0);
-            L.bkey[b * 64 + (y & 7) * 8 + (x & 7)] = -1;
-        }
+        if (on_front(v, x, y)) L.front[atomicAdd(&L.nfront, 1)] = (int16_t)wi;
     }
     __syncthreads();
     const int nfront = L.nfront;
@@ -1034,6 +1026,10 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
             L.img[li] = pix;
             L.gray[li] = gv;
             L.conf[li] = v.C;
+            // off the front from now on
+            const int x = px + dx, y = py + dy;
+            d.pcd[dst] = make_double2(-1.0, 0.0);
+            L.bkey[((y / kBlock - g.aby0) * g.nabx + (x / kBlock - g.abx0)) * 64 + (y & 7) * 8 + (x & 7)] = -1;
         }
     }
     const int64_t remaining = v.remaining - filled;
@@ -1200,8 +1196,9 @@ __device__ uint64_t collect_slots(const uint64_t *fs, int ntiles, uint32_t tag, 
     for (int j = 0; j < per && j < 32; ++j)
         if ((int)threadIdx.x + T * j < ntiles) pend |= 1u << j;
     uint64_t best = ~0ull;   // minimum of (word >> 8)
-    int done = 0;
-    for (uint32_t spin = 0; spin < kSpinLimit; ++spin) {
+    // Each thread polls its own slots (no barrier per round), so the last
+    // report is seen one load latency after it lands.
+    for (uint32_t spin = 0; pend && spin < kSpinLimit; ++spin) {
         for (uint32_t m = pend; m; m &= m - 1) {
             const int j = __builtin_ctz(m);
             const uint64_t w = __hip_atomic_load(&fs[threadIdx.x + T * j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1210,12 +1207,9 @@ __device__ uint64_t collect_slots(const uint64_t *fs, int ntiles, uint32_t tag, 
                 best = (w >> 8) < best ? (w >> 8) : best;
             }
         }
-        if (!__syncthreads_or(pend != 0)) {
-            done = 1;
-            break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+        if (pend) __builtin_amdgcn_s_sleep(1);
     }
+    const int done = !__syncthreads_or(pend != 0);
     *ok = done;
     if (!done) return ~0ull;
     best = block_min_u64(best, s.u);
@@ -1358,7 +1352,6 @@ __device__ void fill_search(const JobDev &d, int ntiles, uint32_t epoch, SearchL
 template <int R>
 struct SearchLdsMfma {
     mtile::MfmaTile<R> tile;
-    tile::TargetLds tgt;
     mtile::FragTables<R> ft;
     uint64_t red[kSearchWaves];
     int32_t flag;
@@ -1387,9 +1380,19 @@ __device__ void fill_search_mfma(const JobDev &d, uint32_t epoch, SearchLdsMfma<
         if (!S.flag) break;
         uint64_t best = ~0ull;
         if (anyv) {
-            load_record<R>(&sy->rec[t % kGoCopies], &S.tgt);
+            // the target straight from this group's record (device-scope
+            // loads, see load_record) into the patch tables, then the
+            // shifted tables
+            const FillRec *rec = &sy->rec[t % kGoCopies];
+            mtile::build_patch<R>(
+                &S.ft,
+                [&](int sl) { return __hip_atomic_load(&rec->tpix[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); },
+                [&](int sl) {
+                    return (__hip_atomic_load(&rec->mbits[sl >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >>
+                            (sl & 31)) & 1u;
+                });
             __syncthreads();
-            mtile::build_tables<R>(&S.tgt, &S.ft);
+            mtile::build_tables<R>(&S.ft);
             __syncthreads();
             mtile::BFrags<R> b;
             mtile::load_frags<R>(&S.ft, b);

@@ -70,46 +70,46 @@ __device__ __forceinline__ void load_frags(const MfmaFrags *fr, BFrags<R> &b) {
     b.rowmask = fr->rowmask;
 }
 
-// Per-target tables a work-group builds in LDS from a TargetLds, from which
-// every wave reads its B operands with a few aligned LDS loads.  With
-// T(dy, x) the target word (RGB ^ 0x808080) at patch column x of row dy
-// where known, 0 elsewhere (also outside 0 <= x < P), and M(dy, x) its 0/1
-// known flag: tc[s][dy][i] = T(dy, i - 16 - s), so the four words lane
-// (n, g) needs, T(dy, 16 h + 4 g - n + j), start 16-byte aligned in copy
-// s = n mod 4; lw[dy][i] = M(dy, i - 16) | M(dy, i - 15) << 16.
+// Per-target tables a work-group builds in LDS, from which every wave reads
+// its B operands with a few aligned LDS loads.  With T(dy, x) the target
+// word (RGB ^ 0x808080) at patch column x of row dy where known, 0 elsewhere
+// (also outside 0 <= x < P), and M(dy, x) its 0/1 known flag:
+// tc[s][dy][i] = T(dy, i - 16 - s), so the four words lane (n, g) needs,
+// T(dy, 16 h + 4 g - n + j), start 16-byte aligned in copy s = n mod 4;
+// lw[dy][i] = M(dy, i - 16) | M(dy, i - 15) << 16.  Built in two passes:
+// the patch itself into tm / km (one slot per thread, with the per-wave
+// partial sums of T2', k and the row mask), then the shifted tables.
 template <int R>
 struct FragTables {
     static constexpr int P = 2 * R + 1;
     alignas(16) uint32_t tc[4][P][48];
     uint32_t lw[P][48];
+    uint32_t tm[P][P];   // T(dy, x)
+    uint8_t km[P][P];    // M(dy, x)
     int t2p[kSearchWaves], k[kSearchWaves];
     uint32_t rowmask[kSearchWaves];
 };
 
-template <int R>
-__device__ __forceinline__ void build_tables(const tile::TargetLds *t, FragTables<R> *ft) {
+// Pass 1, from the staged words (column-major slots x * P + dy) and the
+// known mask; `word(slot)` and `known(slot)` read them wherever they are.
+template <int R, class Word, class Known>
+__device__ __forceinline__ void build_patch(FragTables<R> *ft, Word word, Known known) {
     constexpr int P = 2 * R + 1;
-    auto known = [&](int x, int dy) { return x >= 0 && x < P && ((t->mbits[(x * P + dy) >> 5] >> ((x * P + dy) & 31)) & 1u); };
-    for (int e = threadIdx.x; e < 4 * P * 48; e += blockDim.x) {
-        const int s = e / (P * 48), dy = (e / 48) % P, i = e % 48;
-        const int x = i - 16 - s;
-        ft->tc[s][dy][i] = known(x, dy) ? (t->tpix[x * P + dy] ^ 0x00808080u) : 0u;
-    }
-    for (int e = threadIdx.x; e < P * 48; e += blockDim.x) {
-        const int dy = e / 48, i = e % 48;
-        ft->lw[dy][i] = (known(i - 16, dy) ? 1u : 0u) | (known(i - 15, dy) ? 1u << 16 : 0u);
-    }
-    // T2', k and the row mask: one slot per thread, reduced per wave
     int t2 = 0, kk = 0;
     uint32_t rows = 0;
-    for (int sl = threadIdx.x; sl < P * P; sl += blockDim.x)
-        if ((t->mbits[sl >> 5] >> (sl & 31)) & 1u) {
-            const uint32_t w = t->tpix[sl];
+    for (int sl = threadIdx.x; sl < P * P; sl += blockDim.x) {
+        const int x = sl / P, dy = sl - x * P;
+        const bool kn = known(sl);
+        const uint32_t w = kn ? word(sl) : 0u;
+        ft->tm[dy][x] = kn ? (w ^ 0x00808080u) : 0u;
+        ft->km[dy][x] = kn ? 1 : 0;
+        if (kn) {
             const int a = (int)(w & 255) - 128, b = (int)((w >> 8) & 255) - 128, c = (int)((w >> 16) & 255) - 128;
             t2 += a * a + b * b + c * c;
             kk += 1;
-            rows |= 1u << (sl % P);
+            rows |= 1u << dy;
         }
+    }
     for (int off = 32; off > 0; off >>= 1) {
         t2 += __shfl_xor(t2, off);
         kk += __shfl_xor(kk, off);
@@ -119,6 +119,31 @@ __device__ __forceinline__ void build_tables(const tile::TargetLds *t, FragTable
         ft->t2p[threadIdx.x >> 6] = t2;
         ft->k[threadIdx.x >> 6] = kk;
         ft->rowmask[threadIdx.x >> 6] = rows;
+    }
+}
+
+// Pass 2, after a barrier that publishes pass 1.
+template <int R>
+__device__ __forceinline__ void build_tables(FragTables<R> *ft) {
+    constexpr int P = 2 * R + 1, NT = 4 * P * 48, NL = P * 48, T = kSearchWaves * 64;
+#pragma unroll
+    for (int it = 0; it < (NT + T - 1) / T; ++it) {
+        const int e = threadIdx.x + it * T;
+        if (e < NT) {
+            const int s = e / (P * 48), r = e - s * (P * 48), dy = r / 48, i = r - dy * 48;
+            const int x = i - 16 - s;
+            ft->tc[s][dy][i] = (x >= 0 && x < P) ? ft->tm[dy][x] : 0u;
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < (NL + T - 1) / T; ++it) {
+        const int e = threadIdx.x + it * T;
+        if (e < NL) {
+            const int dy = e / 48, i = e - dy * 48, x = i - 16;
+            const uint32_t m0 = (x >= 0 && x < P) ? ft->km[dy][x] : 0u;
+            const uint32_t m1 = (x + 1 >= 0 && x + 1 < P) ? ft->km[dy][x + 1] : 0u;
+            ft->lw[dy][i] = m0 | (m1 << 16);
+        }
     }
 }
 
