@@ -255,21 +255,32 @@ __device__ __forceinline__ uint64_t score_tile(const JobDev &d, const BFrags<R> 
     const int t2 = b.t2p, kk = b.k;
     const uint32_t rowmask = b.rowmask;
     uint64_t best = ~0ull;
+    (void)rowmask;
 #pragma unroll
     for (int t = 0; t < kMfmaTilesPerWave; ++t) {
         // four independent accumulation chains keep the MFMA pipeline busy
         v4i c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0}, ch = {0, 0, 0, 0}, cl = {0, 0, 0, 0};
+        // Every patch row is multiplied (a row without a known pixel has
+        // zero B operands): without a branch per row the A loads of row
+        // dy + 1 are in flight while row dy is on the matrix cores.
+        const int base = (16 * t + n) * kMfmaStrideA + 16 * wave + 4 * g;
+        const int qbase = (16 * t + n) * kMfmaStrideQ + 32 * wave + 16 * g;
+        v4i a0 = *(const v4i *)&L.a[base], a1 = *(const v4i *)&L.a[base + 16], aq = *(const v4i *)&L.q[qbase];
 #pragma unroll
         for (int dy = 0; dy < P; ++dy) {
-            if (!((rowmask >> dy) & 1u)) continue;   // uniform: patch row without a known pixel
-            const int ly = 16 * t + n + dy;                   // A row = candidate row n of the tile
-            const v4i a0 = *(const v4i *)&L.a[ly * kMfmaStrideA + 16 * wave + 4 * g];
-            const v4i a1 = *(const v4i *)&L.a[ly * kMfmaStrideA + 16 * wave + 16 + 4 * g];
-            const v4i aq = *(const v4i *)&L.q[ly * kMfmaStrideQ + 32 * wave + 16 * g];
+            v4i n0 = a0, n1 = a1, nq = aq;   // A row = candidate row n + dy + 1 of the tile
+            if (dy + 1 < P) {
+                n0 = *(const v4i *)&L.a[base + (dy + 1) * kMfmaStrideA];
+                n1 = *(const v4i *)&L.a[base + (dy + 1) * kMfmaStrideA + 16];
+                nq = *(const v4i *)&L.q[qbase + (dy + 1) * kMfmaStrideQ];
+            }
             c0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b.c[dy][0], c0, 0, 0, 0);
             c1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b.c[dy][1], c1, 0, 0, 0);
             cl = __builtin_amdgcn_mfma_i32_16x16x64_i8(aq, b.l[dy], cl, 0, 0, 0);
             ch = __builtin_amdgcn_mfma_i32_16x16x64_i8(aq, b.h[dy], ch, 0, 0, 0);
+            a0 = n0;
+            a1 = n1;
+            aq = nq;
         }
         // C lane (n, g) holds rows 4g + i of column n.
 #pragma unroll
