@@ -42,6 +42,12 @@ TERM_PEAK = VALU_LANE_OPS * TERMS_PER_VALU_OP                # 117.96e12 terms/s
 MFMA_TERM_PEAK = 2.5e15
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of a kernel, from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# passes on this bench command, scaled by what the same counters read for a
+# plain device copy of known size (see profiles/).  Only valid for the kernel
+# code they were taken on; a kernel not listed reports null.
+TRAFFIC_BYTES_PER_LAUNCH = {}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -55,11 +61,11 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=4.0, help="serve: device memory budget")
     ap.add_argument("--patch", type=int, default=9)
     ap.add_argument("--window", action="store_true", help="alpha = 1 search window (3x the hole bbox)")
-    ap.add_argument("--form", default="stream", choices=["stream", "plain", "persistent"],
+    ap.add_argument("--form", default="persistent", choices=["persistent", "stream", "plain"],
                     help="timed form (kernel events need a non-graph form)")
-    ap.add_argument("--iters-per-check", type=int, default=32)
+    ap.add_argument("--iters-per-check", type=int, default=128)
     ap.add_argument("--tile-rows", type=int, default=0)
-    ap.add_argument("--path", default="simt", choices=["simt", "mfma"], help="exemplar-search kernel")
+    ap.add_argument("--path", default="mfma", choices=["mfma", "simt"], help="exemplar-search kernel")
     ap.add_argument("--no-other-form", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -321,22 +327,33 @@ def main():
     achieved = terms_per_launch / (avg_kernel_ms * 1e-3)
     persistent = res["run_form"] == "persistent"
     peak = MFMA_TERM_PEAK if a.path == "mfma" else TERM_PEAK
+    r = job.patch_radius
+    kernel = ((f"k_fill_mfma<R={r}>" if a.path == "mfma" else f"k_fill<R={r}>") if persistent else
+              f"k_search_mfma<R={r}>" if a.path == "mfma" else f"k_search<R={r},NY={a.tile_rows or 8}>")
     # HBM bytes a search must move at least: the RGBX words of the candidate
     # windows' rows once (the frame is read through L2 / MALL every search).
     rx0, ry0, rx1, ry1 = res["rect"]
-    r = job.patch_radius
     bytes_per_launch = 4 * (min(rx1 + r, job.width) - max(rx0 - r, 0)) * (min(ry1 + r, job.height) - max(ry0 - r, 0))
 
-    # The other forms, untimed by events: the plain form (host check every
-    # iteration) and the graph form (hipGraph replay of the same iterations).
+    # The other forms.  The stream form runs the one-search-per-launch kernels,
+    # so it also gives the search kernel's own launch time and rate; the
+    # graph form replays them as a hipGraph (no events inside).
     others = {}
     if not a.no_other_form:
-        for form in ("plain", "graph"):
-            if form == a.form:
+        for form in ("stream", "graph"):
+            if form == res["run_form"]:
                 continue
-            o = timed_removals(job, 1, 0, form, a.iters_per_check, a.tile_rows, timing=False, path=a.path)
-            others[form] = {"ms_per_removal": round(1000 * o["seconds"], 2),
-                            "patch_evals_per_s": round(sum(o["iters"]) * o["candidates"] / o["seconds"], 1)}
+            o = timed_removals(job, 1, 0, form, a.iters_per_check, a.tile_rows, timing=(form == "stream"), path=a.path)
+            rec = {"ms_per_removal": round(1000 * o["seconds"], 2),
+                   "patch_evals_per_s": round(sum(o["iters"]) * o["candidates"] / o["seconds"], 1)}
+            if form == "stream":
+                sk_ms = o["kernel_ms"] / max(o["searches"], 1)
+                sk_rate = terms_per_removal / max(len(log), 1) / (sk_ms * 1e-3)
+                rec["search_kernel"] = {
+                    "kernel": f"k_search_mfma<R={r}>" if a.path == "mfma" else f"k_search<R={r},NY={a.tile_rows or 8}>",
+                    "avg_launch_us": round(1000 * sk_ms, 3), "achieved": round(sk_rate / 1e12, 3),
+                    "peak": round(peak / 1e12, 2), "unit": "Tterm/s", "frac": round(sk_rate / peak, 5)}
+            others[form] = rec
 
     line = {
         "metric": "masked-SSD patch evals/s (ms per 1080p removal alongside)",
@@ -364,11 +381,10 @@ def main():
         "parity": golden_check(job, a, log, res["image"]),
         "roofline": {
             "bound": "mfma" if a.path == "mfma" else "alu",
-            "kernel": (f"k_fill<R={r}> (persistent: search and commit)" if persistent else
-                       f"k_search_mfma<R={r}>" if a.path == "mfma" else f"k_search<R={r},NY={a.tile_rows or 8}>"),
+            "kernel": kernel,
             "achieved": round(achieved / 1e12, 3), "peak": round(peak / 1e12, 2),
-            "unit": "Tterm/s", "frac": round(achieved / peak, 4),
-            "traffic": None,
+            "unit": "Tterm/s", "frac": round(achieved / peak, 5),
+            "traffic": TRAFFIC_BYTES_PER_LAUNCH.get(kernel),
             "avg_launch_us": round(1000 * avg_kernel_ms, 3), "launches_timed": res["searches"],
             "terms_per_launch": round(terms_per_launch),
             "min_hbm_bytes_per_launch": bytes_per_launch,
