@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="hd", choices=["hd", "vga", "small", "batch", "serve"])
+    ap.add_argument("--workload", default="hd", choices=["hd", "vga", "small", "batch", "serve", "sweep"])
     ap.add_argument("--jobs", type=int, default=32, help="serve: number of jobs")
     ap.add_argument("--graph-iters", type=int, default=16, help="batch / serve: iterations per replay")
     ap.add_argument("--capacity", type=int, default=16, help="serve: batch slots")
@@ -165,6 +165,58 @@ def golden_check(job, a, log, image):
           and gold["log_sha256"] == log_sha256(log)
           and gold["final_rgb_sha256"] == hashlib.sha256(image.tobytes()).hexdigest())
     return "bit-exact vs stored oracle" if ok else "MISMATCH vs stored oracle"
+
+
+def sweep_bench(a):
+    """The paper's trade-off study in kind: search factor alpha x patch size on
+    stand-ins shaped like its four photographs (Table 3).  One warm-up and one
+    timed removal per configuration, persistent form; the MFMA search for
+    P <= 13, the SIMT search for P = 17."""
+    import torch
+    from paper_1403_4238_amd import binding as B
+    from paper_1403_4238_amd import synth
+    alphas = [(1, 20), (1, 5), (1, 2), (1, 1), (2, 1), None]
+    rows = []
+    t_all = time.perf_counter()
+    for name, *_ in synth.PAPER_IMAGES:
+        for patch in (9, 13, 17):
+            for alpha in alphas:
+                job = synth.paper(name, patch=patch, alpha=alpha)
+                path = B.PATH_MFMA if patch <= 13 else B.PATH_SIMT
+                mk = lambda: B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha,
+                                         form="persistent", iters_per_check=a.iters_per_check, path=path)
+                try:
+                    w = mk()
+                except B.InpaintError as e:   # no candidate window fits (thin strip, small alpha)
+                    rows.append({"image": name, "patch": patch,
+                                 "alpha": None if alpha is None else f"{alpha[0]}/{alpha[1]}",
+                                 "error": B.inpaint_status_string(e.status)})
+                    continue
+                w.run()
+                w.close()
+                g = mk()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, n, _ = g.run()
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                log = g.read_log(0, n)
+                rect, cands = g.search_info()
+                k = np.asarray(log["known_k"], dtype=np.float64)
+                rows.append({
+                    "image": name, "patch": patch,
+                    "alpha": None if alpha is None else f"{alpha[0]}/{alpha[1]}",
+                    "search_area": [rect[2] - rect[0], rect[3] - rect[1]],
+                    "candidates_per_search": cands, "iterations": n,
+                    "ms_per_removal": round(1000 * dt, 3),
+                    "patch_evals_per_s": round(n * cands / dt, 1),
+                    "mean_ssd_per_known_value": round(float(np.mean(np.asarray(log["ssd"], dtype=np.float64) / (3 * k))), 3),
+                    "path": "mfma" if path == B.PATH_MFMA else "simt", "form": g.run_form(),
+                })
+                g.close()
+    print(json.dumps({"metric": "alpha x patch-size sweep on paper-shaped stand-ins (ms per removal)",
+                      "unit": "ms per removal", "n_gpus": 1, "data": "synthetic (seeded)",
+                      "seconds_total": round(time.perf_counter() - t_all, 2), "sweep": rows}), flush=True)
 
 
 def batch_bench(a):
@@ -311,6 +363,8 @@ def main():
         return batch_bench(a)
     if a.workload == "serve":
         return serve_bench(a)
+    if a.workload == "sweep":
+        return sweep_bench(a)
     job = make_job(a)
     res = timed_removals(job, a.steps, a.warmup, a.form, a.iters_per_check, a.tile_rows, path=a.path)
     n_steps = a.steps

@@ -24,6 +24,10 @@ Workloads:
            2-10%, 9x9 patch.
   serving  Poisson arrivals of jobs 256x256 .. 2048x1536, 1-10% holes with
            1-3 blobs, patch 7/9/11.
+  paper    stand-ins shaped like the paper's four photographs (Table 3):
+           WalkingMan 512x384 with a 78x126 object, River 480x639 with a
+           59x93 object, DivingMan 576x384 with a 155x186 object, Hill
+           1024x550 with a 1024x10 strip; value-noise + edge content.
 """
 from __future__ import annotations
 
@@ -350,3 +354,55 @@ WORKLOADS = {
     "vga": vga,
     "hd": hd,
 }
+
+
+def mask_object(W: int, H: int, rng: np.random.Generator, obj_w: int, obj_h: int, margin: int) -> np.ndarray:
+    """An irregular object whose bounding box is exactly obj_w x obj_h.
+
+    The inscribed ellipse of the box (it touches all four sides) plus three
+    to six discs centred in the middle half of the box, clipped to the box;
+    the box is placed at a seeded position at least ``margin`` pixels from
+    the border.
+    """
+    x0 = int(rng.integers(margin, W - margin - obj_w + 1))
+    y0 = int(rng.integers(margin, H - margin - obj_h + 1))
+    yy, xx = np.mgrid[0:obj_h, 0:obj_w]
+    # (2x - (w-1))^2 h^2 + (2y - (h-1))^2 w^2 <= w^2 h^2
+    a2, b2 = obj_w * obj_w, obj_h * obj_h
+    inside = (2 * xx - (obj_w - 1)) ** 2 * b2 + (2 * yy - (obj_h - 1)) ** 2 * a2 <= a2 * b2
+    for _ in range(int(rng.integers(3, 7))):
+        cx = int(rng.integers(obj_w // 4, obj_w - obj_w // 4))
+        cy = int(rng.integers(obj_h // 4, obj_h - obj_h // 4))
+        rad = int(rng.integers(max(2, min(obj_w, obj_h) // 8), max(3, min(obj_w, obj_h) // 4) + 1))
+        inside |= (xx - cx) ** 2 + (yy - cy) ** 2 <= rad * rad
+    m = np.zeros((H, W), dtype=np.uint8)
+    m[y0:y0 + obj_h, x0:x0 + obj_w] = inside
+    return m
+
+
+# name, width, height, object width, object height (Table 3)
+PAPER_IMAGES = [
+    ("WalkingMan", 512, 384, 78, 126),
+    ("River", 480, 639, 59, 93),
+    ("DivingMan", 576, 384, 155, 186),
+    ("Hill", 1024, 550, 1024, 10),
+]
+
+
+def paper(name: str, seed: int = 6, patch: int = 9, alpha: tuple | None = None) -> Job:
+    """Stand-in for one of the paper's photographs; alpha None = full search."""
+    idx = [n for n, *_ in PAPER_IMAGES].index(name)
+    _, W, H, ow, oh = PAPER_IMAGES[idx]
+    r_img, r_mask = _rngs(seed * 16 + idx, 2)
+    rgb = content_noise_edges(W, H, r_img)
+    if ow >= W:   # a strip across the whole width
+        y0 = int(r_mask.integers(H // 3, 2 * H // 3))
+        mask = np.zeros((H, W), dtype=np.uint8)
+        mask[y0:y0 + oh, :] = 1
+    else:
+        mask = mask_object(W, H, r_mask, ow, oh, 9)
+    job = Job(f"{name}-{W}x{H}-p{patch}-" + ("full" if alpha is None else f"a{alpha[0]}/{alpha[1]}"),
+              rgb, mask, patch // 2)
+    if alpha is not None:
+        job.search_mode, job.alpha = SEARCH_ALPHA, alpha
+    return job

@@ -561,3 +561,14 @@ def test_create_rejects_bad_arguments(O):
     grid[::4, ::4] = 1
     with pytest.raises(O.OracleError):
         O.Oracle(rgb, grid, 4)
+
+
+def test_paper_standins_have_the_papers_object_sizes():
+    # Table 3's image and object sizes; the alpha windows of the paper's
+    # total-time tables follow from the object size (pinned above).
+    for name, W, H, ow, oh in synth.PAPER_IMAGES:
+        job = synth.paper(name)
+        assert job.rgb.shape == (H, W, 3) and job.mask.shape == (H, W)
+        ys, xs = np.nonzero(job.mask)
+        assert (xs.max() - xs.min() + 1, ys.max() - ys.min() + 1) == (ow, oh), name
+        assert job.sha256() == synth.paper(name).sha256()   # seeded
