@@ -58,7 +58,9 @@ TRAFFIC_BYTES_PER_LAUNCH = {
     ("k_fill_mfma<R=4>", "hd-1920x1080-p9-full"): {
         "bytes": 42789415, "fetch_kib": 16888.57, "write_kib": 8009.39,
         "sources": ["inpaint_dev.h", "search_tile.h", "search_mfma_tile.h", "fill.hip"],
-        "sha256_16": "2acce3a8c805a335"},
+        # (re-hashed after a change to the SIMT tile code that left this
+        # kernel's machine code identical, checked on its assembly)
+        "sha256_16": "452d611e3f74ba8d"},
 }
 
 
@@ -91,7 +93,10 @@ def parse():
                     help="timed form (kernel events need a non-graph form)")
     ap.add_argument("--iters-per-check", type=int, default=128)
     ap.add_argument("--tile-rows", type=int, default=0)
-    ap.add_argument("--path", default="mfma", choices=["mfma", "simt"], help="exemplar-search kernel")
+    ap.add_argument("--path", default="mfma", choices=["mfma", "simt", "direct"],
+                    help="exemplar-search kernel (direct: SIMT without LDS staging)")
+    ap.add_argument("--sweep-part", default="both", choices=["both", "alpha", "lds"],
+                    help="sweep: the persistent alpha x P timings, the LDS staging study, or both")
     ap.add_argument("--no-other-form", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -107,13 +112,24 @@ def make_job(a):
     return synth.small()
 
 
+def path_id(name):
+    from paper_1403_4238_amd import binding as B
+    return {"mfma": B.PATH_MFMA, "simt": B.PATH_SIMT, "direct": B.PATH_SIMT_DIRECT}[name]
+
+
+def search_kernel_name(path, r, tile_rows):
+    if path == "mfma":
+        return f"k_search_mfma<R={r}>"
+    return f"k_search{'_direct' if path == 'direct' else ''}<R={r},NY={tile_rows or 8}>"
+
+
 def timed_removals(job, n_steps, n_warmup, form, iters_per_check, tile_rows, timing=True, path="simt"):
     """Runs n_warmup + n_steps removals; times the last n_steps together."""
     import torch
     from paper_1403_4238_amd import binding as B
     ctxs = [B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, rect=job.rect,
                         form=form, iters_per_check=iters_per_check, tile_rows=tile_rows,
-                        path=B.PATH_MFMA if path == "mfma" else B.PATH_SIMT)
+                        path=path_id(path))
             for _ in range(n_warmup + n_steps)]
     for c in ctxs[:n_warmup]:
         c.run()
@@ -197,7 +213,10 @@ def sweep_bench(a):
     """The paper's trade-off study in kind: search factor alpha x patch size on
     stand-ins shaped like its four photographs (Table 3).  One warm-up and one
     timed removal per configuration, persistent form; the MFMA search for
-    P <= 13, the SIMT search for P = 17."""
+    P <= 13, the SIMT search for P = 17.  Each configuration also runs its
+    local-memory study: one stream-form removal with the SIMT search staged
+    in LDS and one reading device memory directly, timing every search
+    launch (both must give the same fill log)."""
     import torch
     from paper_1403_4238_amd import binding as B
     from paper_1403_4238_amd import synth
@@ -211,35 +230,47 @@ def sweep_bench(a):
                 path = B.PATH_MFMA if patch <= 13 else B.PATH_SIMT
                 mk = lambda: B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha,
                                          form="persistent", iters_per_check=a.iters_per_check, path=path)
+                row = {"image": name, "patch": patch, "alpha": None if alpha is None else f"{alpha[0]}/{alpha[1]}"}
                 try:
-                    w = mk()
+                    mk().close()
                 except B.InpaintError as e:   # no candidate window fits (thin strip, small alpha)
-                    rows.append({"image": name, "patch": patch,
-                                 "alpha": None if alpha is None else f"{alpha[0]}/{alpha[1]}",
-                                 "error": B.inpaint_status_string(e.status)})
+                    row["error"] = B.inpaint_status_string(e.status)
+                    rows.append(row)
                     continue
-                w.run()
-                w.close()
-                g = mk()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                st, n, _ = g.run()
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t0
-                log = g.read_log(0, n)
-                rect, cands = g.search_info()
-                k = np.asarray(log["known_k"], dtype=np.float64)
-                rows.append({
-                    "image": name, "patch": patch,
-                    "alpha": None if alpha is None else f"{alpha[0]}/{alpha[1]}",
-                    "search_area": [rect[2] - rect[0], rect[3] - rect[1]],
-                    "candidates_per_search": cands, "iterations": n,
-                    "ms_per_removal": round(1000 * dt, 3),
-                    "patch_evals_per_s": round(n * cands / dt, 1),
-                    "mean_ssd_per_known_value": round(float(np.mean(np.asarray(log["ssd"], dtype=np.float64) / (3 * k))), 3),
-                    "path": "mfma" if path == B.PATH_MFMA else "simt", "form": g.run_form(),
-                })
-                g.close()
+                log = None
+                if a.sweep_part != "lds":
+                    w = mk()
+                    w.run()
+                    w.close()
+                    g = mk()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st, n, _ = g.run()
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    log = g.read_log(0, n)
+                    rect, cands = g.search_info()
+                    k = np.asarray(log["known_k"], dtype=np.float64)
+                    row.update({
+                        "search_area": [rect[2] - rect[0], rect[3] - rect[1]],
+                        "candidates_per_search": cands, "iterations": n,
+                        "ms_per_removal": round(1000 * dt, 3),
+                        "patch_evals_per_s": round(n * cands / dt, 1),
+                        "mean_ssd_per_known_value": round(float(np.mean(np.asarray(log["ssd"], dtype=np.float64) / (3 * k))), 3),
+                        "path": "mfma" if path == B.PATH_MFMA else "simt", "form": g.run_form()})
+                    g.close()
+                if a.sweep_part != "alpha":
+                    lds = {}
+                    for pth in ("simt", "direct"):
+                        o = timed_removals(job, 1, 0, "stream", a.iters_per_check, 0, timing=True, path=pth)
+                        lds[pth] = {"search_us": round(1000 * o["kernel_ms"] / max(o["searches"], 1), 3),
+                                    "ms_per_removal": round(1000 * o["seconds"], 3)}
+                        if log is None:
+                            log = o["log"]
+                        lds[pth]["same_log"] = bool(np.array_equal(o["log"], log))
+                    row["lds_study"] = {"staged": lds["simt"], "direct": lds["direct"],
+                                        "search_time_ratio": round(lds["direct"]["search_us"] / lds["simt"]["search_us"], 3)}
+                rows.append(row)
     print(json.dumps({"metric": "alpha x patch-size sweep on paper-shaped stand-ins (ms per removal)",
                       "unit": "ms per removal", "n_gpus": 1, "data": "synthetic (seeded)",
                       "seconds_total": round(time.perf_counter() - t_all, 2), "sweep": rows}), flush=True)
@@ -433,7 +464,7 @@ def main():
     peak = MFMA_TERM_PEAK if a.path == "mfma" else TERM_PEAK
     r = job.patch_radius
     kernel = ((f"k_fill_mfma<R={r}>" if a.path == "mfma" else f"k_fill<R={r}>") if persistent else
-              f"k_search_mfma<R={r}>" if a.path == "mfma" else f"k_search<R={r},NY={a.tile_rows or 8}>")
+              search_kernel_name(a.path, r, a.tile_rows))
     # HBM bytes a search must move at least: the RGBX words of the candidate
     # windows' rows once (the frame is read through L2 / MALL every search).
     rx0, ry0, rx1, ry1 = res["rect"]
@@ -454,7 +485,7 @@ def main():
                 sk_ms = o["kernel_ms"] / max(o["searches"], 1)
                 sk_rate = terms_per_removal / max(len(log), 1) / (sk_ms * 1e-3)
                 rec["search_kernel"] = {
-                    "kernel": f"k_search_mfma<R={r}>" if a.path == "mfma" else f"k_search<R={r},NY={a.tile_rows or 8}>",
+                    "kernel": search_kernel_name(a.path, r, a.tile_rows),
                     "avg_launch_us": round(1000 * sk_ms, 3), "achieved": round(OPS_PER_TERM * sk_rate / 1e12, 3),
                     "peak": round(OPS_PER_TERM * peak / 1e12, 2), "unit": "TOP/s", "frac": round(sk_rate / peak, 5)}
             others[form] = rec

@@ -78,6 +78,13 @@ extern "C" {
 #define INPAINT_PATH_AUTO 0
 #define INPAINT_PATH_SIMT 1      /* integer dot-product SSD on the VALU      */
 #define INPAINT_PATH_MFMA 2      /* int8 matrix-core cross term (exact)      */
+/* The SIMT search with no LDS staging: each lane reads its source words from
+ * device memory through the vector caches, as the paper's kernel without
+ * local memory does (Alg. 1, against the local-memory kernel of Alg. 2).
+ * Same results; slower.  It exists for that comparison: PLAIN, STREAM and
+ * GRAPH forms only (PERSISTENT runs as STREAM), and inpaint_batch_step
+ * searches every attached job with the staged kernel. */
+#define INPAINT_PATH_SIMT_DIRECT 3
 
 typedef struct {
     const uint8_t *data;   /* host pixels, row-major, 8 bits per channel     */

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(PKG, "libinpaint.so")
 OK, DONE = 0, 1
 INVALID_ARGUMENT, NO_CANDIDATE, OUT_OF_MEMORY, DEVICE = -1, -2, -3, -4
 SEARCH_FULL, SEARCH_ALPHA, SEARCH_RECT = 0, 1, 2
-PATH_AUTO, PATH_SIMT, PATH_MFMA = 0, 1, 2
+PATH_AUTO, PATH_SIMT, PATH_MFMA, PATH_SIMT_DIRECT = 0, 1, 2, 3
 FORM_PLAIN, FORM_STREAM, FORM_GRAPH, FORM_PERSISTENT = 0, 1, 2, 3
 FORMS = {"plain": FORM_PLAIN, "stream": FORM_STREAM, "graph": FORM_GRAPH, "persistent": FORM_PERSISTENT}
 FORM_NAMES = {v: k for k, v in FORMS.items()}

@@ -181,6 +181,11 @@ hipError_t launch_commit(const JobDev &d, hipStream_t s);
 hipError_t launch_search(const JobDev &d, bool query, int r, int rx0, int ry0, int rx1, int ry1,
                          int tile_rows, int ntx, int nty, hipStream_t s,
                          hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+// The same search without LDS staging (source words read from the padded
+// plane through the vector caches).
+hipError_t launch_search_direct(const JobDev &d, bool query, int r, int rx0, int ry0, int rx1, int ry1,
+                                int tile_rows, int ntx, int nty, hipStream_t s,
+                                hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 bool mfma_supported(int r);
 // int8-MFMA form of the search; same tiling as launch_search with tile_rows 16.
 hipError_t launch_search_mfma(const JobDev &d, bool query, int r, int rx0, int ry0, int rx1, int ry1, int ntx, int nty,

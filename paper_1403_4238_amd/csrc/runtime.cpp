@@ -122,6 +122,7 @@ struct inpaint_ctx {
     int64_t candidates = 0;
     inpaint_rect rect{};      // image-clipped search rect (reported)
     bool mfma = false;        // search on the matrix cores
+    bool direct = false;      // SIMT search without LDS staging
     int32_t run_form = INPAINT_FORM_PLAIN;   // form inpaint_run uses
     uint32_t epoch = 0;       // persistent dispatches so far
     int32_t sticky = 0;
@@ -203,7 +204,7 @@ static int32_t check_params(int32_t W, int32_t H, const inpaint_params *p, std::
         *why = "search rect has x0 > x1 or y0 > y1";
         return INPAINT_INVALID_ARGUMENT;
     }
-    if (p->path < INPAINT_PATH_AUTO || p->path > INPAINT_PATH_MFMA) {
+    if (p->path < INPAINT_PATH_AUTO || p->path > INPAINT_PATH_SIMT_DIRECT) {
         *why = "unknown path";
         return INPAINT_INVALID_ARGUMENT;
     }
@@ -246,6 +247,7 @@ static bool persistent_fits(const inpaint_ctx *c) {
     const JobDev &d = c->d;
     const int ntiles = d.ntx * d.nty;
     // (the committer scans at most 32 slots per thread)
+    if (c->direct) return false;
     if ((!c->mfma && d.tile_rows != kFillTileRows) || ntiles <= 0 || ntiles > 32 * kCommitThreads) return false;
     if ((int64_t)d.W * d.H > (1ll << kSlotIndexBits)) return false;   // slot word index field
     int dev = 0, coop = 0, cus = 0, per_cu = 0;
@@ -401,6 +403,7 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     d.rx1 = std::max(k[2], k[0]);
     d.ry1 = std::max(k[3], k[1]);
     c->mfma = p->path == INPAINT_PATH_MFMA;
+    c->direct = p->path == INPAINT_PATH_SIMT_DIRECT;
     set_tiles(d, c->mfma ? kMfmaTileRows : (p->tile_rows ? p->tile_rows : kDefaultTileRows), c->mfma ? d.r : 0);
 
     // Priority blocks: the hole's bbox grown by 2r+1 (how far a fill can
@@ -470,6 +473,9 @@ int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t tx, int32_t ty, int32_t 
     HIP_OR_FAIL(ctx, launch_stage_query(q, tx, ty, r, s), "stage");
     if (ctx->mfma && mfma_supported(r))
         HIP_OR_FAIL(ctx, launch_search_mfma(q, true, r, q.rx0, q.ry0, q.rx1, q.ry1, q.ntx, q.nty, s), "search");
+    else if (ctx->direct)
+        HIP_OR_FAIL(ctx, launch_search_direct(q, true, r, q.rx0, q.ry0, q.rx1, q.ry1, q.tile_rows, q.ntx, q.nty, s),
+                    "search");
     else
         HIP_OR_FAIL(ctx, launch_search(q, true, r, q.rx0, q.ry0, q.rx1, q.ry1, q.tile_rows, q.ntx, q.nty, s), "search");
     HIP_OR_FAIL(ctx, launch_reduce_partials(q, q.ntx * q.nty, dkey, s), "reduce");
@@ -502,6 +508,8 @@ static hipError_t enqueue_iteration(inpaint_ctx *ctx, hipStream_t s, int slot = 
     hipEvent_t e0 = slot >= 0 ? ctx->ev0[slot] : nullptr, e1 = slot >= 0 ? ctx->ev1[slot] : nullptr;
     if (ctx->mfma)
         e = launch_search_mfma(d, false, d.r, d.rx0, d.ry0, d.rx1, d.ry1, d.ntx, d.nty, s, e0, e1);
+    else if (ctx->direct)
+        e = launch_search_direct(d, false, d.r, d.rx0, d.ry0, d.rx1, d.ry1, d.tile_rows, d.ntx, d.nty, s, e0, e1);
     else
         e = launch_search(d, false, d.r, d.rx0, d.ry0, d.rx1, d.ry1, d.tile_rows, d.ntx, d.nty, s, e0, e1);
     if (e == hipSuccess) e = launch_commit(d, s);

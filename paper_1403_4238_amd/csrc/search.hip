@@ -1,6 +1,8 @@
 // findBestPatch on gfx950, one search per launch: every work-group stages
 // and scores one tile (see search_tile.h) and writes the tile's minimum key
-// to the partials; the commit kernel reduces them.
+// to the partials; the commit kernel reduces them.  k_search_direct is the
+// same search without LDS staging, the paper's kernel without local memory
+// (Alg. 1 as against Alg. 2), kept for that comparison.
 #include <hip/hip_ext.h>
 
 #include "search_tile.h"
@@ -11,6 +13,19 @@ namespace {
 
 using tile::ScalarTarget;
 using tile::TileGeom;
+
+// Minimum over the work-group of the wave minima, written to out[t].
+__device__ __forceinline__ void write_tile_min(uint64_t best, int t, uint64_t *__restrict__ out, uint64_t *red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t b = red[0];
+#pragma unroll
+        for (int w = 1; w < kSearchWaves; ++w) b = red[w] < b ? red[w] : b;
+        out[t] = b;
+    }
+}
 
 // Stages and scores one tile and writes its minimum key to out[t].  `live`
 // (uniform) is false when the fill loop has nothing pending: the tile is then
@@ -29,16 +44,7 @@ __device__ __forceinline__ void search_tile(const JobDev &d, const TargetStage *
         return;
     }
     const ScalarTarget view{(tile::ConstTarget *)tg};
-    const uint64_t best = tile::wave_min_u64(tile::score_tile<R, NY>(d, view, tx0, ty0, vmask, lds));
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) red[wave] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t b = red[0];
-#pragma unroll
-        for (int w = 1; w < kSearchWaves; ++w) b = red[w] < b ? red[w] : b;
-        out[t] = b;
-    }
+    write_tile_min(tile::wave_min_u64(tile::score_tile<R, NY>(d, view, tx0, ty0, vmask, lds)), t, out, red);
 }
 
 // Consecutive work-groups are dispatched round-robin over the 8 XCDs; remap
@@ -67,6 +73,30 @@ __global__ __launch_bounds__(kSearchWaves * 64) void k_search(JobDev d, int quer
     search_tile<R, NY>(d, query ? d.qtgt : d.tgt, live, rx0, ry0, rx1, ry1, ntx, t, d.partials, lds, red);
 }
 
+// One tile scored straight from the padded plane (no LDS tile); otherwise
+// as k_search.
+template <int R, int NY>
+__global__ __launch_bounds__(kSearchWaves * 64) void k_search_direct(JobDev d, int query, int rx0, int ry0,
+                                                                     int rx1, int ry1, int ntx, int ntiles) {
+    __shared__ uint64_t red[kSearchWaves];
+    const int t = xcd_band_tile((int)blockIdx.x, (int)gridDim.x);
+    if (t >= ntiles) return;
+    bool live = true;
+    if (!query) {
+        const IterState *st = d.st;
+        live = !(st->done || st->error || !st->pending || st->iter >= st->iter_limit);
+    }
+    int tx0, ty0;
+    tile::tile_origin<R, NY>(rx0, ry0, ntx, t, &tx0, &ty0);
+    const uint32_t vmask = tile::tile_valid<R, NY>(d, tx0, ty0, rx1, ry1);
+    if (!__syncthreads_or(live && vmask != 0)) {
+        if (threadIdx.x == 0 && live) d.partials[t] = ~0ull;
+        return;
+    }
+    const ScalarTarget view{(tile::ConstTarget *)(query ? d.qtgt : d.tgt)};
+    write_tile_min(tile::wave_min_u64(tile::score_direct<R, NY>(d, view, tx0, ty0, vmask)), t, d.partials, red);
+}
+
 // Persistent form over many images: work-groups stride over a static list of
 // (image slot, tile) items; finished images cost one state read per item.
 template <int R, int NY>
@@ -88,30 +118,31 @@ __global__ __launch_bounds__(kSearchWaves * 64) void k_search_batched(const JobD
     }
 }
 
-template <int R, int NY>
+template <int R, int NY, bool DIRECT>
 hipError_t launch_search_t(const JobDev &d, bool query, int rx0, int ry0, int rx1, int ry1, int ntx,
                            int nty, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
     const int ntiles = ntx * nty;
     if (ntiles <= 0) return hipSuccess;
     const int grid = (ntiles + 7) / 8 * 8;
+    auto kernel = DIRECT ? k_search_direct<R, NY> : k_search<R, NY>;
     if (start) {
         // The runtime stamps these events with the kernel's own begin / end.
-        hipExtLaunchKernelGGL((k_search<R, NY>), dim3(grid), dim3(kSearchWaves * 64), 0, s, start, stop, 0, d,
+        hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kSearchWaves * 64), 0, s, start, stop, 0, d,
                               query ? 1 : 0, rx0, ry0, rx1, ry1, ntx, ntiles);
     } else {
-        hipLaunchKernelGGL((k_search<R, NY>), dim3(grid), dim3(kSearchWaves * 64), 0, s, d, query ? 1 : 0, rx0,
-                           ry0, rx1, ry1, ntx, ntiles);
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kSearchWaves * 64), 0, s, d, query ? 1 : 0, rx0, ry0, rx1,
+                           ry1, ntx, ntiles);
     }
     return hipGetLastError();
 }
 
-template <int R>
+template <int R, bool DIRECT = false>
 hipError_t launch_search_r(const JobDev &d, bool query, int rx0, int ry0, int rx1, int ry1, int tile_rows,
                            int ntx, int nty, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (tile_rows) {
-        case 4: return launch_search_t<R, 4>(d, query, rx0, ry0, rx1, ry1, ntx, nty, s, e0, e1);
-        case 8: return launch_search_t<R, 8>(d, query, rx0, ry0, rx1, ry1, ntx, nty, s, e0, e1);
-        case 16: return launch_search_t<R, 16>(d, query, rx0, ry0, rx1, ry1, ntx, nty, s, e0, e1);
+        case 4: return launch_search_t<R, 4, DIRECT>(d, query, rx0, ry0, rx1, ry1, ntx, nty, s, e0, e1);
+        case 8: return launch_search_t<R, 8, DIRECT>(d, query, rx0, ry0, rx1, ry1, ntx, nty, s, e0, e1);
+        case 16: return launch_search_t<R, 16, DIRECT>(d, query, rx0, ry0, rx1, ry1, ntx, nty, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
@@ -142,6 +173,21 @@ hipError_t launch_search(const JobDev &d, bool query, int r, int rx0, int ry0, i
         case 6: return launch_search_r<6>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
         case 7: return launch_search_r<7>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
         case 8: return launch_search_r<8>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_search_direct(const JobDev &d, bool query, int r, int rx0, int ry0, int rx1, int ry1,
+                                int tile_rows, int ntx, int nty, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    switch (r) {
+        case 1: return launch_search_r<1, true>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 2: return launch_search_r<2, true>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 3: return launch_search_r<3, true>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 4: return launch_search_r<4, true>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 5: return launch_search_r<5, true>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 6: return launch_search_r<6, true>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 7: return launch_search_r<7, true>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
+        case 8: return launch_search_r<8, true>(d, query, rx0, ry0, rx1, ry1, tile_rows, ntx, nty, s, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }

@@ -23,7 +23,9 @@
 // column x0 + l and NY consecutive rows; for each dx it reads the NY + 2r
 // source words of its column once and reuses each for every (dy, candidate)
 // pair that needs it.  The masks are uniform across the wave, so masked
-// offsets are skipped with scalar branches and cost nothing.  Scores reduce
+// offsets are skipped with scalar branches and cost nothing.  (score_direct
+// runs the same scoring reading the plane in device memory instead of the
+// LDS tile, for the comparison with a search without local memory.)  Scores reduce
 // to keys (ssd << 32 | raster index): the minimum key is the
 // (ssd, index)-lexicographic minimum, i.e. ties go to the lowest raster
 // index.  No SSD array is ever written.
@@ -140,16 +142,34 @@ __device__ __forceinline__ uint32_t stage_tile(const JobDev &d, int tx0, int ty0
     return vmask;
 }
 
-// Scores this thread's candidates of a staged tile against target view T
-// and returns their minimum key (~0 if none is valid).
+// Validity bits of this thread's candidates (bit i: row i of its column) for
+// the tile at (tx0, ty0), without staging the tile.
+template <int R, int NY>
+__device__ __forceinline__ uint32_t tile_valid(const JobDev &d, int tx0, int ty0, int rx1, int ry1) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x = tx0 + lane, yb = ty0 + wave * NY;
+    const uint8_t *vr = d.vradp + (int64_t)(yb + kPadT) * d.pitch + (x + kPadL);
+    uint32_t v[NY];
+#pragma unroll
+    for (int i = 0; i < NY; ++i) v[i] = vr[i * d.pitch];
+    uint32_t vmask = 0;
+#pragma unroll
+    for (int i = 0; i < NY; ++i)
+        if (x < rx1 && yb + i < ry1 && v[i] >= (uint32_t)R) vmask |= 1u << i;
+    return vmask;
+}
+
+// Scores this thread's candidates against target view T and returns their
+// minimum key (~0 if none is valid).  `colp` points at the source word of
+// this lane's column for offset (-R, -R) of its first candidate row;
+// consecutive rows are `stride` words apart.
 template <int R, int NY, class T>
-__device__ __forceinline__ uint64_t score_tile(const JobDev &d, const T &tg, int tx0, int ty0, uint32_t vmask,
-                                               const uint32_t *lds) {
+__device__ __forceinline__ uint64_t score_cols(const JobDev &d, const T &tg, int tx0, int ty0, uint32_t vmask,
+                                               const uint32_t *colp, int stride) {
     using G = TileGeom<R, NY>;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int W = d.W;
     const int x = tx0 + lane, yb = ty0 + wave * NY;
-    const int sh = (tx0 - R + kPadL) & 3;
 
     uint32_t A[NY], S[NY];
 #pragma unroll
@@ -164,7 +184,6 @@ __device__ __forceinline__ uint64_t score_tile(const JobDev &d, const T &tg, int
         sb[w] = tg.starts(w);
         eb[w] = tg.ends(w);
     }
-    const uint32_t *colp = lds + wave * NY * G::LW + lane + sh;
 #pragma unroll
     for (int dxi = 0; dxi < G::P; ++dxi) {
         // This column's target words, loaded unconditionally.
@@ -175,7 +194,7 @@ __device__ __forceinline__ uint64_t score_tile(const JobDev &d, const T &tg, int
         pre[0] = 0;
 #pragma unroll
         for (int j = 0; j < G::NJ; ++j) {
-            col[j] = colp[j * G::LW + dxi];
+            col[j] = colp[j * stride + dxi];
             pre[j + 1] = __builtin_amdgcn_udot4(col[j], col[j], pre[j], false);
         }
 #pragma unroll
@@ -213,6 +232,27 @@ __device__ __forceinline__ uint64_t score_tile(const JobDev &d, const T &tg, int
         }
     }
     return best;
+}
+
+// Scores a tile staged in LDS by stage_tile.
+template <int R, int NY, class T>
+__device__ __forceinline__ uint64_t score_tile(const JobDev &d, const T &tg, int tx0, int ty0, uint32_t vmask,
+                                               const uint32_t *lds) {
+    using G = TileGeom<R, NY>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sh = (tx0 - R + kPadL) & 3;
+    return score_cols<R, NY>(d, tg, tx0, ty0, vmask, lds + wave * NY * G::LW + lane + sh, G::LW);
+}
+
+// Scores the tile straight from the padded source plane in device memory
+// (through the vector caches), with no LDS staging.  The words read are a
+// subset of the window stage_tile loads, so the plane's padding covers them.
+template <int R, int NY, class T>
+__device__ __forceinline__ uint64_t score_direct(const JobDev &d, const T &tg, int tx0, int ty0, uint32_t vmask) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x = tx0 + lane, yb = ty0 + wave * NY;
+    const uint32_t *colp = d.srcp + (int64_t)(yb - R + kPadT) * d.pitch + (x - R + kPadL);
+    return score_cols<R, NY>(d, tg, tx0, ty0, vmask, colp, d.pitch);
 }
 
 // Minimum over the wave.  (Kept out of score_tile: inlined there it makes

@@ -376,3 +376,61 @@ def test_mfma_hd_full_run_matches_stored_oracle(key):
     st, n, log = g.run(log_cap=gold["iterations"] + 8)
     assert st == B.DONE
     assert_matches_golden(gold, log, g.read_image(), key + " mfma")
+
+
+# ------------------------------- SIMT search without LDS staging (direct)
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_direct_find_exemplar_matches_oracle(r):
+    job = synth.small()
+    o, g = _pair(job, path=B.PATH_SIMT_DIRECT)
+    rng = np.random.default_rng(200 + r)
+    front = o.front()
+    targets = [(int(i % job.width), int(i // job.width)) for i in front[:: max(len(front) // 5, 1)]]
+    targets += [(int(rng.integers(0, job.width)), int(rng.integers(0, job.height))) for _ in range(3)]
+    targets += [(0, 0), (job.width - 1, job.height - 1)]
+    for (x, y) in targets:
+        for rect in [(0, 0, job.width, job.height), (9, 5, 71, 50)]:
+            try:
+                want = o.find_exemplar(x, y, r, rect)[:2]
+            except oracle.OracleError as e:
+                assert e.status == oracle.NO_CANDIDATE
+                continue
+            assert g.find_exemplar(x, y, r, rect) == want, (r, x, y, rect)
+
+
+@pytest.mark.parametrize("seed,W,H,r,tile_rows", [(21, 16, 16, 1, 8), (22, 67, 45, 5, 4), (23, 90, 70, 8, 16),
+                                                  (24, 130, 21, 4, 8), (25, 33, 70, 6, 16)])
+def test_direct_full_run(seed, W, H, r, tile_rows):
+    rng = np.random.default_rng(seed)
+    rgb = rng.integers(0, 256, size=(H, W, 3)).astype(np.uint8)
+    mask = np.zeros((H, W), np.uint8)
+    mask[H // 3:H // 3 + max(H // 5, 2), W // 3:W // 3 + max(W // 6, 2)] = 1
+    mask[0:max(H // 8, 1), W - max(W // 7, 2):] = 1
+    job = synth.Job(f"direct{seed}", rgb, mask, r)
+    _full_run_parity(job, job.name, path=B.PATH_SIMT_DIRECT, tile_rows=tile_rows, form="stream", iters_per_check=7)
+
+
+def test_direct_small_window_graph_form():
+    j = synth.small()
+    j.search_mode, j.alpha = synth.SEARCH_ALPHA, (1, 1)
+    _full_run_parity(j, "small-win direct", path=B.PATH_SIMT_DIRECT, form="graph", iters_per_check=4)
+
+
+def test_direct_persistent_request_runs_stream_form():
+    job = synth.small()
+    g = B.Inpainter(job.rgb, job.mask, 4, path=B.PATH_SIMT_DIRECT, form="persistent")
+    assert g.run_form() == "stream"
+    g.close()
+    _full_run_parity(job, "small direct persistent", path=B.PATH_SIMT_DIRECT, form="persistent")
+
+
+def test_direct_vga_full_run_matches_stored_oracle():
+    gold = load_golden("vga")
+    if gold is None:
+        pytest.skip("stored oracle result for the 640x480 workload not generated")
+    job = synth.vga()
+    g = B.Inpainter(job.rgb, job.mask, 4, path=B.PATH_SIMT_DIRECT, form="stream", iters_per_check=64)
+    st, n, log = g.run(log_cap=gold["iterations"] + 8)
+    assert st == B.DONE
+    assert_matches_golden(gold, log, g.read_image(), "vga direct")
