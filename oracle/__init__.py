@@ -22,6 +22,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 OK, DONE, INVALID_ARGUMENT, NO_CANDIDATE, OUT_OF_MEMORY = 0, 1, -1, -2, -3
 SEARCH_FULL, SEARCH_ALPHA, SEARCH_RECT = 0, 1, 2
+SOURCE_ORIGINAL, SOURCE_CURRENT = 0, 1
+SCORE_WHOLE, SCORE_INTERSECT = 0, 1
 
 # One fill-iteration record (matches oracle_step_info in oracle.c).
 STEP_DTYPE = np.dtype([
@@ -53,7 +55,7 @@ def lib():
         L = ctypes.CDLL(LIB)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.oracle_create.argtypes = [i32, i32, vp, i32, i32, vp, i32, i32, i32, i32, i32, vp,
-                                    ctypes.POINTER(vp)]
+                                    i32, i32, ctypes.POINTER(vp)]
         L.oracle_create.restype = i32
         L.oracle_destroy.argtypes = [vp]
         L.oracle_destroy.restype = None
@@ -98,7 +100,8 @@ class Oracle:
     """One removal job on the CPU oracle."""
 
     def __init__(self, rgb: np.ndarray, mask: np.ndarray, patch_radius: int,
-                 search_mode: int = SEARCH_FULL, alpha=(0, 1), rect=None):
+                 search_mode: int = SEARCH_FULL, alpha=(0, 1), rect=None,
+                 source_policy: int = SOURCE_ORIGINAL, scoring: int = SCORE_WHOLE):
         rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
         mask = np.ascontiguousarray(mask, dtype=np.uint8)
         H, W, ch = rgb.shape
@@ -108,7 +111,7 @@ class Oracle:
         h = ctypes.c_void_p()
         st = lib().oracle_create(W, H, _ptr(rgb), W * ch, ch, _ptr(mask), W, patch_radius,
                                  search_mode, int(alpha[0]), int(alpha[1]), _ptr(rect_a),
-                                 ctypes.byref(h))
+                                 source_policy, scoring, ctypes.byref(h))
         if st != OK:
             raise OracleError(st, "oracle_create")
         self._h = h

@@ -51,6 +51,25 @@
  *   R12 ties: SSD ties go to the lowest raster index of the candidate centre;
  *       priority ties go to the lowest raster index of the front pixel.
  *   R13 SSD in exact integers over R, G, B only.
+ *
+ * Candidate-domain variants (selected at create; the defaults are the
+ * readings above):
+ *   source policy ORIGINAL (default): the source region Phi is the original
+ *       known region Phi_0, so filled pixels never become sources (R4).
+ *   source policy CURRENT: Phi is the current known region, so pixels become
+ *       sources once they are filled (Section 3 defines Phi = S - Omega with
+ *       Omega the region still to fill).
+ *   scoring WHOLE (default): a candidate's whole window lies in the image and
+ *       in Phi, and its SSD runs over the target's known pixels (R4).
+ *   scoring INTERSECT: Eq. 4 read literally, as Section 5.4 describes for
+ *       candidates that overlap the object.  Any centre in Phi is a candidate,
+ *       whatever its window overlaps.  The SSD runs over the offsets where the
+ *       target pixel is known AND the candidate pixel lies in the image and in
+ *       Phi.  The copy fills only those hole pixels of the target whose source
+ *       pixel lies in the image and in Phi (the rest stay in the hole for a
+ *       later iteration); the centre is a source pixel, so the target pixel
+ *       itself is always filled.  Which source pixels qualify is decided on the
+ *       state before the copy.
  */
 #include <math.h>
 #include <stdint.h>
@@ -66,6 +85,11 @@
 #define OR_SEARCH_FULL 0
 #define OR_SEARCH_ALPHA 1
 #define OR_SEARCH_RECT 2
+
+#define OR_SOURCE_ORIGINAL 0
+#define OR_SOURCE_CURRENT 1
+#define OR_SCORE_WHOLE 0
+#define OR_SCORE_INTERSECT 1
 
 /* One record per fill iteration.  Field order and widths are fixed so Python
  * can read an array of them with a structured dtype. */
@@ -90,6 +114,8 @@ typedef struct {
     uint8_t *hole0;   /* 1 where the pixel is in the original hole Omega_0 */
     double *conf;     /* confidence C */
     int32_t rect[4];  /* candidate-centre search rectangle, half-open */
+    int32_t policy;   /* OR_SOURCE_* */
+    int32_t scoring;  /* OR_SCORE_* */
     int64_t remaining;
     int64_t iter;
     double norm[3];   /* 255 * |n| for |n|^2 = 1, 2 */
@@ -108,15 +134,28 @@ static int known(const oracle_state *s, int x, int y)
     return in_image(s, x, y) && !s->hole[(int64_t)y * s->W + x];
 }
 
+/* The source region Phi: in the image and in the original known region, or
+ * in the current known region under the CURRENT policy. */
+static int in_source(const oracle_state *s, int x, int y)
+{
+    if (!in_image(s, x, y))
+        return 0;
+    int64_t i = (int64_t)y * s->W + x;
+    return s->policy == OR_SOURCE_CURRENT ? !s->hole[i] : !s->hole0[i];
+}
+
 /* R4: the whole (2r+1)^2 window around (cx, cy) is inside the image and
- * inside the original known region. */
+ * inside the source region.  Under INTERSECT scoring only the centre has to
+ * be a source pixel. */
 static int valid_centre(const oracle_state *s, int cx, int cy, int r)
 {
+    if (s->scoring == OR_SCORE_INTERSECT)
+        return in_source(s, cx, cy);
     if (cx - r < 0 || cy - r < 0 || cx + r >= s->W || cy + r >= s->H)
         return 0;
     for (int dy = -r; dy <= r; ++dy)
         for (int dx = -r; dx <= r; ++dx)
-            if (s->hole0[(int64_t)(cy + dy) * s->W + (cx + dx)])
+            if (!in_source(s, cx + dx, cy + dy))
                 return 0;
     return 1;
 }
@@ -147,7 +186,8 @@ static void alpha_axis(int b0, int b1, int n, int an, int ad, int *lo, int *hi)
 int oracle_create(int32_t W, int32_t H, const uint8_t *rgb, int32_t rgb_stride,
                   int32_t channels, const uint8_t *mask, int32_t mask_stride,
                   int32_t r, int32_t search_mode, int32_t alpha_num,
-                  int32_t alpha_den, const int32_t *rect, oracle_state **out)
+                  int32_t alpha_den, const int32_t *rect, int32_t policy,
+                  int32_t scoring, oracle_state **out)
 {
     if (!rgb || !mask || !out || (channels != 3 && channels != 4))
         return OR_INVALID_ARGUMENT;
@@ -162,12 +202,17 @@ int oracle_create(int32_t W, int32_t H, const uint8_t *rgb, int32_t rgb_stride,
         return OR_INVALID_ARGUMENT;
     if (search_mode < 0 || search_mode > 2)
         return OR_INVALID_ARGUMENT;
+    if (policy < OR_SOURCE_ORIGINAL || policy > OR_SOURCE_CURRENT ||
+        scoring < OR_SCORE_WHOLE || scoring > OR_SCORE_INTERSECT)
+        return OR_INVALID_ARGUMENT;
 
     oracle_state *s = (oracle_state *)calloc(1, sizeof(oracle_state));
     if (!s)
         return OR_OUT_OF_MEMORY;
     int64_t n = (int64_t)W * H;
     s->W = W; s->H = H; s->r = r; s->P = P;
+    s->policy = policy;
+    s->scoring = scoring;
     s->rgb = (uint8_t *)malloc((size_t)n * 3);
     s->gray = (uint8_t *)malloc((size_t)n);
     s->hole = (uint8_t *)malloc((size_t)n);
@@ -376,7 +421,9 @@ int oracle_select(const oracle_state *s, int64_t *idx, double *C, double *D, dou
 /* Eq. 3 / Eq. 4 over the candidate centres of `rect` (clipped to the image)
  * that satisfy R4: the (ssd, index)-lexicographic minimum of the masked SSD
  * between the target patch at (tx, ty) and the candidate's patch.  Offsets
- * with the target pixel outside the image or in the hole do not count. */
+ * with the target pixel outside the image or in the hole do not count; under
+ * INTERSECT scoring neither do offsets whose candidate pixel is outside the
+ * source region. */
 int oracle_find_exemplar(const oracle_state *s, int32_t tx, int32_t ty, int32_t r,
                          const int32_t *rect, int64_t *idx, uint32_t *ssd,
                          int32_t *known_k)
@@ -405,6 +452,8 @@ int oracle_find_exemplar(const oracle_state *s, int32_t tx, int32_t ty, int32_t 
             for (int dy = -r; dy <= r; ++dy)
                 for (int dx = -r; dx <= r; ++dx) {
                     if (!known(s, tx + dx, ty + dy))
+                        continue;
+                    if (s->scoring == OR_SCORE_INTERSECT && !in_source(s, cx + dx, cy + dy))
                         continue;
                     const uint8_t *t = s->rgb + ((int64_t)(ty + dy) * W + (tx + dx)) * 3;
                     const uint8_t *q = s->rgb + ((int64_t)(cy + dy) * W + (cx + dx)) * 3;
@@ -451,12 +500,22 @@ int oracle_step(oracle_state *s, oracle_step_info *info)
     int qx = (int)(q % W), qy = (int)(q / W);
 
     /* Copy the source patch into the target's hole pixels; they take the
-     * target's confidence and leave the hole. */
+     * target's confidence and leave the hole.  Under INTERSECT scoring only
+     * the pixels whose source pixel is in the source region are copied, as
+     * decided before the copy changes the hole. */
+    uint8_t take[17 * 17];
+    for (int dy = -r; dy <= r; ++dy)
+        for (int dx = -r; dx <= r; ++dx) {
+            int x = px + dx, y = py + dy;
+            int t = (dy + r) * s->P + (dx + r);
+            take[t] = (uint8_t)(in_image(s, x, y) && s->hole[(int64_t)y * W + x] &&
+                                (s->scoring != OR_SCORE_INTERSECT || in_source(s, qx + dx, qy + dy)));
+        }
     int filled = 0;
     for (int dy = -r; dy <= r; ++dy)
         for (int dx = -r; dx <= r; ++dx) {
             int x = px + dx, y = py + dy;
-            if (!in_image(s, x, y) || !s->hole[(int64_t)y * W + x])
+            if (!take[(dy + r) * s->P + (dx + r)])
                 continue;
             int64_t dst = (int64_t)y * W + x;
             int64_t src = (int64_t)(qy + dy) * W + (qx + dx);
