@@ -86,6 +86,33 @@ extern "C" {
  * searches every attached job with the staged kernel. */
 #define INPAINT_PATH_SIMT_DIRECT 3
 
+/* Candidate domain of the exemplar search.  The default reads Eq. 4 as
+ * Criminisi does: a candidate's whole window lies in the image and in the
+ * ORIGINAL known region Phi_0, so filled pixels never become sources.  The
+ * paper's own wording allows two other readings, which these fields select.
+ *
+ * source_policy CURRENT: the source region is the current known region
+ *   (Section 3 defines Phi = S - Omega, and Omega shrinks as the fill
+ *   proceeds), so filled pixels become sources.  It is evaluated on the
+ *   state at the start of each iteration.
+ * scoring INTERSECT: Eq. 4 read literally, as Section 5.4 describes for
+ *   candidates that overlap the object.
+ *   - A candidate is any centre of the search rect that is itself a source
+ *     pixel; its window may overlap the hole or leave the image.
+ *   - Its SSD runs over the offsets where the target pixel is known and the
+ *     candidate pixel is in the image and in the source region.
+ *   - The copy fills only the target's hole pixels whose source pixel
+ *     qualifies; the others stay in the hole for a later iteration.
+ *
+ * The two fields combine freely.  Any non-default value needs the SIMT
+ * search (path SIMT, SIMT_DIRECT or AUTO; MFMA gives INVALID_ARGUMENT) and
+ * runs in the PLAIN, STREAM or GRAPH form (PERSISTENT runs as STREAM).
+ * Such a context cannot be attached to a batch. */
+#define INPAINT_SOURCE_ORIGINAL 0
+#define INPAINT_SOURCE_CURRENT  1
+#define INPAINT_SCORE_WHOLE     0
+#define INPAINT_SCORE_INTERSECT 1
+
 typedef struct {
     const uint8_t *data;   /* host pixels, row-major, 8 bits per channel     */
     int32_t width;
@@ -115,7 +142,9 @@ typedef struct {
                            /*   its hole-pixel count)                       */
     int32_t tile_rows;     /* search tile: candidate rows per thread (0 =   */
                            /*   default; 4, 8 or 16)                        */
-    int32_t reserved[3];   /* must be zero                                   */
+    int32_t source_policy; /* INPAINT_SOURCE_* (0 = ORIGINAL, the default)  */
+    int32_t scoring;       /* INPAINT_SCORE_* (0 = WHOLE, the default)      */
+    int32_t reserved[1];   /* must be zero                                   */
 } inpaint_params;
 
 /* One fill iteration (64 bytes). */

@@ -21,6 +21,8 @@ OK, DONE = 0, 1
 INVALID_ARGUMENT, NO_CANDIDATE, OUT_OF_MEMORY, DEVICE = -1, -2, -3, -4
 SEARCH_FULL, SEARCH_ALPHA, SEARCH_RECT = 0, 1, 2
 PATH_AUTO, PATH_SIMT, PATH_MFMA, PATH_SIMT_DIRECT = 0, 1, 2, 3
+SOURCE_ORIGINAL, SOURCE_CURRENT = 0, 1
+SCORE_WHOLE, SCORE_INTERSECT = 0, 1
 FORM_PLAIN, FORM_STREAM, FORM_GRAPH, FORM_PERSISTENT = 0, 1, 2, 3
 FORMS = {"plain": FORM_PLAIN, "stream": FORM_STREAM, "graph": FORM_GRAPH, "persistent": FORM_PERSISTENT}
 FORM_NAMES = {v: k for k, v in FORMS.items()}
@@ -41,7 +43,8 @@ class inpaint_params(ctypes.Structure):
                 ("alpha_num", ctypes.c_int32), ("alpha_den", ctypes.c_int32),
                 ("rect", inpaint_rect), ("path", ctypes.c_int32), ("form", ctypes.c_int32),
                 ("iters_per_check", ctypes.c_int32), ("log_capacity", ctypes.c_int32),
-                ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("tile_rows", ctypes.c_int32), ("source_policy", ctypes.c_int32),
+                ("scoring", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class inpaint_batch_params(ctypes.Structure):
@@ -125,7 +128,8 @@ def inpaint_last_error(ctx) -> str:
 
 def make_params(patch_radius: int, search_mode: int = SEARCH_FULL, alpha=(0, 1), rect=(0, 0, 0, 0),
                 path: int = PATH_AUTO, form: str = "plain", iters_per_check: int = 16,
-                log_capacity: int = 0, tile_rows: int = 0) -> inpaint_params:
+                log_capacity: int = 0, tile_rows: int = 0, source_policy: int = SOURCE_ORIGINAL,
+                scoring: int = SCORE_WHOLE) -> inpaint_params:
     p = inpaint_params()
     p.patch_radius = patch_radius
     p.search_mode = search_mode
@@ -136,6 +140,8 @@ def make_params(patch_radius: int, search_mode: int = SEARCH_FULL, alpha=(0, 1),
     p.iters_per_check = iters_per_check
     p.log_capacity = log_capacity
     p.tile_rows = tile_rows
+    p.source_policy = source_policy
+    p.scoring = scoring
     return p
 
 
@@ -158,7 +164,7 @@ class Inpainter:
                  search_mode: int = SEARCH_FULL, alpha=(0, 1), rect=(0, 0, 0, 0),
                  path: int = PATH_AUTO, form: str = "plain", iters_per_check: int = 16,
                  log_capacity: int | None = None, tile_rows: int = 0, device: str = "cuda",
-                 stream=None):
+                 stream=None, source_policy: int = SOURCE_ORIGINAL, scoring: int = SCORE_WHOLE):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: libinpaint has no CPU path")
         rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
@@ -169,7 +175,7 @@ class Inpainter:
         if log_capacity is None:
             log_capacity = int(np.count_nonzero(mask))
         self.params = make_params(patch_radius, search_mode, alpha, rect, path, form,
-                                  iters_per_check, log_capacity, tile_rows)
+                                  iters_per_check, log_capacity, tile_rows, source_policy, scoring)
         self.width, self.height = W, H
         self.ws_bytes = inpaint_workspace_bytes(W, H, self.params)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)

@@ -829,8 +829,10 @@ __global__ __launch_bounds__(256) void k_init_vrad(JobDev d, const uint8_t *hdis
     d.vrad[i] = (uint8_t)v;
 }
 
-// Static search planes: the original image (hole pixels zero) and vrad in
-// the zero-padded layout the search stages from.
+// Search planes: the original image (hole pixels zero) and vrad in the
+// zero-padded layout the search stages from.  With INTERSECT scoring the 4th
+// byte of a source pixel's word is 1 and the validity plane only flags
+// source pixels (a candidate centre needs to be one).
 __global__ __launch_bounds__(256) void k_init_padded(JobDev d) {
     const int pitch = d.pitch;
     const int64_t n = (int64_t)pitch * padded_rows(d.H);
@@ -842,6 +844,11 @@ __global__ __launch_bounds__(256) void k_init_padded(JobDev d) {
     if (x >= 0 && x < d.W && y >= 0 && y < d.H) {
         pix = d.img[(int64_t)y * d.W + x];
         vr = d.vrad[(int64_t)y * d.W + x];
+        if (d.isect) {
+            const bool src = d.hole[(int64_t)y * d.W + x] == 0;
+            pix |= src ? 1u << 24 : 0u;
+            vr = src ? 1 : 0;
+        }
     }
     d.srcp[i] = pix;
     d.vradp[i] = vr;
@@ -857,7 +864,8 @@ __global__ __launch_bounds__(256) void k_count_valid(JobDev d) {
     __syncthreads();
     if (i < n) {
         const int x = d.rx0 + (int)(i % rw), y = d.ry0 + (int)(i / rw);
-        if (d.vrad[(int64_t)y * d.W + x] >= d.r) atomicAdd(&s_cnt, 1);
+        const int64_t j = (int64_t)y * d.W + x;
+        if (d.isect ? d.hole[j] == 0 : d.vrad[j] >= d.r) atomicAdd(&s_cnt, 1);
     }
     __syncthreads();
     if (threadIdx.x == 0 && s_cnt)
@@ -977,6 +985,78 @@ __device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, Ld
     return best;
 }
 
+// What the stream-form commit reports about its copy: the target and the
+// number of pixels filled (nf counts them under INTERSECT scoring).
+struct CommitNote {
+    int64_t p;
+    int32_t filled;
+    int32_t nf;
+};
+
+// CURRENT source policy: the pixels this iteration filled become source
+// pixels.  Writes their words into the padded source plane and brings the
+// validity planes up to date around the patch: the horizontal distances of
+// the patch rows, then the validity radii of every centre whose radius can
+// have changed (as k_init_hdist / k_init_vrad compute them).  The hole map
+// changed only inside the patch, which the LDS neighbourhood holds; every
+// other pixel is read from device memory, unchanged since earlier launches.
+template <int R, bool ISECT>
+__device__ void add_filled_sources(const JobDev &d, const LdsStage<R> &L, int px, int py) {
+    constexpr int P = 2 * R + 1, half = Stage<R>::half, side = Stage<R>::side;
+    constexpr int HW = 2 * R + 19;   // columns px - R - 9 .. px + R + 9
+    const int W = d.W, H = d.H, pitch = d.pitch;
+    auto known = [&](int x, int y) -> bool {
+        if ((unsigned)x >= (unsigned)W || (unsigned)y >= (unsigned)H) return false;
+        const int lx = x - px + half, ly = y - py + half;
+        if ((unsigned)lx < (unsigned)side && (unsigned)ly < (unsigned)side) return L.st[ly * side + lx] == 0;
+        return d.hole[(int64_t)y * W + x] == 0;
+    };
+    // the patch's known pixels (rewriting the unchanged ones is harmless)
+    for (int t = threadIdx.x; t < P * P; t += blockDim.x) {
+        const int x = px + t % P - R, y = py + t / P - R;
+        if (!known(x, y)) continue;
+        const int64_t pi = (int64_t)(y + kPadT) * pitch + (x + kPadL);
+        d.srcp[pi] = L.img[(y - py + half) * side + (x - px + half)] | (ISECT ? 1u << 24 : 0u);
+        if (ISECT) d.vradp[pi] = 1;
+    }
+    if (ISECT) return;   // INTERSECT candidates only need their centre to be a source pixel
+    __shared__ uint8_t hrow[P * HW];
+    for (int t = threadIdx.x; t < P * HW; t += blockDim.x) {
+        const int x = px - R - 9 + t % HW, y = py - R + t / HW;
+        uint8_t h = 0;
+        if ((unsigned)x < (unsigned)W && (unsigned)y < (unsigned)H) {
+            int hh = 10;
+            for (int dx = 0; dx < 10; ++dx)
+                if (!known(x - dx, y) || !known(x + dx, y)) {
+                    hh = dx;
+                    break;
+                }
+            h = (uint8_t)hh;
+            d.hdist[(int64_t)y * W + x] = h;
+        }
+        hrow[t] = h;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < HW * HW; t += blockDim.x) {
+        const int x = px - R - 9 + t % HW, y = py - R - 9 + t / HW;
+        if ((unsigned)x >= (unsigned)W || (unsigned)y >= (unsigned)H) continue;
+        int dist = 10;
+        for (int dy = -9; dy <= 9; ++dy) {
+            const int yy = y + dy, ady = dy < 0 ? -dy : dy;
+            int h;
+            if (yy < 0 || yy >= H) h = 0;
+            else if (yy >= py - R && yy <= py + R) h = hrow[(yy - py + R) * HW + (x - px + R + 9)];
+            else h = d.hdist[(int64_t)yy * W + x];
+            const int m = ady > h ? ady : h;
+            dist = m < dist ? m : dist;
+        }
+        int v = dist - 1;
+        v = v < 0 ? 0 : (v > kMaxRadius ? kMaxRadius : v);
+        d.vrad[(int64_t)y * W + x] = (uint8_t)v;
+        d.vradp[(int64_t)(y + kPadT) * pitch + (x + kPadL)] = (uint8_t)v;
+    }
+}
+
 // The part of a fill iteration that needs the search result `best`: copy the
 // source patch into the target's hole pixels (they take the target's
 // confidence), log, refresh priorities near the patch, select and stage the
@@ -988,9 +1068,10 @@ __device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, Ld
 // LDS when its patch lies inside the staged neighbourhood (the common case:
 // the front moves locally).  (key0, idx0) is the argmax over the blocks the
 // refresh does not touch (block-uniform).
-template <int R>
+template <int R, bool ISECT = false>
 __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const Snap &v, uint64_t best,
-                              const Refresh &g, int64_t key0, int64_t idx0, Snap *out, FillSync *recs = nullptr) {
+                              const Refresh &g, int64_t key0, int64_t idx0, Snap *out, FillSync *recs = nullptr,
+                              CommitNote *note = nullptr) {
     IterState *st = d.st;
     constexpr int P = 2 * R + 1;
     const int W = d.W;
@@ -1010,11 +1091,24 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
     const uint32_t ssd = (uint32_t)(best >> 32);
     const int qx = (int)(q % W), qy = (int)(q / W);
     // the hole pixels of the target patch: its in-image pixels minus the known k
-    const int64_t filled = (int64_t)(min(px + R + 1, W) - max(px - R, 0)) * (min(py + R + 1, d.H) - max(py - R, 0)) - v.k;
+    // (with INTERSECT scoring only those whose source pixel is a source pixel
+    // are filled, counted as they are copied)
+    int64_t filled = (int64_t)(min(px + R + 1, W) - max(px - R, 0)) * (min(py + R + 1, d.H) - max(py - R, 0)) - v.k;
+    if (ISECT) {
+        if (threadIdx.x == 0) note->nf = 0;
+        __syncthreads();
+    }
     for (int t = threadIdx.x; t < P * P; t += blockDim.x) {
         const int dx = t % P - R, dy = t / P - R;
         const int li = (dy + Stage<R>::half) * Stage<R>::side + (dx + Stage<R>::half);
         if (L.st[li] == 1) {
+            if (ISECT) {
+                // the flag byte of the source word, read before any of this
+                // copy's writes (the padded plane covers R pixels around the image)
+                const uint32_t sw = d.srcp[(int64_t)(qy + dy + kPadT) * d.pitch + (qx + dx + kPadL)];
+                if ((sw >> 24) == 0) continue;
+                atomicAdd(&note->nf, 1);
+            }
             const int64_t dst = (int64_t)(py + dy) * W + (px + dx), src = (int64_t)(qy + dy) * W + (qx + dx);
             const uint32_t pix = d.img[src];
             const uint8_t gv = d.gray[src];
@@ -1031,6 +1125,14 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
             d.pcd[dst] = make_double2(-1.0, 0.0);
             L.bkey[((y / kBlock - g.aby0) * g.nabx + (x / kBlock - g.abx0)) * 64 + (y & 7) * 8 + (x & 7)] = -1;
         }
+    }
+    if (ISECT) {
+        __syncthreads();
+        filled = note->nf;
+    }
+    if (note && threadIdx.x == 0) {
+        note->p = v.p;
+        note->filled = (int32_t)filled;
     }
     const int64_t remaining = v.remaining - filled;
     if (threadIdx.x == 0) {
@@ -1121,8 +1223,8 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
 // finish.  With no staged target (right after create) it only selects and
 // stages.  Latency is the cost here, so every global load that does not
 // depend on the search result is issued at once up front (gather).
-template <int R>
-__device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L) {
+template <int R, bool ISECT = false>
+__device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L, CommitNote *note = nullptr) {
     const Snap v = load_snap(d.st, d.tgt);
     if (v.done || v.err) return;
     if (!v.pending) {
@@ -1137,7 +1239,7 @@ __device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L) {
     best = block_min_u64(best, s.u);   // its barriers also publish the LDS stores
     grad_pass<R>(L, 1, Stage<R>::side - 1);
     block_argmax(key, idx, s.k, s.i);
-    commit_finish<R>(d, s, L, v, best, g, key, idx, &s.snap);
+    commit_finish<R, ISECT>(d, s, L, v, best, g, key, idx, &s.snap, nullptr, note);
 }
 
 // ---- persistent fill: one cooperative dispatch runs many iterations ------
@@ -1426,11 +1528,17 @@ __global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(
         fill_search<R, kFillTileRows>(d, ntiles, epoch, lds.s);
 }
 
-template <int R>
+template <int R, bool ISECT>
 __global__ __launch_bounds__(kCommitThreads) void k_commit(JobDev d) {
     __shared__ Scratch s;
     __shared__ LdsStage<R> L;
-    commit_body<R>(d, s, L);
+    __shared__ CommitNote note;
+    if (threadIdx.x == 0) note.filled = 0;
+    commit_body<R, ISECT>(d, s, L, &note);
+    if (d.policy == INPAINT_SOURCE_CURRENT) {
+        __syncthreads();
+        if (note.filled > 0) add_filled_sources<R, ISECT>(d, L, (int)(note.p % d.W), (int)(note.p / d.W));
+    }
 }
 
 // One work-group per listed slot (all with patch radius R); the list length
@@ -1528,7 +1636,9 @@ hipError_t launch_prio_init(const JobDev &d, hipStream_t s) {
 }
 
 hipError_t launch_commit(const JobDev &d, hipStream_t s) {
-#define CALL(R) hipLaunchKernelGGL(k_commit<R>, dim3(1), dim3(kCommitThreads), 0, s, d)
+#define CALL(R)                                                                            \
+    if (d.isect) hipLaunchKernelGGL((k_commit<R, true>), dim3(1), dim3(kCommitThreads), 0, s, d); \
+    else hipLaunchKernelGGL((k_commit<R, false>), dim3(1), dim3(kCommitThreads), 0, s, d)
     INPAINT_RADIUS_SWITCH(d.r, CALL)
 #undef CALL
     return hipGetLastError();

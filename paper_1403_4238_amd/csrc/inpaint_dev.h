@@ -146,8 +146,13 @@ struct JobDev {
     TargetStage *qtgt;   // staged target of inpaint_find_exemplar
     uint32_t *srcw;      // MFMA: original RGBX ^ 0x80808080, padded plane (static)
     uint16_t *srcq;      // MFMA: (|s'|^2 low byte - 128, high byte - 128), padded plane (static)
-    uint32_t *srcp;      // original RGBX in the padded plane, zero outside the image (static)
-    uint8_t *vradp;      // vrad in the padded plane, zero outside the image (static)
+    uint32_t *srcp;      // source RGBX in the padded plane, zero outside the image and in the hole;
+                         // with INTERSECT scoring the 4th byte is 1 on source pixels.  Static,
+                         // except under the CURRENT source policy (filled pixels are added)
+    uint8_t *vradp;      // vrad in the padded plane, zero outside the image (static as srcp);
+                         // with INTERSECT scoring 1 on source pixels, 0 elsewhere
+    uint8_t *hdist;      // CURRENT policy with WHOLE scoring: per pixel, the horizontal distance
+                         // (capped at 10) to the nearest hole or out-of-image pixel of its row
     MfmaFrags *frag;     // MFMA B operands of tgt (when mfma)
     MfmaFrags *qfrag;    // MFMA B operands of qtgt (when mfma)
     IterState *st;
@@ -163,6 +168,8 @@ struct JobDev {
     int32_t ntx, nty;             // search tiles over the rect
     int32_t mfma;                 // 1: the search runs on the matrix cores
     int32_t pitch;                // row pitch of srcp / vradp in pixels (multiple of 4)
+    int32_t policy;               // INPAINT_SOURCE_*
+    int32_t isect;                // 1: INTERSECT scoring
     double norm1, norm2;          // 255 * |n| for |n|^2 = 1 and 2
 };
 
@@ -178,6 +185,7 @@ hipError_t launch_init(const JobDev &d, const uint8_t *stage_rgb, int channels,
 hipError_t launch_count_valid(const JobDev &d, hipStream_t s);
 hipError_t launch_prio_init(const JobDev &d, hipStream_t s);
 hipError_t launch_commit(const JobDev &d, hipStream_t s);
+// SIMT search of one target; `d.isect` selects INTERSECT scoring.
 hipError_t launch_search(const JobDev &d, bool query, int r, int rx0, int ry0, int rx1, int ry1,
                          int tile_rows, int ntx, int nty, hipStream_t s,
                          hipEvent_t start = nullptr, hipEvent_t stop = nullptr);

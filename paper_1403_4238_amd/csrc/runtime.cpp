@@ -31,8 +31,8 @@ constexpr int kDefaultTileRows = 8;
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t img, gray, hole, vrad, conf, pcd, blk, partials, tgt, qtgt, frag, qfrag, srcw, srcq, srcp, vradp, st, sync,
-        fslot, info, key, log, total;
+    uint64_t img, gray, hole, vrad, conf, pcd, blk, partials, tgt, qtgt, frag, qfrag, srcw, srcq, srcp, vradp, hdist, st,
+        sync, fslot, info, key, log, total;
     int64_t log_cap;
     int max_tiles;
 };
@@ -73,6 +73,9 @@ Layout make_layout(int W, int H, const inpaint_params &p) {
     L.srcq = mfma ? take(2 * np) : 0;
     L.srcp = take(4 * np);
     L.vradp = take(np);
+    // the CURRENT source policy with WHOLE scoring keeps its row distances
+    const bool keep_hdist = p.source_policy == INPAINT_SOURCE_CURRENT && p.scoring == INPAINT_SCORE_WHOLE;
+    L.hdist = keep_hdist ? take(n) : 0;
     L.st = take(sizeof(IterState));
     L.sync = take(sizeof(FillSync));
     L.fslot = take(8 * (uint64_t)L.max_tiles);
@@ -228,11 +231,23 @@ static int32_t check_params(int32_t W, int32_t H, const inpaint_params *p, std::
         *why = "the int8-MFMA search supports patch radius 1..6";
         return INPAINT_INVALID_ARGUMENT;
     }
+    if (p->source_policy < INPAINT_SOURCE_ORIGINAL || p->source_policy > INPAINT_SOURCE_CURRENT) {
+        *why = "unknown source_policy";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    if (p->scoring < INPAINT_SCORE_WHOLE || p->scoring > INPAINT_SCORE_INTERSECT) {
+        *why = "unknown scoring";
+        return INPAINT_INVALID_ARGUMENT;
+    }
+    if (p->path == INPAINT_PATH_MFMA && (p->source_policy != INPAINT_SOURCE_ORIGINAL || p->scoring != INPAINT_SCORE_WHOLE)) {
+        *why = "the int8-MFMA search supports only the default candidate domain";
+        return INPAINT_INVALID_ARGUMENT;
+    }
     if (p->path == INPAINT_PATH_MFMA && p->tile_rows != 0 && p->tile_rows != kMfmaTileRows) {
         *why = "the int8-MFMA search uses tile_rows 16";
         return INPAINT_INVALID_ARGUMENT;
     }
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 1; ++i)
         if (p->reserved[i] != 0) {
             *why = "reserved fields must be zero";
             return INPAINT_INVALID_ARGUMENT;
@@ -247,7 +262,7 @@ static bool persistent_fits(const inpaint_ctx *c) {
     const JobDev &d = c->d;
     const int ntiles = d.ntx * d.nty;
     // (the committer scans at most 32 slots per thread)
-    if (c->direct) return false;
+    if (c->direct || c->d.policy != INPAINT_SOURCE_ORIGINAL || c->d.isect) return false;
     if ((!c->mfma && d.tile_rows != kFillTileRows) || ntiles <= 0 || ntiles > 32 * kCommitThreads) return false;
     if ((int64_t)d.W * d.H > (1ll << kSlotIndexBits)) return false;   // slot word index field
     int dev = 0, coop = 0, cus = 0, per_cu = 0;
@@ -269,6 +284,7 @@ int32_t inpaint_workspace_bytes(int32_t W, int32_t H, const inpaint_params *p, u
 
 // Kernel rectangle of candidate centres: the image-clipped rect further
 // clipped to [r, W - r) x [r, H - r), outside of which no centre is valid.
+// (INTERSECT scoring passes r = 0: its windows may leave the image.)
 static void kernel_rect(int W, int H, int r, const inpaint_rect &img_rect, int *k) {
     k[0] = std::max(img_rect.x0, r);
     k[1] = std::max(img_rect.y0, r);
@@ -348,6 +364,9 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     d.srcq = d.mfma ? (uint16_t *)(ws + L.srcq) : nullptr;
     d.srcp = (uint32_t *)(ws + L.srcp);
     d.vradp = ws + L.vradp;
+    d.hdist = L.hdist ? ws + L.hdist : nullptr;
+    d.policy = p->source_policy;
+    d.isect = p->scoring == INPAINT_SCORE_INTERSECT ? 1 : 0;
     d.pitch = padded_pitch(W);
     d.st = (IterState *)(ws + L.st);
     d.sync = (FillSync *)(ws + L.sync);
@@ -367,7 +386,7 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     const uint64_t n = (uint64_t)W * H;
     uint8_t *stage_rgb = (uint8_t *)d.pcd;
     uint8_t *stage_mask = stage_rgb + 4 * n;
-    uint8_t *hdist = stage_mask + n;
+    uint8_t *hdist = d.hdist ? d.hdist : stage_mask + n;
     hipStream_t s = c->stream;
     hipError_t e = hipMemcpy2DAsync(stage_rgb, (size_t)W * ch, img->data, img->stride_bytes, (size_t)W * ch, H,
                                     hipMemcpyHostToDevice, s);
@@ -397,7 +416,7 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     }
     c->rect = R;
     int k[4];
-    kernel_rect(W, H, d.r, R, k);
+    kernel_rect(W, H, d.isect ? 0 : d.r, R, k);
     d.rx0 = k[0];
     d.ry0 = k[1];
     d.rx1 = std::max(k[2], k[0]);
@@ -460,7 +479,7 @@ int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t tx, int32_t ty, int32_t 
     if (rect.x0 > rect.x1 || rect.y0 > rect.y1) return ctx->fail(INPAINT_INVALID_ARGUMENT, "x0 > x1 or y0 > y1");
     inpaint_rect R{std::max(rect.x0, 0), std::max(rect.y0, 0), std::min(rect.x1, d.W), std::min(rect.y1, d.H)};
     int k[4];
-    kernel_rect(d.W, d.H, r, R, k);
+    kernel_rect(d.W, d.H, d.isect ? 0 : r, R, k);
     if (k[2] <= k[0] || k[3] <= k[1]) return ctx->fail(INPAINT_NO_CANDIDATE, "no valid centre in the rect");
     JobDev q = d;
     q.rx0 = k[0];
@@ -995,6 +1014,8 @@ int32_t inpaint_batch_create(const inpaint_batch_params *bp, void *hip_stream, i
 
 int32_t inpaint_batch_attach(inpaint_batch *b, inpaint_ctx *ctx, int32_t *slot) {
     if (!b || !ctx || ctx->batch || ctx->sticky) return INPAINT_INVALID_ARGUMENT;
+    if (ctx->d.policy != INPAINT_SOURCE_ORIGINAL || ctx->d.isect)
+        return ctx->fail(INPAINT_INVALID_ARGUMENT, "a batch runs only the default candidate domain");
     int i = 0;
     while (i < (int)b->slots.size() && b->slots[i]) ++i;
     if (i == (int)b->slots.size()) return INPAINT_INVALID_ARGUMENT;

@@ -30,13 +30,13 @@ __device__ __forceinline__ void write_tile_min(uint64_t best, int t, uint64_t *_
 // Stages and scores one tile and writes its minimum key to out[t].  `live`
 // (uniform) is false when the fill loop has nothing pending: the tile is then
 // staged but neither scored nor written.
-template <int R, int NY>
+template <int R, int NY, bool ISECT = false>
 __device__ __forceinline__ void search_tile(const JobDev &d, const TargetStage *tg, bool live, int rx0, int ry0,
                                             int rx1, int ry1, int ntx, int t, uint64_t *__restrict__ out,
                                             uint32_t *lds, uint64_t *red) {
     int tx0, ty0;
     tile::tile_origin<R, NY>(rx0, ry0, ntx, t, &tx0, &ty0);
-    const uint32_t vmask = tile::stage_tile<R, NY>(d, tx0, ty0, rx1, ry1, lds);
+    const uint32_t vmask = tile::stage_tile<R, NY, ISECT>(d, tx0, ty0, rx1, ry1, lds);
     // one barrier publishes the LDS tile and tells whether any candidate of
     // the tile is valid
     if (!__syncthreads_or(live && vmask != 0)) {
@@ -44,7 +44,8 @@ __device__ __forceinline__ void search_tile(const JobDev &d, const TargetStage *
         return;
     }
     const ScalarTarget view{(tile::ConstTarget *)tg};
-    write_tile_min(tile::wave_min_u64(tile::score_tile<R, NY>(d, view, tx0, ty0, vmask, lds)), t, out, red);
+    write_tile_min(tile::wave_min_u64(tile::score_tile<R, NY, ScalarTarget, ISECT>(d, view, tx0, ty0, vmask, lds)),
+                   t, out, red);
 }
 
 // Consecutive work-groups are dispatched round-robin over the 8 XCDs; remap
@@ -55,7 +56,7 @@ __device__ __forceinline__ int xcd_band_tile(int bid, int grid) {
     return (bid & 7) * per + (bid >> 3);
 }
 
-template <int R, int NY>
+template <int R, int NY, bool ISECT>
 __global__ __launch_bounds__(kSearchWaves * 64) void k_search(JobDev d, int query, int rx0, int ry0,
                                                               int rx1, int ry1, int ntx, int ntiles) {
     using G = TileGeom<R, NY>;
@@ -70,12 +71,12 @@ __global__ __launch_bounds__(kSearchWaves * 64) void k_search(JobDev d, int quer
         const IterState *st = d.st;
         live = !(st->done || st->error || !st->pending || st->iter >= st->iter_limit);
     }
-    search_tile<R, NY>(d, query ? d.qtgt : d.tgt, live, rx0, ry0, rx1, ry1, ntx, t, d.partials, lds, red);
+    search_tile<R, NY, ISECT>(d, query ? d.qtgt : d.tgt, live, rx0, ry0, rx1, ry1, ntx, t, d.partials, lds, red);
 }
 
 // One tile scored straight from the padded plane (no LDS tile); otherwise
 // as k_search.
-template <int R, int NY>
+template <int R, int NY, bool ISECT>
 __global__ __launch_bounds__(kSearchWaves * 64) void k_search_direct(JobDev d, int query, int rx0, int ry0,
                                                                      int rx1, int ry1, int ntx, int ntiles) {
     __shared__ uint64_t red[kSearchWaves];
@@ -88,13 +89,14 @@ __global__ __launch_bounds__(kSearchWaves * 64) void k_search_direct(JobDev d, i
     }
     int tx0, ty0;
     tile::tile_origin<R, NY>(rx0, ry0, ntx, t, &tx0, &ty0);
-    const uint32_t vmask = tile::tile_valid<R, NY>(d, tx0, ty0, rx1, ry1);
+    const uint32_t vmask = tile::tile_valid<R, NY, ISECT>(d, tx0, ty0, rx1, ry1);
     if (!__syncthreads_or(live && vmask != 0)) {
         if (threadIdx.x == 0 && live) d.partials[t] = ~0ull;
         return;
     }
     const ScalarTarget view{(tile::ConstTarget *)(query ? d.qtgt : d.tgt)};
-    write_tile_min(tile::wave_min_u64(tile::score_direct<R, NY>(d, view, tx0, ty0, vmask)), t, d.partials, red);
+    write_tile_min(tile::wave_min_u64(tile::score_direct<R, NY, ScalarTarget, ISECT>(d, view, tx0, ty0, vmask)), t,
+                   d.partials, red);
 }
 
 // Persistent form over many images: work-groups stride over a static list of
@@ -124,7 +126,8 @@ hipError_t launch_search_t(const JobDev &d, bool query, int rx0, int ry0, int rx
     const int ntiles = ntx * nty;
     if (ntiles <= 0) return hipSuccess;
     const int grid = (ntiles + 7) / 8 * 8;
-    auto kernel = DIRECT ? k_search_direct<R, NY> : k_search<R, NY>;
+    auto kernel = DIRECT ? (d.isect ? k_search_direct<R, NY, true> : k_search_direct<R, NY, false>)
+                         : (d.isect ? k_search<R, NY, true> : k_search<R, NY, false>);
     if (start) {
         // The runtime stamps these events with the kernel's own begin / end.
         hipExtLaunchKernelGGL(kernel, dim3(grid), dim3(kSearchWaves * 64), 0, s, start, stop, 0, d,

@@ -83,6 +83,14 @@ __device__ __forceinline__ void load_target(const TargetStage *tg, TargetLds *t)
     if (threadIdx.x == 0) t->t2 = tg->t2;
 }
 
+// Smallest validity-plane value of a candidate centre: the patch radius
+// (its whole window is source) or, with INTERSECT scoring, 1 (the centre
+// itself is a source pixel).
+template <int R, bool ISECT>
+__device__ __forceinline__ constexpr uint32_t valid_min() {
+    return ISECT ? 1u : (uint32_t)R;
+}
+
 template <int R, int NY>
 struct TileGeom {
     static constexpr int P = 2 * R + 1;
@@ -110,7 +118,7 @@ __device__ __forceinline__ void tile_origin(int rx0, int ry0, int ntx, int tile,
 // then writes the window to LDS.  Returns this thread's candidate validity
 // bits (bit i: row i of its column); the caller publishes the LDS tile with
 // a barrier.
-template <int R, int NY>
+template <int R, int NY, bool ISECT = false>
 __device__ __forceinline__ uint32_t stage_tile(const JobDev &d, int tx0, int ty0, int rx1, int ry1, uint32_t *lds) {
     using G = TileGeom<R, NY>;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -138,13 +146,13 @@ __device__ __forceinline__ uint32_t stage_tile(const JobDev &d, int tx0, int ty0
     uint32_t vmask = 0;
 #pragma unroll
     for (int i = 0; i < NY; ++i)
-        if (x < rx1 && yb + i < ry1 && v[i] >= (uint32_t)R) vmask |= 1u << i;
+        if (x < rx1 && yb + i < ry1 && v[i] >= valid_min<R, ISECT>()) vmask |= 1u << i;
     return vmask;
 }
 
 // Validity bits of this thread's candidates (bit i: row i of its column) for
 // the tile at (tx0, ty0), without staging the tile.
-template <int R, int NY>
+template <int R, int NY, bool ISECT = false>
 __device__ __forceinline__ uint32_t tile_valid(const JobDev &d, int tx0, int ty0, int rx1, int ry1) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int x = tx0 + lane, yb = ty0 + wave * NY;
@@ -155,7 +163,7 @@ __device__ __forceinline__ uint32_t tile_valid(const JobDev &d, int tx0, int ty0
     uint32_t vmask = 0;
 #pragma unroll
     for (int i = 0; i < NY; ++i)
-        if (x < rx1 && yb + i < ry1 && v[i] >= (uint32_t)R) vmask |= 1u << i;
+        if (x < rx1 && yb + i < ry1 && v[i] >= valid_min<R, ISECT>()) vmask |= 1u << i;
     return vmask;
 }
 
@@ -163,7 +171,14 @@ __device__ __forceinline__ uint32_t tile_valid(const JobDev &d, int tx0, int ty0
 // minimum key (~0 if none is valid).  `colp` points at the source word of
 // this lane's column for offset (-R, -R) of its first candidate row;
 // consecutive rows are `stride` words apart.
-template <int R, int NY, class T>
+//
+// With INTERSECT scoring an offset counts only where the source pixel is a
+// source pixel too, flagged by the 4th byte of its word (1, else the word is
+// 0).  The cross and square terms need no change, because non-source words
+// are zero (the flag byte is masked out of the square term).  The target
+// term becomes per candidate: the sum of |t|^2 times the flag over the
+// target's known offsets.
+template <int R, int NY, bool ISECT, class T>
 __device__ __forceinline__ uint64_t score_cols(const JobDev &d, const T &tg, int tx0, int ty0, uint32_t vmask,
                                                const uint32_t *colp, int stride) {
     using G = TileGeom<R, NY>;
@@ -171,11 +186,12 @@ __device__ __forceinline__ uint64_t score_cols(const JobDev &d, const T &tg, int
     const int W = d.W;
     const int x = tx0 + lane, yb = ty0 + wave * NY;
 
-    uint32_t A[NY], S[NY];
+    uint32_t A[NY], S[NY], T2[NY];
 #pragma unroll
     for (int i = 0; i < NY; ++i) {
         A[i] = 0;
         S[i] = 0;
+        T2[i] = 0;
     }
     uint32_t mb[G::MW], sb[G::MW], eb[G::MW];
 #pragma unroll
@@ -195,7 +211,8 @@ __device__ __forceinline__ uint64_t score_cols(const JobDev &d, const T &tg, int
 #pragma unroll
         for (int j = 0; j < G::NJ; ++j) {
             col[j] = colp[j * stride + dxi];
-            pre[j + 1] = __builtin_amdgcn_udot4(col[j], col[j], pre[j], false);
+            const uint32_t c3 = ISECT ? (col[j] & 0x00ffffffu) : col[j];
+            pre[j + 1] = __builtin_amdgcn_udot4(c3, c3, pre[j], false);
         }
 #pragma unroll
         for (int dyi = 0; dyi < G::P; ++dyi) {
@@ -205,6 +222,11 @@ __device__ __forceinline__ uint64_t score_cols(const JobDev &d, const T &tg, int
                 const uint32_t t = tcol[dyi];
 #pragma unroll
                 for (int i = 0; i < NY; ++i) A[i] = __builtin_amdgcn_udot4(t, col[i + dyi], A[i], false);
+                if (ISECT) {
+                    const uint32_t tsq = __builtin_amdgcn_udot4(t, t, 0u, false);
+#pragma unroll
+                    for (int i = 0; i < NY; ++i) T2[i] += (col[i + dyi] >> 24) * tsq;
+                }
             }
             // The empty volatile asm keeps these blocks behind their scalar
             // branches (instead of being speculated into selects).
@@ -226,7 +248,7 @@ __device__ __forceinline__ uint64_t score_cols(const JobDev &d, const T &tg, int
 #pragma unroll
     for (int i = 0; i < NY; ++i) {
         if (vmask & (1u << i)) {
-            const uint32_t ssd = t2 - 2u * A[i] + S[i];
+            const uint32_t ssd = (ISECT ? T2[i] : t2) - 2u * A[i] + S[i];
             const uint64_t key = ((uint64_t)ssd << 32) | (uint32_t)((yb + i) * W + x);
             best = key < best ? key : best;
         }
@@ -235,24 +257,24 @@ __device__ __forceinline__ uint64_t score_cols(const JobDev &d, const T &tg, int
 }
 
 // Scores a tile staged in LDS by stage_tile.
-template <int R, int NY, class T>
+template <int R, int NY, class T, bool ISECT = false>
 __device__ __forceinline__ uint64_t score_tile(const JobDev &d, const T &tg, int tx0, int ty0, uint32_t vmask,
                                                const uint32_t *lds) {
     using G = TileGeom<R, NY>;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int sh = (tx0 - R + kPadL) & 3;
-    return score_cols<R, NY>(d, tg, tx0, ty0, vmask, lds + wave * NY * G::LW + lane + sh, G::LW);
+    return score_cols<R, NY, ISECT>(d, tg, tx0, ty0, vmask, lds + wave * NY * G::LW + lane + sh, G::LW);
 }
 
 // Scores the tile straight from the padded source plane in device memory
 // (through the vector caches), with no LDS staging.  The words read are a
 // subset of the window stage_tile loads, so the plane's padding covers them.
-template <int R, int NY, class T>
+template <int R, int NY, class T, bool ISECT = false>
 __device__ __forceinline__ uint64_t score_direct(const JobDev &d, const T &tg, int tx0, int ty0, uint32_t vmask) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int x = tx0 + lane, yb = ty0 + wave * NY;
     const uint32_t *colp = d.srcp + (int64_t)(yb - R + kPadT) * d.pitch + (x - R + kPadL);
-    return score_cols<R, NY>(d, tg, tx0, ty0, vmask, colp, d.pitch);
+    return score_cols<R, NY, ISECT>(d, tg, tx0, ty0, vmask, colp, d.pitch);
 }
 
 // Minimum over the wave.  (Kept out of score_tile: inlined there it makes
