@@ -95,6 +95,10 @@ def parse():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--path", default="mfma", choices=["mfma", "simt", "direct"],
                     help="exemplar-search kernel (direct: SIMT without LDS staging)")
+    ap.add_argument("--source-policy", default="original", choices=["original", "current"],
+                    help="candidate domain: filled pixels become sources (current)")
+    ap.add_argument("--scoring", default="whole", choices=["whole", "intersect"],
+                    help="candidate domain: score overlapping candidates on the known intersection")
     ap.add_argument("--sweep-part", default="both", choices=["both", "alpha", "lds"],
                     help="sweep: the persistent alpha x P timings, the LDS staging study, or both")
     ap.add_argument("--no-other-form", action="store_true")
@@ -123,13 +127,16 @@ def search_kernel_name(path, r, tile_rows):
     return f"k_search{'_direct' if path == 'direct' else ''}<R={r},NY={tile_rows or 8}>"
 
 
-def timed_removals(job, n_steps, n_warmup, form, iters_per_check, tile_rows, timing=True, path="simt"):
+def timed_removals(job, n_steps, n_warmup, form, iters_per_check, tile_rows, timing=True, path="simt",
+                   domain=("original", "whole")):
     """Runs n_warmup + n_steps removals; times the last n_steps together."""
     import torch
     from paper_1403_4238_amd import binding as B
+    policy = B.SOURCE_CURRENT if domain[0] == "current" else B.SOURCE_ORIGINAL
+    scoring = B.SCORE_INTERSECT if domain[1] == "intersect" else B.SCORE_WHOLE
     ctxs = [B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, rect=job.rect,
                         form=form, iters_per_check=iters_per_check, tile_rows=tile_rows,
-                        path=path_id(path))
+                        path=path_id(path), source_policy=policy, scoring=scoring)
             for _ in range(n_warmup + n_steps)]
     for c in ctxs[:n_warmup]:
         c.run()
@@ -447,7 +454,12 @@ def main():
     if a.workload == "copy":
         return copy_bench(a)
     job = make_job(a)
-    res = timed_removals(job, a.steps, a.warmup, a.form, a.iters_per_check, a.tile_rows, path=a.path)
+    domain = (a.source_policy, a.scoring)
+    if domain != ("original", "whole") and (a.path == "mfma" or a.form == "persistent"):
+        sys.exit("the candidate-domain variants run on the SIMT search (--path simt|direct) in the "
+                 "plain / stream / graph forms")
+    res = timed_removals(job, a.steps, a.warmup, a.form, a.iters_per_check, a.tile_rows, path=a.path,
+                         domain=domain)
     n_steps = a.steps
     evals = sum(res["iters"]) * res["candidates"]
     value = evals / res["seconds"]
@@ -478,7 +490,8 @@ def main():
         for form in ("stream", "graph"):
             if form == res["run_form"]:
                 continue
-            o = timed_removals(job, 1, 0, form, a.iters_per_check, a.tile_rows, timing=(form == "stream"), path=a.path)
+            o = timed_removals(job, 1, 0, form, a.iters_per_check, a.tile_rows, timing=(form == "stream"),
+                               path=a.path, domain=domain)
             rec = {"ms_per_removal": round(1000 * o["seconds"], 2),
                    "patch_evals_per_s": round(sum(o["iters"]) * o["candidates"] / o["seconds"], 1)}
             if form == "stream":
@@ -504,6 +517,8 @@ def main():
                         f"{2 * r + 1}x{2 * r + 1} patch, "
                         f"{'alpha=1 window' if a.window else 'full search'}, "
                         f"{'int8-MFMA' if a.path == 'mfma' else 'SIMT dot4'} search, "
+                        + ("" if domain == ("original", "whole") else
+                           f"candidate domain {a.source_policy} sources / {a.scoring} scoring, ") +
                         f"{res['run_form']} form" + (f" ({a.iters_per_check} iterations per host check)"
                                                      if a.form != "plain" else ""),
             "width": job.width, "height": job.height, "patch": 2 * r + 1,
@@ -513,7 +528,8 @@ def main():
         },
         "ms_per_removal": round(ms_per_step, 3),
         "iterations_per_s": round(sum(res["iters"]) / res["seconds"], 1),
-        "parity": golden_check(job, a, log, res["image"]),
+        "parity": (golden_check(job, a, log, res["image"]) if domain == ("original", "whole")
+                   else "no stored oracle result for this candidate domain (parity: tests/test_domains_gpu.py)"),
         "roofline": {
             "bound": "mfma" if a.path == "mfma" else "alu",
             "kernel": kernel,

@@ -79,6 +79,10 @@ def lib():
         L.oracle_get_rect.restype = i32
         L.oracle_remaining.argtypes = [vp]
         L.oracle_remaining.restype = i64
+        L.oracle_import_state.argtypes = [vp, vp, i32, i32, vp, i32, vp, i64]
+        L.oracle_import_state.restype = i32
+        L.oracle_iterations.argtypes = [vp]
+        L.oracle_iterations.restype = i64
         L.oracle_step_info_size.argtypes = []
         L.oracle_step_info_size.restype = i32
         assert L.oracle_step_info_size() == STEP_DTYPE.itemsize
@@ -203,3 +207,23 @@ class Oracle:
 
     def remaining(self) -> int:
         return int(lib().oracle_remaining(self._h))
+
+    def iterations(self) -> int:
+        return int(lib().oracle_iterations(self._h))
+
+    def export_state(self):
+        """(rgb, hole, conf, iterations): what import_state takes back."""
+        rgb, _, hole, conf = self.read()
+        return rgb, hole, conf, self.iterations()
+
+    def import_state(self, rgb: np.ndarray, hole: np.ndarray, conf: np.ndarray, iterations: int):
+        """Continues from a checkpoint of the same removal (see oracle.c)."""
+        rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+        hole = np.ascontiguousarray(hole, dtype=np.uint8)
+        conf = np.ascontiguousarray(conf, dtype=np.float64)
+        assert rgb.shape[:2] == hole.shape == conf.shape == (self.H, self.W)
+        ch = rgb.shape[2]
+        st = lib().oracle_import_state(self._h, _ptr(rgb), self.W * ch, ch, _ptr(hole), self.W, _ptr(conf),
+                                       int(iterations))
+        if st != OK:
+            raise OracleError(st, "oracle_import_state")

@@ -568,6 +568,62 @@ int oracle_run(oracle_state *s, int64_t max_iters, int64_t *iters_done,
     return st;
 }
 
+/* ------------------------------------------------------------- resume */
+
+/* Iterative editing / resume (the paper's interactive workflow, Section 6):
+ * replaces the fill state of a removal by a checkpoint of the same removal
+ * -- the image, the hole still to fill, the confidence map and the number of
+ * iterations done -- so that continuing from it gives what the uninterrupted
+ * run gives.  The state is defined by the original hole (fixed at create),
+ * so only pixels of the original hole change:
+ *   - those still in the checkpoint's hole become hole again (zeroed, R1);
+ *   - the others take the checkpoint's colour, its confidence and the gray
+ *     value R2 gives for that colour.
+ * Pixels outside the original hole keep the values given at create.  The
+ * checkpoint's hole must lie inside the original hole, and its confidences
+ * there must be in [0, 1]; otherwise nothing changes. */
+int oracle_import_state(oracle_state *s, const uint8_t *rgb, int32_t rgb_stride,
+                        int32_t channels, const uint8_t *hole, int32_t hole_stride,
+                        const double *conf, int64_t iterations)
+{
+    if (!s || !rgb || !hole || !conf || iterations < 0 || (channels != 3 && channels != 4))
+        return OR_INVALID_ARGUMENT;
+    int W = s->W, H = s->H;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int64_t i = (int64_t)y * W + x;
+            int h = hole[(int64_t)y * hole_stride + x] != 0;
+            if (h && !s->hole0[i])
+                return OR_INVALID_ARGUMENT;
+            if (s->hole0[i] && !h && !(conf[i] >= 0.0 && conf[i] <= 1.0))
+                return OR_INVALID_ARGUMENT;
+        }
+    int64_t remaining = 0;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int64_t i = (int64_t)y * W + x;
+            if (!s->hole0[i])
+                continue;
+            int h = hole[(int64_t)y * hole_stride + x] != 0;
+            const uint8_t *px = rgb + (int64_t)y * rgb_stride + (int64_t)x * channels;
+            for (int c = 0; c < 3; ++c)
+                s->rgb[i * 3 + c] = h ? 0 : px[c];
+            s->gray[i] = (uint8_t)((299 * s->rgb[i * 3] + 587 * s->rgb[i * 3 + 1] +
+                                    114 * s->rgb[i * 3 + 2] + 500) / 1000);
+            s->conf[i] = h ? 0.0 : conf[i];
+            s->hole[i] = (uint8_t)h;
+            remaining += h;
+        }
+    s->remaining = remaining;
+    s->iter = iterations;
+    return OR_OK;
+}
+
+int64_t oracle_iterations(const oracle_state *s)
+{
+    return s->iter;
+}
+
 /* -------------------------------------------------------------- accessors */
 
 int oracle_read(const oracle_state *s, uint8_t *rgb, uint8_t *gray,
