@@ -233,6 +233,34 @@ int32_t inpaint_remaining(inpaint_ctx *ctx, int64_t *remaining);
  * Synchronises. */
 int32_t inpaint_progress(inpaint_ctx *ctx, int64_t *iterations, int64_t *remaining);
 
+/* Resume / iterative editing (the interactive workflow of Section 6).
+ * Replaces the fill state of `ctx` by a checkpoint of the same removal, as
+ * inpaint_read_image, inpaint_read_state and inpaint_progress return it:
+ *   - the image: `rgb`, rows of `rgb_stride` bytes, `channels` 3 or 4;
+ *   - the hole still to fill: `hole`, nonzero = to fill, rows of
+ *     `hole_stride` bytes;
+ *   - the confidence map: `conf`, width*height doubles, row-major;
+ *   - `iterations` already done.
+ * Continuing from it gives exactly what the uninterrupted run gives: the
+ * same fill order, with log records numbered from `iterations` on (size
+ * log_capacity for the whole removal).
+ *
+ * Only pixels of the context's original hole change: those still in the
+ * checkpoint's hole become hole again, and the others take the checkpoint's
+ * colour and confidence.  Pixels outside the original hole keep the values
+ * given at create, so a context created from the checkpoint image and the
+ * original mask can resume.  Host inputs are copied.  Legal between runs on
+ * a context not attached to a batch.
+ *
+ * Errors: INVALID_ARGUMENT, with the state unchanged, if
+ *   - the hole leaves the original hole;
+ *   - a filled pixel's confidence is not in [0, 1];
+ *   - iterations < 0;
+ *   - a pointer is NULL, channels is wrong or a stride is too small.
+ * Synchronises. */
+int32_t inpaint_import_state(inpaint_ctx *ctx, const uint8_t *rgb, int32_t rgb_stride, int32_t channels,
+                             const uint8_t *hole, int32_t hole_stride, const double *conf, int64_t iterations);
+
 /* The context's search rectangle after clipping (alpha windows resolved) and
  * the number of valid source centres in it, i.e. patch evaluations per
  * search.  No device work. */

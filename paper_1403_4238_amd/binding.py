@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
         "inpaint_profile_search": (i32, [vp, i32]),
         "inpaint_search_time": (i32, [vp, P(ctypes.c_double), P(i64)]),
         "inpaint_run_form": (i32, [vp, P(i32)]),
+        "inpaint_import_state": (i32, [vp, vp, i32, i32, vp, i32, vp, i64]),
         "inpaint_destroy": (i32, [vp]),
         "inpaint_status_string": (ctypes.c_char_p, [i32]),
         "inpaint_last_error": (ctypes.c_char_p, [vp]),
@@ -255,6 +256,23 @@ class Inpainter:
         it, rem = ctypes.c_int64(), ctypes.c_int64()
         self._check(lib().inpaint_progress(self.ctx, ctypes.byref(it), ctypes.byref(rem)), "inpaint_progress")
         return it.value, rem.value
+
+    def export_state(self):
+        """(rgb, hole, conf, iterations): a checkpoint that import_state takes back."""
+        hole, conf = self.read_state()
+        return self.read_image(), hole, conf, self.progress()[0]
+
+    def import_state(self, rgb: np.ndarray, hole: np.ndarray, conf: np.ndarray, iterations: int):
+        """Continues this removal from a checkpoint of it (inpaint_import_state)."""
+        rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+        hole = np.ascontiguousarray(hole, dtype=np.uint8)
+        conf = np.ascontiguousarray(conf, dtype=np.float64)
+        if rgb.shape[:2] != (self.height, self.width) or hole.shape != rgb.shape[:2] or conf.shape != hole.shape:
+            raise ValueError("checkpoint shape does not match the context")
+        ch = rgb.shape[2]
+        self._check(lib().inpaint_import_state(self.ctx, rgb.ctypes.data, self.width * ch, ch, hole.ctypes.data,
+                                               self.width, conf.ctypes.data, int(iterations)),
+                    "inpaint_import_state")
 
     def profile_search(self, enable: bool = True):
         self._check(lib().inpaint_profile_search(self.ctx, 1 if enable else 0), "inpaint_profile_search")

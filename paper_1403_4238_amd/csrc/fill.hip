@@ -741,6 +741,7 @@ __device__ __forceinline__ int stage_target_lds(const LdsStage<R> &L, int px, in
 
 __global__ void k_init_info(InitInfo *info) {
     info->hole_count = 0;
+    info->bad = 0;
     info->bx0 = INT32_MAX;
     info->by0 = INT32_MAX;
     info->bx1 = INT32_MIN;
@@ -772,6 +773,7 @@ __global__ __launch_bounds__(256) void k_init_pixels(JobDev d, const uint8_t *rg
         d.img[i] = R | (G << 8) | (B << 16);
         d.gray[i] = (uint8_t)((299 * R + 587 * G + 114 * B + 500) / 1000);
         d.hole[i] = h ? 1 : 0;
+        d.hole0[i] = h ? 1 : 0;
         d.conf[i] = h ? 0.0 : 1.0;
         if (h) {
             atomicAdd(&s_cnt, 1);
@@ -789,6 +791,51 @@ __global__ __launch_bounds__(256) void k_init_pixels(JobDev d, const uint8_t *rg
         atomicMax(&d.info->bx1, s_x1);
         atomicMax(&d.info->by1, s_y1);
     }
+}
+
+// ---- checkpoint import (resume / iterative editing) ------------------------
+
+// Counts the pixels of a checkpoint that fail its checks: a hole pixel
+// outside the original hole, or a filled pixel of the original hole whose
+// confidence is not in [0, 1] (NaN included).  Writes nothing else.
+__global__ __launch_bounds__(256) void k_import_check(JobDev d, const uint8_t *hole, const double *conf) {
+    const int64_t n = (int64_t)d.W * d.H;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int bad = 0;
+    if (i < n) {
+        const bool h = hole[i] != 0, h0 = d.hole0[i] != 0;
+        const double c = conf[i];
+        bad = (h && !h0) || (h0 && !h && !(c >= 0.0 && c <= 1.0));
+    }
+    if (bad) atomicAdd((unsigned long long *)&d.info->bad, 1ull);
+}
+
+// Overlays a checked checkpoint on the original-hole pixels: those still in
+// its hole become hole again (zeroed), the others take its colour, the gray
+// value of that colour and its confidence.  Other pixels keep their values.
+__global__ __launch_bounds__(256) void k_import_apply(JobDev d, const uint8_t *rgb, int ch, const uint8_t *hole,
+                                                      const double *conf) {
+    const int64_t n = (int64_t)d.W * d.H;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int s_cnt;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    if (i < n && d.hole0[i]) {
+        const bool h = hole[i] != 0;
+        const uint32_t R = h ? 0 : rgb[i * ch], G = h ? 0 : rgb[i * ch + 1], B = h ? 0 : rgb[i * ch + 2];
+        d.img[i] = R | (G << 8) | (B << 16);
+        d.gray[i] = (uint8_t)((299 * R + 587 * G + 114 * B + 500) / 1000);
+        d.hole[i] = h ? 1 : 0;
+        d.conf[i] = h ? 0.0 : conf[i];
+        if (h) atomicAdd(&s_cnt, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt > 0) atomicAdd((unsigned long long *)&d.info->hole_count, (unsigned long long)s_cnt);
+}
+
+__global__ void k_import_reset(InitInfo *info) {
+    info->hole_count = 0;
+    info->bad = 0;
 }
 
 // Horizontal distance (capped at 10) from each pixel to the nearest hole or
@@ -1604,6 +1651,28 @@ hipError_t launch_init(const JobDev &d, const uint8_t *stage_rgb, int channels,
                        (const uint8_t *)hdist);
     const int64_t np = (int64_t)d.pitch * padded_rows(d.H);
     hipLaunchKernelGGL(k_init_padded, dim3(blocks_for(np, 256)), dim3(256), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_import_check(const JobDev &d, const uint8_t *hole, const double *conf, hipStream_t s) {
+    const int64_t n = (int64_t)d.W * d.H;
+    hipLaunchKernelGGL(k_import_reset, dim3(1), dim3(1), 0, s, d.info);
+    hipLaunchKernelGGL(k_import_check, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, hole, conf);
+    return hipGetLastError();
+}
+
+hipError_t launch_import_apply(const JobDev &d, const uint8_t *rgb, int channels, const uint8_t *hole,
+                               const double *conf, uint8_t *hdist, hipStream_t s) {
+    const int64_t n = (int64_t)d.W * d.H;
+    hipLaunchKernelGGL(k_import_reset, dim3(1), dim3(1), 0, s, d.info);
+    hipLaunchKernelGGL(k_import_apply, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, rgb, channels, hole, conf);
+    if (d.policy == INPAINT_SOURCE_CURRENT) {
+        // the source region is the current known region: rebuild its planes
+        hipLaunchKernelGGL(k_init_hdist, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, hdist);
+        hipLaunchKernelGGL(k_init_vrad, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, (const uint8_t *)hdist);
+        const int64_t np = (int64_t)d.pitch * padded_rows(d.H);
+        hipLaunchKernelGGL(k_init_padded, dim3(blocks_for(np, 256)), dim3(256), 0, s, d);
+    }
     return hipGetLastError();
 }
 

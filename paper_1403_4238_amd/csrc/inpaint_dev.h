@@ -129,6 +129,7 @@ struct InitInfo {
     int64_t hole_count;
     int32_t bx0, by0, bx1, by1;  // bounding box of the hole, half-open
     int64_t valid_count;         // valid source centres in the search rect
+    int64_t bad;                 // pixels of an imported checkpoint that fail its checks
 };
 
 // Everything a kernel needs about one job.  Passed by value to the
@@ -137,6 +138,7 @@ struct JobDev {
     uint32_t *img;       // RGBX, W*H
     uint8_t *gray;       // W*H
     uint8_t *hole;       // W*H, 1 = still to fill
+    uint8_t *hole0;      // W*H, 1 = in the original hole (fixed at create)
     uint8_t *vrad;       // W*H, largest r <= 8 with a valid patch at the centre
     double *conf;        // W*H
     double2 *pcd;        // W*H (C, D) of front pixels; C = -1 elsewhere
@@ -183,6 +185,13 @@ struct WorkItem {
 hipError_t launch_init(const JobDev &d, const uint8_t *stage_rgb, int channels,
                        const uint8_t *stage_mask, uint8_t *hdist, hipStream_t s);
 hipError_t launch_count_valid(const JobDev &d, hipStream_t s);
+// Checkpoint import: the checks (counted into info->bad, nothing written),
+// then the overlay of the original-hole pixels (remaining hole counted into
+// info->hole_count) and, under the CURRENT source policy, the rebuilt source
+// and validity planes.
+hipError_t launch_import_check(const JobDev &d, const uint8_t *hole, const double *conf, hipStream_t s);
+hipError_t launch_import_apply(const JobDev &d, const uint8_t *rgb, int channels, const uint8_t *hole,
+                               const double *conf, uint8_t *hdist, hipStream_t s);
 hipError_t launch_prio_init(const JobDev &d, hipStream_t s);
 hipError_t launch_commit(const JobDev &d, hipStream_t s);
 // SIMT search of one target; `d.isect` selects INTERSECT scoring.

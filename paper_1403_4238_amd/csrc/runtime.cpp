@@ -31,7 +31,7 @@ constexpr int kDefaultTileRows = 8;
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t img, gray, hole, vrad, conf, pcd, blk, partials, tgt, qtgt, frag, qfrag, srcw, srcq, srcp, vradp, hdist, st,
+    uint64_t img, gray, hole, hole0, vrad, conf, pcd, blk, partials, tgt, qtgt, frag, qfrag, srcw, srcq, srcp, vradp, hdist, st,
         sync, fslot, info, key, log, total;
     int64_t log_cap;
     int max_tiles;
@@ -55,6 +55,7 @@ Layout make_layout(int W, int H, const inpaint_params &p) {
     L.img = take(4 * n);
     L.gray = take(n);
     L.hole = take(n);
+    L.hole0 = take(n);
     L.vrad = take(n);
     L.conf = take(8 * n);
     L.pcd = take(16 * n);  // also the upload staging area during create (<= 6n bytes)
@@ -350,6 +351,7 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     d.img = (uint32_t *)(ws + L.img);
     d.gray = ws + L.gray;
     d.hole = ws + L.hole;
+    d.hole0 = ws + L.hole0;
     d.vrad = ws + L.vrad;
     d.conf = (double *)(ws + L.conf);
     d.pcd = (double2 *)(ws + L.pcd);
@@ -702,6 +704,60 @@ int32_t inpaint_progress(inpaint_ctx *ctx, int64_t *iterations, int64_t *remaini
     HIP_OR_FAIL(ctx, ctx->pull_state(), "state");
     if (iterations) *iterations = ctx->h_state->iter;
     if (remaining) *remaining = ctx->h_state->remaining;
+    return INPAINT_OK;
+}
+
+int32_t inpaint_import_state(inpaint_ctx *ctx, const uint8_t *rgb, int32_t rgb_stride, int32_t channels,
+                             const uint8_t *hole, int32_t hole_stride, const double *conf, int64_t iterations) {
+    if (!ctx) return INPAINT_INVALID_ARGUMENT;
+    if (ctx->sticky) return ctx->sticky;
+    if (ctx->batch) return ctx->fail(INPAINT_INVALID_ARGUMENT, "context is attached to a batch");
+    const JobDev &d = ctx->d;
+    const int W = d.W, H = d.H;
+    if (!rgb || !hole || !conf) return ctx->fail(INPAINT_INVALID_ARGUMENT, "NULL checkpoint array");
+    if (channels != 3 && channels != 4) return ctx->fail(INPAINT_INVALID_ARGUMENT, "channels must be 3 or 4");
+    if (rgb_stride < W * channels || hole_stride < W)
+        return ctx->fail(INPAINT_INVALID_ARGUMENT, "row stride smaller than a row");
+    if (iterations < 0) return ctx->fail(INPAINT_INVALID_ARGUMENT, "iterations must be >= 0");
+    hipStream_t s = ctx->stream;
+    // Staging in the priority-term plane (16 bytes per pixel, rebuilt below):
+    // colours [0, 4n), hole [4n, 5n), row distances [5n, 6n), confidences [8n, 16n).
+    const uint64_t n = (uint64_t)W * H;
+    uint8_t *stage = (uint8_t *)d.pcd;
+    uint8_t *s_rgb = stage, *s_hole = stage + 4 * n, *s_hdist = stage + 5 * n;
+    double *s_conf = (double *)(stage + 8 * n);
+    HIP_OR_FAIL(ctx, hipMemcpy2DAsync(s_rgb, (size_t)W * channels, rgb, rgb_stride, (size_t)W * channels, H,
+                                      hipMemcpyHostToDevice, s), "upload");
+    HIP_OR_FAIL(ctx, hipMemcpy2DAsync(s_hole, W, hole, hole_stride, W, H, hipMemcpyHostToDevice, s), "upload");
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(s_conf, conf, 8 * n, hipMemcpyHostToDevice, s), "upload");
+    HIP_OR_FAIL(ctx, launch_import_check(d, s_hole, s_conf, s), "check");
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_key, d.info, sizeof(InitInfo), hipMemcpyDeviceToHost, s), "check");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(s), "check");
+    InitInfo info;
+    std::memcpy(&info, ctx->h_key, sizeof(info));
+    if (info.bad != 0) {
+        // nothing changed but the priority terms the staging overwrote
+        HIP_OR_FAIL(ctx, launch_prio_init(d, s), "restore");
+        HIP_OR_FAIL(ctx, hipStreamSynchronize(s), "restore");
+        return ctx->fail(INPAINT_INVALID_ARGUMENT,
+                         "checkpoint hole leaves the original hole, or a filled pixel's confidence is not in [0, 1]");
+    }
+    HIP_OR_FAIL(ctx, launch_import_apply(d, s_rgb, channels, s_hole, s_conf, d.hdist ? d.hdist : s_hdist, s),
+                "import");
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_key, d.info, sizeof(InitInfo), hipMemcpyDeviceToHost, s), "import");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(s), "import");
+    std::memcpy(&info, ctx->h_key, sizeof(info));
+    IterState &h = *ctx->h_state;
+    std::memset(&h, 0, sizeof(h));
+    h.remaining = info.hole_count;
+    h.iter = iterations;
+    h.iter_limit = INT64_MAX;
+    h.done = info.hole_count == 0 ? 1 : 0;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(d.st, &h, sizeof(IterState), hipMemcpyHostToDevice, s), "state");
+    HIP_OR_FAIL(ctx, launch_prio_init(d, s), "priorities");
+    HIP_OR_FAIL(ctx, launch_commit(d, s), "select");   // selects and stages the next target
+    HIP_OR_FAIL(ctx, ctx->pull_state(), "state");
+    if (ctx->h_state->error) return ctx->hip_fail(hipErrorUnknown, "device error during the selection");
     return INPAINT_OK;
 }
 

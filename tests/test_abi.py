@@ -28,7 +28,8 @@ def so():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ["inpaint_create", "inpaint_find_exemplar", "inpaint_step", "inpaint_run",
-                     "inpaint_workspace_bytes", "inpaint_batch_step", "inpaint_destroy"]:
+                     "inpaint_workspace_bytes", "inpaint_batch_step", "inpaint_destroy",
+                     "inpaint_import_state"]:
         assert required in names
 
 
@@ -57,9 +58,10 @@ def test_library_loads_and_host_only_calls(so):
     assert f(1920, 1080, ctypes.byref(p), ctypes.byref(b)) == 0
     n = 1920 * 1080
     npad = ((8 + 1920 + 84 + 7) // 8 * 8) * (8 + 1080 + 72)
-    # RGBX + gray + hole + validity + confidence + cached priority terms (C, D),
-    # the padded static search planes (RGBX + validity), plus small tables
-    base = 4 * n + 3 * n + 8 * n + 16 * n + 5 * npad
+    # RGBX + gray + hole + original hole + validity + confidence + cached
+    # priority terms (C, D), the padded search planes (RGBX + validity), plus
+    # small tables
+    base = 4 * n + 4 * n + 8 * n + 16 * n + 5 * npad
     assert base <= b.value < base + 2_000_000
     p.log_capacity = 1000
     b2 = ctypes.c_uint64()
