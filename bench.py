@@ -56,11 +56,9 @@ HBM_PEAK_GBS = 8000.0
 # the kernel's sources it was taken on; once they change it reports null.
 TRAFFIC_BYTES_PER_LAUNCH = {
     ("k_fill_mfma<R=4>", "hd-1920x1080-p9-full"): {
-        "bytes": 42789415, "fetch_kib": 16888.57, "write_kib": 8009.39,
+        "bytes": 42667790, "fetch_kib": 16829.19, "write_kib": 8009.39,
         "sources": ["inpaint_dev.h", "search_tile.h", "search_mfma_tile.h", "fill.hip"],
-        # (re-hashed after a change to the SIMT tile code that left this
-        # kernel's machine code identical, checked on its assembly)
-        "sha256_16": "452d611e3f74ba8d"},
+        "sha256_16": "04e3dd4a292201a8"},
 }
 
 
@@ -82,7 +80,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="hd", choices=["hd", "vga", "small", "batch", "serve", "sweep", "copy"])
+    ap.add_argument("--workload", default="hd", choices=["hd", "vga", "small", "batch", "serve", "sweep", "copy", "resume"])
     ap.add_argument("--jobs", type=int, default=32, help="serve: number of jobs")
     ap.add_argument("--graph-iters", type=int, default=16, help="batch / serve: iterations per replay")
     ap.add_argument("--capacity", type=int, default=16, help="serve: batch slots")
@@ -200,9 +198,10 @@ def _cpu_name():
     return "unknown"
 
 
-def golden_check(job, a, log, image):
+def golden_check(job, a, log, image, workload=None):
+    wl = workload or a.workload
     key = {("hd", 9, False): "hd9", ("hd", 9, True): "hd9w", ("hd", 13, False): "hd13",
-           ("hd", 13, True): "hd13w"}.get((a.workload, a.patch, a.window), a.workload)
+           ("hd", 13, True): "hd13w"}.get((wl, a.patch, a.window), wl)
     path = os.path.join(ROOT, "tests", "golden", f"oracle_{key}.json")
     if not os.path.exists(path):
         return "no stored oracle result"
@@ -281,6 +280,51 @@ def sweep_bench(a):
     print(json.dumps({"metric": "alpha x patch-size sweep on paper-shaped stand-ins (ms per removal)",
                       "unit": "ms per removal", "n_gpus": 1, "data": "synthetic (seeded)",
                       "seconds_total": round(time.perf_counter() - t_all, 2), "sweep": rows}), flush=True)
+
+
+def resume_bench(a):
+    """Iterative editing / resume at 1080p: the removal is stopped half way,
+    exported (image, hole, confidences, iteration count), imported into a
+    new context created from the checkpoint image and finished there; the
+    joined fill log and final image must match the stored oracle result."""
+    import torch
+    from paper_1403_4238_amd import binding as B
+    job = synth_hd(a)
+    kw = dict(form=a.form, iters_per_check=a.iters_per_check, path=path_id(a.path))
+    full = B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, **kw)
+    full.run()                                   # warm-up of the same removal
+    full.close()
+    g1 = B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, **kw)
+    half = 1878
+    _, n1, log1 = g1.run(max_iters=half, log_cap=half)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ck = g1.export_state()
+    t1 = time.perf_counter()
+    g2 = B.Inpainter(ck[0], job.mask, job.patch_radius, job.search_mode, job.alpha, **kw)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g2.import_state(*ck)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    st, n2, log2 = g2.run(log_cap=job.mask.size)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    log = np.concatenate([log1, log2])
+    parity = golden_check(job, a, log, g2.read_image(), workload="hd")
+    print(json.dumps({"metric": "resume from a checkpoint (1080p 9x9 full search, stopped half way)",
+                      "value": round(1000 * (t3 - t2), 3), "unit": "ms per import", "n_gpus": 1,
+                      "higher_is_better": False, "data": "synthetic (seeded)",
+                      "config": {"workload": f"{job.name}, checkpoint after {n1} of {n1 + n2} iterations, "
+                                             f"{g2.run_form()} form"},
+                      "export_ms": round(1000 * (t1 - t0), 3), "create_ms": round(1000 * (t2 - t1), 3),
+                      "import_ms": round(1000 * (t3 - t2), 3), "finish_ms": round(1000 * (t4 - t3), 3),
+                      "parity": parity}), flush=True)
+
+
+def synth_hd(a):
+    from paper_1403_4238_amd import synth
+    return synth.hd(patch=a.patch, window=a.window)
 
 
 def copy_bench(a):
@@ -453,6 +497,8 @@ def main():
         return sweep_bench(a)
     if a.workload == "copy":
         return copy_bench(a)
+    if a.workload == "resume":
+        return resume_bench(a)
     job = make_job(a)
     domain = (a.source_policy, a.scoring)
     if domain != ("original", "whole") and (a.path == "mfma" or a.form == "persistent"):
