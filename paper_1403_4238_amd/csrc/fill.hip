@@ -78,6 +78,8 @@ struct LdsStage {
     double2 wcd[WIN * WIN];         // (C, D) of the window pixels
     int16_t front[WIN * WIN];       // window pixels on the front (window-local index)
     int nfront;
+    double fsum[64];                // per front pixel of a round: confidence sum
+    int fbest[2][64], fbxy[2][64];  // and the best gradient of the top / bottom rows
 };
 
 template <int R>
@@ -162,65 +164,80 @@ __device__ void priority_terms(const V &v, int px, int py, double norm1, double 
     }
 }
 
-// Eq. 2 on the LDS neighbourhood, same operation order as priority_terms.
-// The patch is read one row ahead of the arithmetic: each row's P
-// confidences, gradient magnitudes and packed gradients are loaded together
-// while the previous row is summed, so the serial FP64 chain of the
-// confidence sum does not wait for an LDS round trip every few terms.
+// The confidence sum of Eq. 2 at (px, py) on the LDS neighbourhood, in
+// raster order as priority_terms adds it (rows read one ahead of the adds).
 template <int R>
-__device__ void priority_terms_lds(const LdsView<R> &v, int px, int py, double norm1, double norm2, double *C,
-                                   double *D) {
+__device__ double conf_sum_lds(const LdsView<R> &v, int px, int py) {
     constexpr int P = 2 * R + 1, side = LdsView<R>::side;
-    const int base = v.at(px - R, py - R);
-    const double *cf = v.s.conf + base;
-    const int *mg = v.s.mag + base;
-    const int *gp = v.s.gxy + base;
+    const double *cf = v.s.conf + v.at(px - R, py - R);
     double c0[P], c1[P];
-    int m0[P], m1[P], g0[P], g1[P];
 #pragma unroll
-    for (int dx = 0; dx < P; ++dx) {
-        c0[dx] = cf[dx];
-        m0[dx] = mg[dx];
-        g0[dx] = gp[dx];
-    }
+    for (int dx = 0; dx < P; ++dx) c0[dx] = cf[dx];
     double sum = 0.0;
-    int best = -1, bxy = 0;
-    // (rolled: unrolled, the compiler hoists every row's loads at once)
 #pragma unroll 1
     for (int dy = 0; dy < P; ++dy) {
         // the row after the last one is still inside the staged square
 #pragma unroll
+        for (int dx = 0; dx < P; ++dx) c1[dx] = cf[(dy + 1) * side + dx];
+#pragma unroll
+        for (int dx = 0; dx < P; ++dx) sum = sum + c0[dx];
+#pragma unroll
+        for (int dx = 0; dx < P; ++dx) c0[dx] = c1[dx];
+    }
+    return sum;
+}
+
+// The largest gradient magnitude of the patch rows dy0 .. dy1 - 1 (offsets
+// from the top row) at (px, py), first in raster order on ties: *best (-1 if
+// none) and its packed gradient *bxy.
+template <int R>
+__device__ void grad_best_lds(const LdsView<R> &v, int px, int py, int dy0, int dy1, int *best, int *bxy) {
+    constexpr int P = 2 * R + 1, side = LdsView<R>::side;
+    const int base = v.at(px - R, py - R) + dy0 * side;
+    const int *mg = v.s.mag + base;
+    const int *gp = v.s.gxy + base;
+    int m0[P], m1[P], g0[P], g1[P];
+#pragma unroll
+    for (int dx = 0; dx < P; ++dx) {
+        m0[dx] = mg[dx];
+        g0[dx] = gp[dx];
+    }
+    int b = -1, bg = 0;
+#pragma unroll 1
+    for (int dy = dy0; dy < dy1; ++dy) {
+#pragma unroll
         for (int dx = 0; dx < P; ++dx) {
-            c1[dx] = cf[(dy + 1) * side + dx];
-            m1[dx] = mg[(dy + 1) * side + dx];
-            g1[dx] = gp[(dy + 1) * side + dx];
+            m1[dx] = mg[(dy - dy0 + 1) * side + dx];
+            g1[dx] = gp[(dy - dy0 + 1) * side + dx];
         }
 #pragma unroll
         for (int dx = 0; dx < P; ++dx) {
-            sum = sum + c0[dx];
-            const bool take = m0[dx] > best;   // first in raster order on ties
-            best = take ? m0[dx] : best;
-            bxy = take ? g0[dx] : bxy;
+            const bool take = m0[dx] > b;
+            b = take ? m0[dx] : b;
+            bg = take ? g0[dx] : bg;
         }
 #pragma unroll
         for (int dx = 0; dx < P; ++dx) {
-            c0[dx] = c1[dx];
             m0[dx] = m1[dx];
             g0[dx] = g1[dx];
         }
     }
-    *C = sum / (double)(P * P);
+    *best = b;
+    *bxy = bg;
+}
+
+// D of Eq. 2 from the chosen packed gradient and the normal at (px, py),
+// as priority_terms computes it.
+template <int R>
+__device__ double data_term_lds(const LdsView<R> &v, int px, int py, int bxy, double norm1, double norm2) {
     const int gx = (int)(int16_t)(bxy & 0xffff), gy = bxy >> 16;
     const int nx = v.hole_or_out(px + 1, py) - v.hole_or_out(px - 1, py);
     const int ny = v.hole_or_out(px, py + 1) - v.hole_or_out(px, py - 1);
     const int kn = nx * nx + ny * ny;
-    if (kn == 0) {
-        *D = 0.0;
-    } else {
-        int a = gx * ny - gy * nx;
-        if (a < 0) a = -a;
-        *D = (0.5 * (double)a) / (kn == 1 ? norm1 : norm2);
-    }
+    if (kn == 0) return 0.0;
+    int a = gx * ny - gy * nx;
+    if (a < 0) a = -a;
+    return (0.5 * (double)a) / (kn == 1 ? norm1 : norm2);
 }
 
 // (C, D) of a pixel: C = -1 marks "not on the front".
@@ -670,17 +687,42 @@ __device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, 
     }
     __syncthreads();
     const int nfront = L.nfront;
-    for (int f = threadIdx.x; f < nfront; f += blockDim.x) {
-        const int wi = L.front[f];
-        const int x = px - 2 * R - 1 + wi % WIN, y = py - 2 * R - 1 + wi / WIN;
-        double2 cd;
-        priority_terms_lds<R>(v, x, y, d.norm1, d.norm2, &cd.x, &cd.y);
-        d.pcd[(int64_t)y * d.W + x] = cd;
-        L.wcd[wi] = cd;
-        const int b = (y / kBlock - g.aby0) * g.nabx + (x / kBlock - g.abx0);
-        L.bkey[b * 64 + (y & 7) * 8 + (x & 7)] = key_of(cd);
+    // Rounds of 64 front pixels.  The confidence sum (a serial FP64 chain)
+    // runs in wave 0 and the gradient search in waves 2 (top rows) and 3
+    // (bottom rows), one front pixel per lane, so each lane reads about a
+    // third of a patch's LDS words.  The bottom half's best wins only when
+    // strictly larger, which keeps the first-in-raster-order tie rule.
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int f0 = 0; f0 < nfront; f0 += 64) {
+        const int f = f0 + lane;
+        if (f < nfront && wave != 1) {
+            const int wi = L.front[f];
+            const int x = px - 2 * R - 1 + wi % WIN, y = py - 2 * R - 1 + wi / WIN;
+            if (wave == 0) {
+                L.fsum[lane] = conf_sum_lds<R>(v, x, y);
+            } else {
+                const int h = wave - 2;
+                int b, bg;
+                grad_best_lds<R>(v, x, y, h ? R + 1 : 0, h ? 2 * R + 1 : R + 1, &b, &bg);
+                L.fbest[h][lane] = b;
+                L.fbxy[h][lane] = bg;
+            }
+        }
+        __syncthreads();
+        if (f < nfront && wave == 0) {
+            const int wi = L.front[f];
+            const int x = px - 2 * R - 1 + wi % WIN, y = py - 2 * R - 1 + wi / WIN;
+            const int bxy = L.fbest[1][lane] > L.fbest[0][lane] ? L.fbxy[1][lane] : L.fbxy[0][lane];
+            double2 cd;
+            cd.x = L.fsum[lane] / (double)((2 * R + 1) * (2 * R + 1));
+            cd.y = data_term_lds<R>(v, x, y, bxy, d.norm1, d.norm2);
+            d.pcd[(int64_t)y * d.W + x] = cd;
+            L.wcd[wi] = cd;
+            const int b = (y / kBlock - g.aby0) * g.nabx + (x / kBlock - g.abx0);
+            L.bkey[b * 64 + (y & 7) * 8 + (x & 7)] = key_of(cd);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     // Block maxima: 16 threads per touched block, 4 keys each, then a
     // 16-lane reduction ((key, index) pairs are totally ordered, so any
     // reduction order gives the same maximum); the block's first thread
@@ -1032,6 +1074,32 @@ __device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, Ld
     return best;
 }
 
+// A copy of one target patch in LDS (slot order as stage_target), with its
+// centre's raster index (-1: none).
+template <int R>
+struct PatchCopy {
+    uint32_t pix[(2 * R + 1) * (2 * R + 1)];
+    uint8_t known[(2 * R + 1) * (2 * R + 1)];
+    int64_t idx;
+};
+
+// Copies the patch at raster index idx (< 0: none) into *c (whole group; the
+// caller's next barrier publishes it).
+template <int R>
+__device__ void copy_patch(const JobDev &d, int64_t idx, PatchCopy<R> *c) {
+    constexpr int P = 2 * R + 1;
+    if (threadIdx.x == 0) c->idx = idx;
+    if (idx < 0) return;
+    const int tx = (int)(idx % d.W), ty = (int)(idx / d.W);
+    const GlobalView v{d};
+    for (int t = threadIdx.x; t < P * P; t += blockDim.x) {
+        const int x = tx + t / P - R, y = ty + t % P - R;
+        const bool kn = v.known(x, y);
+        c->known[t] = kn ? 1 : 0;
+        c->pix[t] = kn ? d.img[(int64_t)y * d.W + x] & 0x00ffffffu : 0u;
+    }
+}
+
 // What the stream-form commit reports about its copy: the target and the
 // number of pixels filled (nf counts them under INTERSECT scoring).
 struct CommitNote {
@@ -1118,7 +1186,7 @@ __device__ void add_filled_sources(const JobDev &d, const LdsStage<R> &L, int px
 template <int R, bool ISECT = false>
 __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const Snap &v, uint64_t best,
                               const Refresh &g, int64_t key0, int64_t idx0, Snap *out, FillSync *recs = nullptr,
-                              CommitNote *note = nullptr) {
+                              CommitNote *note = nullptr, const PatchCopy<R> *far = nullptr) {
     IterState *st = d.st;
     constexpr int P = 2 * R + 1;
     const int W = d.W;
@@ -1241,10 +1309,19 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
     const int tx = (int)(idx % W), ty = (int)(idx / W);
     const int adx = abs(tx - px), ady = abs(ty - py);
     int kk;
-    if (adx <= 2 * R + 2 && ady <= 2 * R + 2)
+    if (adx <= 2 * R + 2 && ady <= 2 * R + 2) {
         kk = stage_target_lds<R>(L, px, py, tx, ty, d.tgt, s, d.mfma ? d.frag : nullptr, recs);
-    else
+    } else if (far && far->idx == idx) {
+        // the best pixel of the untouched blocks, copied before this
+        // iteration's search ended: its patch is at least 2r + 2 pixels from
+        // the filled one, so the copy did not change it
+        kk = stage_slots(R, tx, ty, d.tgt, s, d.mfma ? d.frag : nullptr, recs, [&](int t, uint32_t *pix) {
+            *pix = far->pix[t];
+            return far->known[t] != 0;
+        });
+    } else {
         kk = stage_target(d, tx, ty, R, d.tgt, s, d.mfma ? d.frag : nullptr, recs);
+    }
     if (threadIdx.x == 0) {
         double2 cd;
         if (adx <= 2 * R + 1 && ady <= 2 * R + 1)
@@ -1371,6 +1448,7 @@ template <int R>
 struct CommitLds {
     Scratch s;
     LdsStage<R> L;
+    PatchCopy<R> far;   // the untouched blocks' best pixel: the usual far next target
 };
 
 template <int R, int NY>
@@ -1430,6 +1508,9 @@ __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t 
         __syncthreads();
         grad_pass<R>(L, 1, Stage<R>::side - 1);
         block_argmax(key, idx, s.k, s.i);
+        // the untouched blocks' best pixel wins whenever the next target is
+        // far: copy its patch while the search still runs
+        copy_patch<R>(d, key >= 0 ? idx : -1, &C.far);
 
         // (its barriers also publish the gathered LDS neighbourhood)
         int ok = 0;
@@ -1439,7 +1520,7 @@ __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t 
             v.err = INPAINT_DEVICE;
             continue;      // publishes stop
         }
-        commit_finish<R>(d, s, L, v, best, g, key, idx, &s.snap, sy);
+        commit_finish<R>(d, s, L, v, best, g, key, idx, &s.snap, sy, nullptr, &C.far);
         __syncthreads();
         v = s.snap;
         staged = true;
