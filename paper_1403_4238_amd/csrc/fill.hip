@@ -79,7 +79,7 @@ struct LdsStage {
     int16_t front[WIN * WIN];       // window pixels on the front (window-local index)
     int nfront;
     double fsum[64];                // per front pixel of a round: confidence sum
-    int fbest[2][64], fbxy[2][64];  // and the best gradient of the top / bottom rows
+    int fbest[4][64], fbxy[4][64];  // and the best gradient of parts of the patch rows
 };
 
 template <int R>
@@ -260,77 +260,76 @@ __device__ __forceinline__ bool better(int64_t ka, int64_t ia, int64_t kb, int64
     return ka > kb || (ka == kb && ia < ib);
 }
 
+// (key, index) pairs, the greater key winning and equal keys going to the
+// lower index: a strict total order, so every fold order gives the same pair.
+// For the DPP folds a pair is encoded as (key + 1, INT64_MAX - index), which
+// maps the identity (-1, INT64_MAX) to (0, 0) and the order to the
+// lexicographic order of the two unsigned words (keys are -1 or the bits of
+// a non-negative double, indices non-negative).
+struct KeyIdx {
+    uint64_t k, i;
+};
+__device__ __forceinline__ KeyIdx key_idx_max(KeyIdx a, KeyIdx b) {
+    return (b.k > a.k || (b.k == a.k && b.i > a.i)) ? b : a;
+}
+template <int CTRL>
+__device__ __forceinline__ KeyIdx key_idx_mov(KeyIdx v) {
+    return {dpp::mov<CTRL>(v.k), dpp::mov<CTRL>(v.i)};
+}
+__device__ __forceinline__ KeyIdx key_idx_enc(int64_t key, int64_t idx) {
+    return {(uint64_t)(key + 1), (uint64_t)(INT64_MAX - idx)};
+}
+__device__ __forceinline__ void key_idx_dec(KeyIdx v, int64_t &key, int64_t &idx) {
+    key = (int64_t)v.k - 1;
+    idx = INT64_MAX - (int64_t)v.i;
+}
+__device__ __forceinline__ KeyIdx row_argmax_enc(KeyIdx v) {
+    v = key_idx_max(v, key_idx_mov<dpp::kShr1>(v));
+    v = key_idx_max(v, key_idx_mov<dpp::kShr2>(v));
+    v = key_idx_max(v, key_idx_mov<dpp::kShr4>(v));
+    v = key_idx_max(v, key_idx_mov<dpp::kShr8>(v));
+    return v;
+}
+// Lane 15 of each 16-lane row ends with the row's maximum.
+__device__ __forceinline__ void row_argmax(int64_t &key, int64_t &idx) {
+    key_idx_dec(row_argmax_enc(key_idx_enc(key, idx)), key, idx);
+}
+// The wave's maximum, in every lane (all lanes active).
+__device__ __forceinline__ void wave_argmax(int64_t &key, int64_t &idx) {
+    KeyIdx v = row_argmax_enc(key_idx_enc(key, idx));
+    v = key_idx_max(v, key_idx_mov<dpp::kBcast15>(v));
+    v = key_idx_max(v, key_idx_mov<dpp::kBcast31>(v));
+    key_idx_dec({dpp::lane63(v.k), dpp::lane63(v.i)}, key, idx);
+}
+
+// Work-group folds: each wave folds on DPP, lane 0 posts the wave's result,
+// then every thread folds the posted results itself (no second wave pass).
+// The closing barrier lets the caller reuse the scratch words.
 __device__ void block_argmax(int64_t &key, int64_t &idx, int64_t *sk, int64_t *si) {
-    for (int off = 32; off > 0; off >>= 1) {
-        const int64_t k2 = __shfl_xor(key, off);
-        const int64_t i2 = __shfl_xor(idx, off);
-        if (better(k2, i2, key, idx)) {
-            key = k2;
-            idx = i2;
-        }
-    }
+    wave_argmax(key, idx);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (lane == 0) {
         sk[w] = key;
         si[w] = idx;
     }
     __syncthreads();
-    if (w == 0) {
-        key = lane < nw ? sk[lane] : -1;
-        idx = lane < nw ? si[lane] : INT64_MAX;
-        for (int off = 32; off > 0; off >>= 1) {
-            const int64_t k2 = __shfl_xor(key, off);
-            const int64_t i2 = __shfl_xor(idx, off);
-            if (better(k2, i2, key, idx)) {
-                key = k2;
-                idx = i2;
-            }
-        }
-        if (lane == 0) {
-            sk[0] = key;
-            si[0] = idx;
-        }
-    }
-    __syncthreads();
     key = sk[0];
     idx = si[0];
+    for (int q = 1; q < nw; ++q)
+        if (better(sk[q], si[q], key, idx)) {
+            key = sk[q];
+            idx = si[q];
+        }
     __syncthreads();
 }
 
 __device__ uint64_t block_min_u64(uint64_t v, uint64_t *sh) {
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t o = __shfl_xor(v, off);
-        v = o < v ? o : v;
-    }
+    v = dpp::min_u64(v);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     if (lane == 0) sh[w] = v;
     __syncthreads();
-    if (w == 0) {
-        v = lane < nw ? sh[lane] : ~0ull;
-        for (int off = 32; off > 0; off >>= 1) {
-            const uint64_t o = __shfl_xor(v, off);
-            v = o < v ? o : v;
-        }
-        if (lane == 0) sh[0] = v;
-    }
-    __syncthreads();
     v = sh[0];
-    __syncthreads();
-    return v;
-}
-
-__device__ int64_t block_sum_i64(int64_t v, int64_t *sh) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (lane == 0) sh[w] = v;
-    __syncthreads();
-    if (w == 0) {
-        v = lane < nw ? sh[lane] : 0;
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) sh[0] = v;
-    }
-    __syncthreads();
-    v = sh[0];
+    for (int q = 1; q < nw; ++q) v = sh[q] < v ? sh[q] : v;
     __syncthreads();
     return v;
 }
@@ -418,11 +417,9 @@ __device__ void build_mfma_frags(int r, Scratch &s, MfmaFrags *f) {
                 kk += 1;
                 rows |= 1u << (sl % P);
             }
-        for (int off = 32; off > 0; off >>= 1) {
-            t2 += __shfl_xor(t2, off);
-            kk += __shfl_xor(kk, off);
-            rows |= __shfl_xor(rows, off);
-        }
+        t2 = (int)dpp::sum_u32((uint32_t)t2);   // exact: 32-bit wrap-around sums
+        kk = (int)dpp::sum_u32((uint32_t)kk);
+        rows = dpp::or_u32(rows);
         if (threadIdx.x == 0) {
             f->t2p = t2;
             f->k = kk;
@@ -468,17 +465,6 @@ __device__ void write_records(FillSync *sy, const TargetStage *tg, int P) {
     if (threadIdx.x < kGoCopies) {
         sy->rec[threadIdx.x].t2 = tg->t2;
         sy->rec[threadIdx.x].k = (uint32_t)tg->k;
-    }
-}
-
-__device__ __forceinline__ void wave_argmax(int64_t &key, int64_t &idx) {
-    for (int off = 32; off > 0; off >>= 1) {
-        const int64_t k2 = __shfl_xor(key, off);
-        const int64_t i2 = __shfl_xor(idx, off);
-        if (better(k2, i2, key, idx)) {
-            key = k2;
-            idx = i2;
-        }
     }
 }
 
@@ -532,7 +518,7 @@ __device__ int stage_slots(int r, int tx, int ty, TargetStage *tg, Scratch &s, M
             if (w0 + 1 < 16) s.mbits[w0 + 1] = (uint32_t)(bal >> 32);
         }
     }
-    for (int off = 32; off > 0; off >>= 1) t2 += __shfl_xor(t2, off);
+    t2 = dpp::sum_u32(t2);
     if (lane == 0) s.u[wave] = t2;
     __syncthreads();
     const int mw = (n + 31) / 32, nw = blockDim.x >> 6;
@@ -662,22 +648,50 @@ __device__ void grad_pass(LdsStage<R> &L, int lo, int hi) {
 // each front pixel's (C, D).  New terms go to global memory (for later
 // iterations) and to LDS; then one wave per touched block recomputes its
 // maximum, writes it, and folds it into the thread's running argmax.
+// Block maxima of the refreshed window: 16 threads per touched block, 4 keys
+// each, then a 16-lane reduction ((key, index) pairs are totally ordered, so
+// any reduction order gives the same maximum); the block's first thread
+// writes it to global memory and to s.bmk / s.bmi.
 template <int R>
-__device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, LdsStage<R> &L, Scratch &s) {
+__device__ void block_maxima(const JobDev &d, const Refresh &g, LdsStage<R> &L, Scratch &s) {
+    const int sub = threadIdx.x & 15, nb = g.nabx * g.naby;
+    for (int b0 = 0; b0 < nb; b0 += blockDim.x >> 4) {
+        const int b = b0 + (threadIdx.x >> 4);
+        const int bx = g.abx0 + b % g.nabx, by = g.aby0 + b / g.nabx;
+        int64_t bk = -1, bi = INT64_MAX;
+        if (b < nb) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int e = sub + 16 * j;
+                const int x = bx * kBlock + (e & 7), y = by * kBlock + (e >> 3);
+                const int64_t k = in_img(d, x, y) ? L.bkey[b * 64 + e] : -1;
+                const int64_t i = in_img(d, x, y) ? (int64_t)y * d.W + x : INT64_MAX;
+                if (better(k, i, bk, bi)) {
+                    bk = k;
+                    bi = i;
+                }
+            }
+        }
+        row_argmax(bk, bi);   // the block's 16 threads are one DPP row
+        if (b < nb && sub == 15) {
+            d.blk[by * d.nbw + bx].key = bk;
+            d.blk[by * d.nbw + bx].idx = bi;
+            s.bmk[b] = bk;
+            s.bmi[b] = bi;
+        }
+    }
+}
+
+// Front pixels of the refresh window go to a compact list so the costly
+// evaluations fill whole waves (L.nfront must be 0 before; the caller's
+// barrier publishes the list).  Pixels off the front already carry (C, D) =
+// (-1, 0) in global memory and key -1 in LDS: a hole pixel off the front has
+// never been on it (the front only gains hole pixels), a known one was set
+// when it was filled (the copy) or at initialisation.
+template <int R>
+__device__ void list_front(int px, int py, const Refresh &g, LdsStage<R> &L) {
     using S = Stage<R>;
-    const int ox = px - S::half, oy = py - S::half;
-    const LdsView<R> v{L, ox, oy};
-    if (threadIdx.x == 0) L.nfront = 0;
-    // The copy changed gradients only within one pixel of the patch; the
-    // rest of the square was evaluated before it (grad_pass on the whole).
-    __syncthreads();   // the copied pixels
-    grad_pass<R>(L, S::half - R - 1, S::half + R + 2);
-    __syncthreads();
-    // Front pixels of the window go to a compact list so the costly
-    // evaluations fill whole waves.  Pixels off the front already carry
-    // (C, D) = (-1, 0) in global memory and key -1 in LDS: a hole pixel off
-    // the front has never been on it (the front only gains hole pixels), a
-    // known one was set when it was filled (the copy) or at initialisation.
+    const LdsView<R> v{L, px - S::half, py - S::half};
     const int ww = g.wx1 - g.wx0, nwin = ww * (g.wy1 - g.wy0);
     constexpr int WIN = LdsStage<R>::WIN;
     for (int t = threadIdx.x; t < nwin; t += blockDim.x) {
@@ -685,7 +699,122 @@ __device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, 
         const int wi = (y - (py - 2 * R - 1)) * WIN + (x - (px - 2 * R - 1));
         if (on_front(v, x, y)) L.front[atomicAdd(&L.nfront, 1)] = (int16_t)wi;
     }
+}
+
+// The search-independent half of a commit, run by the persistent committer
+// while the search is still going: which pixels the copy fills (the hole
+// pixels of the target patch) and the confidence they take (C of the
+// target) do not depend on the source patch chosen.  So it marks them filled
+// (hole map, confidence, off the front), lists the new front of the refresh
+// window, and computes each front pixel's confidence term into L.wcd[wi].x.
+// The raster-order FP64 sums are the same ones the full refresh computes.
+// Only the copied colours, the gradients near the patch and the data terms
+// wait for the search.  fb gets the patch slots to copy (bit t: dx = t % P
+// - r, dy = t / P - r).  Only for the original source region with whole-patch
+// scoring: there the candidate set never changes and context creation
+// rejects an empty one, so the search always returns a source patch.
+template <int R>
+__device__ void precommit(const JobDev &d, const Snap &v, const Refresh &g, LdsStage<R> &L, uint32_t *fb) {
+    using S = Stage<R>;
+    constexpr int P = 2 * R + 1;
+    const int W = d.W;
+    const int px = (int)(v.p % W), py = (int)(v.p / W);
+    if (threadIdx.x < kMaskWords) fb[threadIdx.x] = 0;
+    if (threadIdx.x == 0) L.nfront = 0;
     __syncthreads();
+    for (int t = threadIdx.x; t < P * P; t += blockDim.x) {
+        const int dx = t % P - R, dy = t / P - R;
+        const int li = (dy + S::half) * S::side + (dx + S::half);
+        if (L.st[li] == 1) {
+            atomicOr(&fb[t >> 5], 1u << (t & 31));
+            const int x = px + dx, y = py + dy;
+            const int64_t dst = (int64_t)y * W + x;
+            d.conf[dst] = v.C;
+            d.hole[dst] = 0;
+            d.pcd[dst] = make_double2(-1.0, 0.0);
+            L.st[li] = 0;
+            L.conf[li] = v.C;
+            L.bkey[((y / kBlock - g.aby0) * g.nabx + (x / kBlock - g.abx0)) * 64 + (y & 7) * 8 + (x & 7)] = -1;
+        }
+    }
+    __syncthreads();
+    list_front<R>(px, py, g, L);
+    __syncthreads();
+    const LdsView<R> lv{L, px - S::half, py - S::half};
+    constexpr int WIN = LdsStage<R>::WIN;
+    const int nfront = L.nfront;
+    for (int f = threadIdx.x; f < nfront; f += blockDim.x) {
+        const int wi = L.front[f];
+        const int x = px - 2 * R - 1 + wi % WIN, y = py - 2 * R - 1 + wi / WIN;
+        L.wcd[wi].x = conf_sum_lds<R>(lv, x, y) / (double)(P * P);
+    }
+}
+
+// Data terms of the listed front pixels (their C already in L.wcd[wi].x),
+// in rounds of 64: wave w searches the gradient maxima of the w-th quarter
+// of the patch rows; the quarters combine in row order, a later one winning
+// only when strictly larger (the first-in-raster-order tie rule).
+template <int R>
+__device__ void refresh_data_terms(const JobDev &d, int px, int py, const Refresh &g, LdsStage<R> &L) {
+    using S = Stage<R>;
+    constexpr int P = 2 * R + 1, WIN = LdsStage<R>::WIN;
+    const LdsView<R> v{L, px - S::half, py - S::half};
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nfront = L.nfront;
+    for (int f0 = 0; f0 < nfront; f0 += 64) {
+        const int f = f0 + lane;
+        if (f < nfront) {
+            const int wi = L.front[f];
+            const int x = px - 2 * R - 1 + wi % WIN, y = py - 2 * R - 1 + wi / WIN;
+            int b, bg;
+            grad_best_lds<R>(v, x, y, wave * P / 4, (wave + 1) * P / 4, &b, &bg);
+            L.fbest[wave][lane] = b;
+            L.fbxy[wave][lane] = bg;
+        }
+        __syncthreads();
+        if (f < nfront && wave == 0) {
+            const int wi = L.front[f];
+            const int x = px - 2 * R - 1 + wi % WIN, y = py - 2 * R - 1 + wi / WIN;
+            int best = L.fbest[0][lane], bxy = L.fbxy[0][lane];
+#pragma unroll
+            for (int q = 1; q < 4; ++q)
+                if (L.fbest[q][lane] > best) {
+                    best = L.fbest[q][lane];
+                    bxy = L.fbxy[q][lane];
+                }
+            double2 cd;
+            cd.x = L.wcd[wi].x;
+            cd.y = data_term_lds<R>(v, x, y, bxy, d.norm1, d.norm2);
+            d.pcd[(int64_t)y * d.W + x] = cd;
+            L.wcd[wi] = cd;
+            const int b = (y / kBlock - g.aby0) * g.nabx + (x / kBlock - g.abx0);
+            L.bkey[b * 64 + (y & 7) * 8 + (x & 7)] = key_of(cd);
+        }
+        __syncthreads();
+    }
+}
+
+template <int R, bool PRE = false>
+__device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, LdsStage<R> &L, Scratch &s) {
+    using S = Stage<R>;
+    const int ox = px - S::half, oy = py - S::half;
+    const LdsView<R> v{L, ox, oy};
+    if (!PRE && threadIdx.x == 0) L.nfront = 0;
+    // The copy changed gradients only within one pixel of the patch; the
+    // rest of the square was evaluated before it (grad_pass on the whole).
+    __syncthreads();   // the copied pixels
+    grad_pass<R>(L, S::half - R - 1, S::half + R + 2);
+    __syncthreads();
+    if (PRE) {
+        // precommit listed the front and put each front pixel's C in
+        // L.wcd[wi].x; only D needs the copied gray values.
+        refresh_data_terms<R>(d, px, py, g, L);
+        block_maxima<R>(d, g, L, s);
+        return;
+    }
+    list_front<R>(px, py, g, L);
+    __syncthreads();
+    constexpr int WIN = LdsStage<R>::WIN;
     const int nfront = L.nfront;
     // Rounds of 64 front pixels.  The confidence sum (a serial FP64 chain)
     // runs in wave 0 and the gradient search in waves 2 (top rows) and 3
@@ -723,43 +852,7 @@ __device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, 
         }
         __syncthreads();
     }
-    // Block maxima: 16 threads per touched block, 4 keys each, then a
-    // 16-lane reduction ((key, index) pairs are totally ordered, so any
-    // reduction order gives the same maximum); the block's first thread
-    // writes it to global memory and to s.bmk / s.bmi.
-    const int sub = threadIdx.x & 15, nb = g.nabx * g.naby;
-    for (int b0 = 0; b0 < nb; b0 += blockDim.x >> 4) {
-        const int b = b0 + (threadIdx.x >> 4);
-        const int bx = g.abx0 + b % g.nabx, by = g.aby0 + b / g.nabx;
-        int64_t bk = -1, bi = INT64_MAX;
-        if (b < nb) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int e = sub + 16 * j;
-                const int x = bx * kBlock + (e & 7), y = by * kBlock + (e >> 3);
-                const int64_t k = in_img(d, x, y) ? L.bkey[b * 64 + e] : -1;
-                const int64_t i = in_img(d, x, y) ? (int64_t)y * d.W + x : INT64_MAX;
-                if (better(k, i, bk, bi)) {
-                    bk = k;
-                    bi = i;
-                }
-            }
-        }
-        for (int off = 8; off > 0; off >>= 1) {
-            const int64_t k2 = __shfl_xor(bk, off);
-            const int64_t i2 = __shfl_xor(bi, off);
-            if (better(k2, i2, bk, bi)) {
-                bk = k2;
-                bi = i2;
-            }
-        }
-        if (b < nb && sub == 0) {
-            d.blk[by * d.nbw + bx].key = bk;
-            d.blk[by * d.nbw + bx].idx = bi;
-            s.bmk[b] = bk;
-            s.bmi[b] = bi;
-        }
-    }
+    block_maxima<R>(d, g, L, s);
 }
 
 // Stages the next target (nx, ny) from the LDS neighbourhood of the filled
@@ -983,7 +1076,7 @@ __global__ __launch_bounds__(256) void k_prio_init(JobDev d) {
 // trip.  Leaves the neighbourhood and the block keys in LDS, the running
 // argmax over the untouched blocks in (key, idx), and returns the minimum
 // search key of this thread's partials.
-template <int R, bool PARTIALS>
+template <int R, bool PARTIALS, int TB = 8>
 __device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, LdsStage<R> &L, int64_t &key,
                            int64_t &idx) {
     using S = Stage<R>;
@@ -1067,10 +1160,28 @@ __device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, Ld
 #pragma unroll
     for (int k = 0; k < PIT; ++k) best = pv[k] < best ? pv[k] : best;   // clamped repeats are harmless
 
-    // ---- tails of very large holes / rectangles
-    for (int t = tid + BIT * T; t < nb; t += T) take_block(t, d.blk[(d.pby0 + t / bw) * d.nbw + d.pbx0 + t % bw]);
-    if (PARTIALS)
-        for (int t = tid + PIT * T; t < ntiles; t += T) best = d.partials[t] < best ? d.partials[t] : best;
+    // ---- tails of large holes / rectangles, TB loads in flight per round
+    // trip (the arrays above are dead by now, so their registers are free);
+    // the argmax is order-independent (a strict total order)
+    for (int t0 = tid + BIT * T; t0 < nb; t0 += TB * T) {
+        BlockBest tb[TB];
+#pragma unroll
+        for (int q = 0; q < TB; ++q) {
+            const int t = min(t0 + q * T, nb - 1);
+            tb[q] = d.blk[(d.pby0 + t / bw) * d.nbw + d.pbx0 + t % bw];
+        }
+#pragma unroll
+        for (int q = 0; q < TB; ++q) take_block(t0 + q * T, tb[q]);   // t >= nb is skipped there
+    }
+    if (PARTIALS) {
+        for (int t0 = tid + PIT * T; t0 < ntiles; t0 += TB * T) {
+            uint64_t tp[TB];
+#pragma unroll
+            for (int q = 0; q < TB; ++q) tp[q] = d.partials[min(t0 + q * T, ntiles - 1)];
+#pragma unroll
+            for (int q = 0; q < TB; ++q) best = tp[q] < best ? tp[q] : best;   // clamped repeats are harmless
+        }
+    }
     return best;
 }
 
@@ -1183,10 +1294,15 @@ __device__ void add_filled_sources(const JobDev &d, const LdsStage<R> &L, int px
 // LDS when its patch lies inside the staged neighbourhood (the common case:
 // the front moves locally).  (key0, idx0) is the argmax over the blocks the
 // refresh does not touch (block-uniform).
-template <int R, bool ISECT = false>
+//
+// PRE: precommit() already marked the patch's hole pixels filled (fb lists
+// them), listed the new front and computed its confidence terms; only the
+// colours are copied here.
+template <int R, bool ISECT = false, bool PRE = false>
 __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const Snap &v, uint64_t best,
                               const Refresh &g, int64_t key0, int64_t idx0, Snap *out, FillSync *recs = nullptr,
-                              CommitNote *note = nullptr, const PatchCopy<R> *far = nullptr) {
+                              CommitNote *note = nullptr, const PatchCopy<R> *far = nullptr,
+                              const uint32_t *fb = nullptr) {
     IterState *st = d.st;
     constexpr int P = 2 * R + 1;
     const int W = d.W;
@@ -1216,7 +1332,17 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
     for (int t = threadIdx.x; t < P * P; t += blockDim.x) {
         const int dx = t % P - R, dy = t / P - R;
         const int li = (dy + Stage<R>::half) * Stage<R>::side + (dx + Stage<R>::half);
-        if (L.st[li] == 1) {
+        if (PRE) {
+            if ((fb[t >> 5] >> (t & 31)) & 1) {
+                const int64_t dst = (int64_t)(py + dy) * W + (px + dx), src = (int64_t)(qy + dy) * W + (qx + dx);
+                const uint32_t pix = d.img[src];
+                const uint8_t gv = d.gray[src];
+                d.img[dst] = pix;
+                d.gray[dst] = gv;
+                L.img[li] = pix;
+                L.gray[li] = gv;
+            }
+        } else if (L.st[li] == 1) {
             if (ISECT) {
                 // the flag byte of the source word, read before any of this
                 // copy's writes (the padded plane covers R pixels around the image)
@@ -1280,7 +1406,7 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
 
     // ---- priorities near the patch, block maxima, argmax: wave 0 reduces
     // the touched blocks' maxima and (key0, idx0)
-    refresh_near<R>(d, px, py, g, L, s);
+    refresh_near<R, PRE>(d, px, py, g, L, s);
     __syncthreads();
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x, nb = g.nabx * g.naby;
@@ -1449,6 +1575,7 @@ struct CommitLds {
     Scratch s;
     LdsStage<R> L;
     PatchCopy<R> far;   // the untouched blocks' best pixel: the usual far next target
+    uint32_t fill[kMaskWords];   // the target patch's hole pixels (precommit)
 };
 
 template <int R, int NY>
@@ -1465,7 +1592,8 @@ union FillLds {
     SearchLds<R, NY> s;
 };
 
-template <int R>
+// TB: tail loads in flight in gather() (fewer under a tighter register budget).
+template <int R, int TB>
 __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t epoch, CommitLds<R> &C) {
     Scratch &s = C.s;
     LdsStage<R> &L = C.L;
@@ -1504,13 +1632,14 @@ __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t 
         const int px = (int)(v.p % d.W), py = (int)(v.p / d.W);
         const Refresh g = refresh_geometry<R>(d, px, py);
         int64_t key = -1, idx = INT64_MAX;
-        gather<R, false>(d, px, py, g, L, key, idx);
+        gather<R, false, TB>(d, px, py, g, L, key, idx);
         __syncthreads();
         grad_pass<R>(L, 1, Stage<R>::side - 1);
         block_argmax(key, idx, s.k, s.i);
         // the untouched blocks' best pixel wins whenever the next target is
         // far: copy its patch while the search still runs
         copy_patch<R>(d, key >= 0 ? idx : -1, &C.far);
+        precommit<R>(d, v, g, L, C.fill);
 
         // (its barriers also publish the gathered LDS neighbourhood)
         int ok = 0;
@@ -1520,7 +1649,7 @@ __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t 
             v.err = INPAINT_DEVICE;
             continue;      // publishes stop
         }
-        commit_finish<R>(d, s, L, v, best, g, key, idx, &s.snap, sy, nullptr, &C.far);
+        commit_finish<R, false, true>(d, s, L, v, best, g, key, idx, &s.snap, sy, nullptr, &C.far, C.fill);
         __syncthreads();
         v = s.snap;
         staged = true;
@@ -1642,7 +1771,7 @@ template <int R>
 __global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_fill_mfma(JobDev d, int ntiles, int n_iters, uint32_t epoch) {
     __shared__ FillLdsMfma<R> lds;
     if (blockIdx.x == 0)
-        fill_commit<R>(d, ntiles, n_iters, epoch, lds.c);
+        fill_commit<R, 8>(d, ntiles, n_iters, epoch, lds.c);
     else
         fill_search_mfma<R>(d, epoch, lds.s);
 }
@@ -1651,7 +1780,7 @@ template <int R>
 __global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fill(JobDev d, int ntiles, int n_iters, uint32_t epoch) {
     __shared__ FillLds<R, kFillTileRows> lds;
     if (blockIdx.x == 0)
-        fill_commit<R>(d, ntiles, n_iters, epoch, lds.c);
+        fill_commit<R, 2>(d, ntiles, n_iters, epoch, lds.c);
     else
         fill_search<R, kFillTileRows>(d, ntiles, epoch, lds.s);
 }

@@ -110,11 +110,9 @@ __device__ __forceinline__ void build_patch(FragTables<R> *ft, Word word, Known 
             rows |= 1u << dy;
         }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        t2 += __shfl_xor(t2, off);
-        kk += __shfl_xor(kk, off);
-        rows |= __shfl_xor(rows, off);
-    }
+    t2 = (int)dpp::sum_u32((uint32_t)t2);   // exact: 32-bit wrap-around sums
+    kk = (int)dpp::sum_u32((uint32_t)kk);
+    rows = dpp::or_u32(rows);
     if ((threadIdx.x & 63) == 0) {
         ft->t2p[threadIdx.x >> 6] = t2;
         ft->k[threadIdx.x >> 6] = kk;

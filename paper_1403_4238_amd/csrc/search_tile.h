@@ -34,6 +34,58 @@
 #include "inpaint_dev.h"
 
 namespace inpaint {
+
+// ---- wave-wide folds on DPP lane moves (VALU only: no LDS round trip per
+// step as with shuffles).  Rows of 16 lanes fold by row_shr 1, 2, 4 and 8,
+// which leaves each row's fold in its lane 15; row_bcast 15 then folds row
+// 2 into lane 63 (and row 0 into lane 31), and row_bcast 31 folds lane 31
+// into lane 63, which readlane hands to every lane.  A lane whose source
+// lies outside the wave or before the start of its row reads 0, so every
+// fold here is one with identity 0 (values are re-encoded where needed);
+// no identity registers are tied to the moves.  Lanes other than 63 end with
+// partial folds.  Every lane of the wave must be active.
+namespace dpp {
+constexpr int kShr1 = 0x111, kShr2 = 0x112, kShr4 = 0x114, kShr8 = 0x118, kBcast15 = 0x142, kBcast31 = 0x143;
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t mov(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t mov(uint64_t v) {
+    return (uint64_t)mov<CTRL>((uint32_t)v) | (uint64_t)mov<CTRL>((uint32_t)(v >> 32)) << 32;
+}
+__device__ __forceinline__ uint32_t lane63(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 63); }
+__device__ __forceinline__ uint64_t lane63(uint64_t v) { return (uint64_t)lane63((uint32_t)v) | (uint64_t)lane63((uint32_t)(v >> 32)) << 32; }
+
+// Row folds: lane 15 of each 16-lane row ends with its row's fold.
+template <class T, class Op>
+__device__ __forceinline__ T fold_rows(T v, Op op) {
+    v = op(v, mov<kShr1>(v));
+    v = op(v, mov<kShr2>(v));
+    v = op(v, mov<kShr4>(v));
+    v = op(v, mov<kShr8>(v));
+    return v;
+}
+// Wave fold, in every lane.
+template <class T, class Op>
+__device__ __forceinline__ T fold_wave(T v, Op op) {
+    v = fold_rows(v, op);
+    v = op(v, mov<kBcast15>(v));
+    v = op(v, mov<kBcast31>(v));
+    return lane63(v);
+}
+__device__ __forceinline__ uint64_t min_u64(uint64_t v) {   // as the maximum of the complements
+    return ~fold_wave(~v, [](uint64_t a, uint64_t b) { return b > a ? b : a; });
+}
+__device__ __forceinline__ uint32_t sum_u32(uint32_t v) {
+    return fold_wave(v, [](uint32_t a, uint32_t b) { return a + b; });
+}
+__device__ __forceinline__ uint32_t or_u32(uint32_t v) {
+    return fold_wave(v, [](uint32_t a, uint32_t b) { return a | b; });
+}
+}  // namespace dpp
+
 namespace tile {
 
 // The target patch is read-only for a whole search and uniform across the
@@ -279,13 +331,7 @@ __device__ __forceinline__ uint64_t score_direct(const JobDev &d, const T &tg, i
 
 // Minimum over the wave.  (Kept out of score_tile: inlined there it makes
 // the register allocator copy the square-term accumulators at every branch.)
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint64_t o = __shfl_xor(v, off);
-        v = o < v ? o : v;
-    }
-    return v;
-}
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) { return dpp::min_u64(v); }
 
 }  // namespace tile
 }  // namespace inpaint
