@@ -487,6 +487,21 @@ __device__ void refresh_block_wave(const JobDev &d, int bx, int by) {
 // Stages the target patch at (tx, ty) with radius r into *tg: known mask,
 // RGBX words and T2 = sum of squared known target values, in column-major
 // slot order (dx + r) * P + (dy + r).
+// Column-run bits of mask word w (of mw) of a P x P patch in column-major
+// slot order: a known slot starts a run when the slot above it in its column
+// is unknown or outside the patch, and ends one when the slot below is.
+__device__ __forceinline__ void run_bits(const uint32_t *mbits, int w, int mw, int P, uint32_t *sb, uint32_t *eb) {
+    const uint32_t m = mbits[w];
+    const uint32_t up = (m << 1) | (w > 0 ? mbits[w - 1] >> 31 : 0u);        // slot - 1 known
+    const uint32_t dn = (m >> 1) | (w + 1 < mw ? mbits[w + 1] << 31 : 0u);   // slot + 1 known
+    uint32_t cs = 0, ce = 0;   // slots at the top / bottom of their column
+    const int base = 32 * w;
+    for (int c = (base + P - 1) / P * P; c < base + 32; c += P) cs |= 1u << (c - base);
+    for (int c = (base + P) / P * P - 1; c < base + 32; c += P) ce |= 1u << (c - base);
+    *sb = m & (cs | ~up);
+    *eb = m & (ce | ~dn);
+}
+
 // Target staging core: slot(t, &pix) says whether patch slot t (column-major,
 // (dx + r) * P + (dy + r)) is known and gives its RGB word.  One pass over
 // the slots writes the words and takes the known mask with a wave ballot per
@@ -528,17 +543,11 @@ __device__ int stage_slots(int r, int tx, int ty, TargetStage *tg, Scratch &s, M
     for (int w = 0; w < mw; ++w) kk += __popc(s.mbits[w]);
     if ((int)threadIdx.x < mw) {
         const int w = threadIdx.x;
-        const uint32_t m = s.mbits[w];
-        const uint32_t up = (m << 1) | (w > 0 ? s.mbits[w - 1] >> 31 : 0u);        // slot - 1 known
-        const uint32_t dn = (m >> 1) | (w + 1 < mw ? s.mbits[w + 1] << 31 : 0u);   // slot + 1 known
-        uint32_t cs = 0, ce = 0;   // slots at the top / bottom of their column
-        const int base = 32 * w;
-        for (int c = (base + P - 1) / P * P; c < base + 32; c += P) cs |= 1u << (c - base);
-        for (int c = (base + P) / P * P - 1; c < base + 32; c += P) ce |= 1u << (c - base);
-        const uint32_t sb = m & (cs | ~up), eb = m & (ce | ~dn);
+        uint32_t sb, eb;
+        run_bits(s.mbits, w, mw, P, &sb, &eb);
         s.sbits[w] = sb;
         s.ebits[w] = eb;
-        tg->mbits[w] = m;
+        tg->mbits[w] = s.mbits[w];
         tg->sbits[w] = sb;
         tg->ebits[w] = eb;
     }
@@ -565,6 +574,75 @@ __device__ int stage_target(const JobDev &d, int tx, int ty, int r, TargetStage 
         *pix = d.img[(int64_t)y * d.W + x] & 0x00ffffffu;
         return true;
     });
+}
+
+// Persistent fill with the MFMA search: stages only what its search groups
+// read -- the words and the known mask -- into the target and every record
+// (the words straight from the slot pass, no barrier in between).  T2 and the
+// column-run bits of the target follow once, for the last target staged in a
+// dispatch (finish_stage).  Returns k.
+template <class F>
+__device__ int stage_slots_lean(int r, int tx, int ty, TargetStage *tg, Scratch &s, FillSync *recs, F slot) {
+    const int P = 2 * r + 1, n = P * P, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int base = 0; base < n; base += blockDim.x) {
+        const int t = base + threadIdx.x;
+        uint32_t pix = 0;
+        const bool kn = t < n && slot(t, &pix);
+        if (t < n) {
+            tg->tpix[t] = pix;
+            s.tp[t] = pix;
+#pragma unroll
+            for (int c = 0; c < kGoCopies; ++c) recs->rec[c].tpix[t] = pix;
+        }
+        const uint64_t bal = __ballot(kn);
+        const int w0 = (base >> 5) + 2 * wave;
+        if (lane == 0 && w0 < 16) {
+            s.mbits[w0] = (uint32_t)bal;
+            if (w0 + 1 < 16) s.mbits[w0 + 1] = (uint32_t)(bal >> 32);
+        }
+    }
+    __syncthreads();
+    const int mw = (n + 31) / 32;
+    int kk = 0;
+    for (int w = 0; w < mw; ++w) kk += __popc(s.mbits[w]);
+    for (int i = threadIdx.x; i < kGoCopies * 16; i += blockDim.x) {   // (copy, word) pairs
+        const int w = i & 15;
+        if (w < mw) recs->rec[i >> 4].mbits[w] = s.mbits[w];
+    }
+    if ((int)threadIdx.x < mw) tg->mbits[threadIdx.x] = s.mbits[threadIdx.x];
+    if (threadIdx.x == 0) {
+        tg->tx = tx;
+        tg->ty = ty;
+        tg->r = r;
+        tg->k = kk;
+    }
+    return kk;
+}
+
+// Completes the target that stage_slots_lean left in s.tp / s.mbits: T2 and
+// the column-run bits.
+__device__ void finish_stage(int r, TargetStage *tg, Scratch &s) {
+    const int P = 2 * r + 1, n = P * P, mw = (n + 31) / 32, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t t2 = 0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x)
+        if ((s.mbits[t >> 5] >> (t & 31)) & 1u) {
+            const uint32_t pix = s.tp[t], R = pix & 255, G = (pix >> 8) & 255, B = (pix >> 16) & 255;
+            t2 += R * R + G * G + B * B;
+        }
+    t2 = dpp::sum_u32(t2);
+    if (lane == 0) s.u[wave] = t2;
+    __syncthreads();
+    if ((int)threadIdx.x < mw) {
+        uint32_t sb, eb;
+        run_bits(s.mbits, threadIdx.x, mw, P, &sb, &eb);
+        tg->sbits[threadIdx.x] = sb;
+        tg->ebits[threadIdx.x] = eb;
+    }
+    if (threadIdx.x == 0) {
+        uint32_t T2 = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) T2 += (uint32_t)s.u[w];
+        tg->t2 = T2;
+    }
 }
 
 // Argmax over the priority blocks, then stages the winner as the next target.
@@ -1076,14 +1154,17 @@ __global__ __launch_bounds__(256) void k_prio_init(JobDev d) {
 // trip.  Leaves the neighbourhood and the block keys in LDS, the running
 // argmax over the untouched blocks in (key, idx), and returns the minimum
 // search key of this thread's partials.
-template <int R, bool PARTIALS, int TB = 8>
+// BW: priority-block loads per thread issued with the first batch (the whole
+// range of a hole up to BW * 256 blocks); TB: loads in flight per round trip
+// for the rest.
+template <int R, bool PARTIALS, int TB = 8, int BW = 4>
 __device__ uint64_t gather(const JobDev &d, int px, int py, const Refresh &g, LdsStage<R> &L, int64_t &key,
                            int64_t &idx) {
     using S = Stage<R>;
     constexpr int T = kCommitThreads;
     constexpr int NIT = (S::n + T - 1) / T;
     constexpr int KIT = (LdsStage<R>::NBA * LdsStage<R>::NBA * 64 + T - 1) / T;
-    constexpr int BIT = PARTIALS ? 16 : 4, PIT = PARTIALS ? 8 : 0;
+    constexpr int BIT = PARTIALS ? 16 : BW, PIT = PARTIALS ? 8 : 0;
     const int ox = px - S::half, oy = py - S::half;
     const int nkeys = g.nabx * g.naby * 64;
     const int bw = d.pbx1 - d.pbx0, nb = bw * (d.pby1 - d.pby0);
@@ -1194,20 +1275,50 @@ struct PatchCopy {
     int64_t idx;
 };
 
-// Copies the patch at raster index idx (< 0: none) into *c (whole group; the
-// caller's next barrier publishes it).
+// The patch at raster index idx in registers: load_patch() issues the loads
+// (hole byte and word together, from clamped addresses) without waiting for
+// them, so they stay in flight across other work; store_patch() then writes
+// the copy to *c (idx < 0: none; whole group, the caller's next barrier
+// publishes it).
 template <int R>
-__device__ void copy_patch(const JobDev &d, int64_t idx, PatchCopy<R> *c) {
+struct PatchLoad {
+    static constexpr int P = 2 * R + 1, N = (P * P + kCommitThreads - 1) / kCommitThreads;
+    uint32_t pix[N];
+    uint8_t hole[N];
+};
+
+template <int R>
+__device__ __forceinline__ PatchLoad<R> load_patch(const JobDev &d, int64_t idx) {
+    constexpr int P = 2 * R + 1;
+    PatchLoad<R> f{};
+    if (idx < 0) return f;
+    const int tx = (int)(idx % d.W), ty = (int)(idx / d.W);
+#pragma unroll
+    for (int j = 0; j < PatchLoad<R>::N; ++j) {
+        const int t = min((int)threadIdx.x + j * kCommitThreads, P * P - 1);
+        const int x = min(max(tx + t / P - R, 0), d.W - 1), y = min(max(ty + t % P - R, 0), d.H - 1);
+        const int64_t i = (int64_t)y * d.W + x;
+        f.hole[j] = d.hole[i];
+        f.pix[j] = d.img[i];
+    }
+    return f;
+}
+
+template <int R>
+__device__ __forceinline__ void store_patch(const JobDev &d, int64_t idx, const PatchLoad<R> &f, PatchCopy<R> *c) {
     constexpr int P = 2 * R + 1;
     if (threadIdx.x == 0) c->idx = idx;
     if (idx < 0) return;
     const int tx = (int)(idx % d.W), ty = (int)(idx / d.W);
-    const GlobalView v{d};
-    for (int t = threadIdx.x; t < P * P; t += blockDim.x) {
-        const int x = tx + t / P - R, y = ty + t % P - R;
-        const bool kn = v.known(x, y);
-        c->known[t] = kn ? 1 : 0;
-        c->pix[t] = kn ? d.img[(int64_t)y * d.W + x] & 0x00ffffffu : 0u;
+#pragma unroll
+    for (int j = 0; j < PatchLoad<R>::N; ++j) {
+        const int t = (int)threadIdx.x + j * kCommitThreads;
+        if (t < P * P) {
+            const int x = tx + t / P - R, y = ty + t % P - R;
+            const bool kn = in_img(d, x, y) && f.hole[j] == 0;
+            c->known[t] = kn ? 1 : 0;
+            c->pix[t] = kn ? f.pix[j] & 0x00ffffffu : 0u;
+        }
     }
 }
 
@@ -1298,7 +1409,7 @@ __device__ void add_filled_sources(const JobDev &d, const LdsStage<R> &L, int px
 // PRE: precommit() already marked the patch's hole pixels filled (fb lists
 // them), listed the new front and computed its confidence terms; only the
 // colours are copied here.
-template <int R, bool ISECT = false, bool PRE = false>
+template <int R, bool ISECT = false, bool PRE = false, bool LEAN = false>
 __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const Snap &v, uint64_t best,
                               const Refresh &g, int64_t key0, int64_t idx0, Snap *out, FillSync *recs = nullptr,
                               CommitNote *note = nullptr, const PatchCopy<R> *far = nullptr,
@@ -1435,7 +1546,32 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
     const int tx = (int)(idx % W), ty = (int)(idx / W);
     const int adx = abs(tx - px), ady = abs(ty - py);
     int kk;
-    if (adx <= 2 * R + 2 && ady <= 2 * R + 2) {
+    if (LEAN) {
+        // (the same three sources of the patch as below)
+        using S = Stage<R>;
+        constexpr int P = 2 * R + 1;
+        if (adx <= 2 * R + 2 && ady <= 2 * R + 2) {
+            kk = stage_slots_lean(R, tx, ty, d.tgt, s, recs, [&](int t, uint32_t *pix) {
+                const int i = (ty + t % P - R - py + S::half) * S::side + (tx + t / P - R - px + S::half);
+                if (L.st[i] != 0) return false;
+                *pix = L.img[i] & 0x00ffffffu;
+                return true;
+            });
+        } else if (far && far->idx == idx) {
+            kk = stage_slots_lean(R, tx, ty, d.tgt, s, recs, [&](int t, uint32_t *pix) {
+                *pix = far->pix[t];
+                return far->known[t] != 0;
+            });
+        } else {
+            const GlobalView gv{d};
+            kk = stage_slots_lean(R, tx, ty, d.tgt, s, recs, [&](int t, uint32_t *pix) {
+                const int x = tx + t / P - R, y = ty + t % P - R;
+                if (!gv.known(x, y)) return false;
+                *pix = d.img[(int64_t)y * d.W + x] & 0x00ffffffu;
+                return true;
+            });
+        }
+    } else if (adx <= 2 * R + 2 && ady <= 2 * R + 2) {
         kk = stage_target_lds<R>(L, px, py, tx, ty, d.tgt, s, d.mfma ? d.frag : nullptr, recs);
     } else if (far && far->idx == idx) {
         // the best pixel of the untouched blocks, copied before this
@@ -1592,8 +1728,9 @@ union FillLds {
     SearchLds<R, NY> s;
 };
 
-// TB: tail loads in flight in gather() (fewer under a tighter register budget).
-template <int R, int TB>
+// TB, BW: gather()'s load batching (smaller under a tighter register budget);
+// LEAN: the search groups read only the words and the known mask of a record.
+template <int R, int TB, int BW, bool LEAN>
 __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t epoch, CommitLds<R> &C) {
     Scratch &s = C.s;
     LdsStage<R> &L = C.L;
@@ -1616,15 +1753,18 @@ __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t 
     if (!v.done && !v.err && v.pending) write_records(sy, d.tgt, 2 * R + 1);
     for (int i = threadIdx.x; i < ntiles; i += blockDim.x)
         __hip_atomic_store(&d.fslot[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool fresh = false;   // s.snap holds the state commit_finish left
     for (uint32_t k = 0;; ++k) {
-        const bool stop = v.done || v.err || !v.pending || v.iter >= v.limit || (int)k >= n_iters;
         // Every wave's writes (records, state, slot resets) reach this
         // XCD's L2; then wave 0's release of go writes the L2 back, so they
         // reach device scope before go does.  (Nothing this group reads is
         // written by another group except through device-scope loads, so no
-        // acquire is needed.)
+        // acquire is needed.)  The barrier also publishes s.snap.
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+        if (fresh) v = s.snap;
+        fresh = false;
+        const bool stop = v.done || v.err || !v.pending || v.iter >= v.limit || (int)k >= n_iters;
         publish_go(sy, go_word(epoch, stop ? 0xffffffffu : k + 1));
         if (stop) break;
 
@@ -1632,14 +1772,18 @@ __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t 
         const int px = (int)(v.p % d.W), py = (int)(v.p / d.W);
         const Refresh g = refresh_geometry<R>(d, px, py);
         int64_t key = -1, idx = INT64_MAX;
-        gather<R, false, TB>(d, px, py, g, L, key, idx);
-        __syncthreads();
-        grad_pass<R>(L, 1, Stage<R>::side - 1);
-        block_argmax(key, idx, s.k, s.i);
+        gather<R, false, TB, BW>(d, px, py, g, L, key, idx);
+        block_argmax(key, idx, s.k, s.i);   // its barriers also publish the neighbourhood
         // the untouched blocks' best pixel wins whenever the next target is
-        // far: copy its patch while the search still runs
-        copy_patch<R>(d, key >= 0 ? idx : -1, &C.far);
+        // far: copy its patch while the search still runs, its loads in
+        // flight during the precommit
+        const int64_t far_idx = key >= 0 ? idx : -1;
+        const PatchLoad<R> far = load_patch<R>(d, far_idx);
         precommit<R>(d, v, g, L, C.fill);
+        // (after the precommit marked the patch known: the gradients within
+        // one pixel of the patch are recomputed after the copy anyway)
+        grad_pass<R>(L, 1, Stage<R>::side - 1);
+        store_patch<R>(d, far_idx, far, &C.far);
 
         // (its barriers also publish the gathered LDS neighbourhood)
         int ok = 0;
@@ -1649,12 +1793,15 @@ __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t 
             v.err = INPAINT_DEVICE;
             continue;      // publishes stop
         }
-        commit_finish<R, false, true>(d, s, L, v, best, g, key, idx, &s.snap, sy, nullptr, &C.far, C.fill);
-        __syncthreads();
-        v = s.snap;
+        commit_finish<R, false, true, LEAN>(d, s, L, v, best, g, key, idx, &s.snap, sy, nullptr, &C.far, C.fill);
+        fresh = true;
         staged = true;
     }
     // s.tp / s.mbits hold the last target staged here
+    if (LEAN && staged && v.pending && !v.done && !v.err) {
+        finish_stage(R, d.tgt, s);
+        __syncthreads();
+    }
     if (d0.mfma && staged && v.pending && !v.done && !v.err) build_mfma_frags(R, s, d0.frag);
 }
 
@@ -1771,7 +1918,7 @@ template <int R>
 __global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_fill_mfma(JobDev d, int ntiles, int n_iters, uint32_t epoch) {
     __shared__ FillLdsMfma<R> lds;
     if (blockIdx.x == 0)
-        fill_commit<R, 8>(d, ntiles, n_iters, epoch, lds.c);
+        fill_commit<R, 8, 12, true>(d, ntiles, n_iters, epoch, lds.c);
     else
         fill_search_mfma<R>(d, epoch, lds.s);
 }
@@ -1780,7 +1927,7 @@ template <int R>
 __global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fill(JobDev d, int ntiles, int n_iters, uint32_t epoch) {
     __shared__ FillLds<R, kFillTileRows> lds;
     if (blockIdx.x == 0)
-        fill_commit<R, 2>(d, ntiles, n_iters, epoch, lds.c);
+        fill_commit<R, 2, 4, false>(d, ntiles, n_iters, epoch, lds.c);
     else
         fill_search<R, kFillTileRows>(d, ntiles, epoch, lds.s);
 }

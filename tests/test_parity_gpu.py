@@ -227,6 +227,30 @@ def test_step_and_partial_runs_equal_one_run():
     assert g.run()[0] == B.DONE
 
 
+@pytest.mark.parametrize("path", [B.PATH_MFMA, B.PATH_SIMT])
+def test_persistent_dispatches_interleaved_with_steps(path):
+    # A persistent dispatch leaves the last target it staged for whatever
+    # runs next: single steps (stream form) and later dispatches must
+    # continue exactly where it stopped.
+    job = synth.small()
+    o = oracle.Oracle(job.rgb, job.mask, 4)
+    want = o.run()
+    g = B.Inpainter(job.rgb, job.mask, 4, form="persistent", path=path, iters_per_check=5)
+    assert g.run_form() == "persistent"
+    parts = []
+    st, n, got = g.run(max_iters=7, log_cap=8)
+    assert st == B.OK and n == 7
+    parts += [got, np.array([g.step(), g.step()], dtype=B.STEP_DTYPE)]
+    st, n, got = g.run(max_iters=3, log_cap=4)
+    assert st == B.OK and n == 3
+    parts += [got, np.array([g.step()], dtype=B.STEP_DTYPE)]
+    st, n, got = g.run(log_cap=len(want))
+    assert st == B.DONE
+    parts.append(got)
+    assert_logs_equal(np.concatenate(parts), want, f"persistent + steps, path {path}")
+    assert (g.read_image() == o.read()[0]).all()
+
+
 def test_create_errors():
     rgb = np.zeros((20, 20, 3), np.uint8)
     for mask, r, status in [(np.zeros((20, 20), np.uint8), 2, B.INVALID_ARGUMENT),
