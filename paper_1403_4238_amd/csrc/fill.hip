@@ -38,6 +38,11 @@ __device__ __forceinline__ bool in_img(const JobDev &d, int x, int y) {
 // ---- pixel views: what a priority evaluation reads -------------------------
 
 // Straight from global memory.
+// Column and row of a raster index (0 <= i < W * H < 2^31, so a 32-bit
+// unsigned division, much shorter than a 64-bit one).
+__device__ __forceinline__ int col_of(int64_t i, int W) { return (int)((uint32_t)i % (uint32_t)W); }
+__device__ __forceinline__ int row_of(int64_t i, int W) { return (int)((uint32_t)i / (uint32_t)W); }
+
 struct GlobalView {
     const JobDev &d;
     __device__ bool known(int x, int y) const { return in_img(d, x, y) && d.hole[(int64_t)y * d.W + x] == 0; }
@@ -664,7 +669,7 @@ __device__ void select_and_stage(const JobDev &d, Scratch &s) {
         if (threadIdx.x == 0) st->error = INPAINT_DEVICE;
         return;
     }
-    const int px = (int)(idx % d.W), py = (int)(idx / d.W);
+    const int px = col_of(idx, d.W), py = row_of(idx, d.W);
     stage_target(d, px, py, d.r, d.tgt, s, d.mfma ? d.frag : nullptr);
     if (threadIdx.x == 0) {
         const double2 cd = d.pcd[idx];
@@ -796,7 +801,7 @@ __device__ void precommit(const JobDev &d, const Snap &v, const Refresh &g, LdsS
     using S = Stage<R>;
     constexpr int P = 2 * R + 1;
     const int W = d.W;
-    const int px = (int)(v.p % W), py = (int)(v.p / W);
+    const int px = col_of(v.p, W), py = row_of(v.p, W);
     if (threadIdx.x < kMaskWords) fb[threadIdx.x] = 0;
     if (threadIdx.x == 0) L.nfront = 0;
     __syncthreads();
@@ -979,7 +984,7 @@ __global__ __launch_bounds__(256) void k_init_pixels(JobDev d, const uint8_t *rg
     }
     __syncthreads();
     if (i < n) {
-        const int x = (int)(i % d.W), y = (int)(i / d.W);
+        const int x = col_of(i, d.W), y = row_of(i, d.W);
         const bool h = mask[i] != 0;
         const uint32_t R = h ? 0 : rgb[i * ch], G = h ? 0 : rgb[i * ch + 1],
                        B = h ? 0 : rgb[i * ch + 2];
@@ -1057,7 +1062,7 @@ __global__ __launch_bounds__(256) void k_init_hdist(JobDev d, uint8_t *hdist) {
     const int64_t n = (int64_t)d.W * d.H;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int x = (int)(i % d.W), y = (int)(i / d.W);
+    const int x = col_of(i, d.W), y = row_of(i, d.W);
     int h = 10;
     for (int dx = 0; dx < 10; ++dx) {
         const int xl = x - dx, xr = x + dx;
@@ -1076,7 +1081,7 @@ __global__ __launch_bounds__(256) void k_init_vrad(JobDev d, const uint8_t *hdis
     const int64_t n = (int64_t)d.W * d.H;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int x = (int)(i % d.W), y = (int)(i / d.W);
+    const int x = col_of(i, d.W), y = row_of(i, d.W);
     int dist = 10;
     for (int dy = -9; dy <= 9; ++dy) {
         const int yy = y + dy, ady = dy < 0 ? -dy : dy;
@@ -1292,7 +1297,7 @@ __device__ __forceinline__ PatchLoad<R> load_patch(const JobDev &d, int64_t idx)
     constexpr int P = 2 * R + 1;
     PatchLoad<R> f{};
     if (idx < 0) return f;
-    const int tx = (int)(idx % d.W), ty = (int)(idx / d.W);
+    const int tx = col_of(idx, d.W), ty = row_of(idx, d.W);
 #pragma unroll
     for (int j = 0; j < PatchLoad<R>::N; ++j) {
         const int t = min((int)threadIdx.x + j * kCommitThreads, P * P - 1);
@@ -1309,7 +1314,7 @@ __device__ __forceinline__ void store_patch(const JobDev &d, int64_t idx, const 
     constexpr int P = 2 * R + 1;
     if (threadIdx.x == 0) c->idx = idx;
     if (idx < 0) return;
-    const int tx = (int)(idx % d.W), ty = (int)(idx / d.W);
+    const int tx = col_of(idx, d.W), ty = row_of(idx, d.W);
 #pragma unroll
     for (int j = 0; j < PatchLoad<R>::N; ++j) {
         const int t = (int)threadIdx.x + j * kCommitThreads;
@@ -1417,7 +1422,7 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
     IterState *st = d.st;
     constexpr int P = 2 * R + 1;
     const int W = d.W;
-    const int px = (int)(v.p % W), py = (int)(v.p / W);
+    const int px = col_of(v.p, W), py = row_of(v.p, W);
     Snap n = v;
     if (best == ~0ull) {
         if (threadIdx.x == 0) {
@@ -1431,7 +1436,7 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
     // ---- copy the source patch
     const int64_t q = (int64_t)(best & 0xffffffffu);
     const uint32_t ssd = (uint32_t)(best >> 32);
-    const int qx = (int)(q % W), qy = (int)(q / W);
+    const int qx = col_of(q, W), qy = row_of(q, W);
     // the hole pixels of the target patch: its in-image pixels minus the known k
     // (with INTERSECT scoring only those whose source pixel is a source pixel
     // are filled, counted as they are copied)
@@ -1543,7 +1548,7 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
     }
 
     // ---- stage the next target
-    const int tx = (int)(idx % W), ty = (int)(idx / W);
+    const int tx = col_of(idx, W), ty = row_of(idx, W);
     const int adx = abs(tx - px), ady = abs(ty - py);
     int kk;
     if (LEAN) {
@@ -1618,7 +1623,7 @@ __device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L, CommitN
         return;
     }
     if (v.iter >= v.limit) return;
-    const int px = (int)(v.p % d.W), py = (int)(v.p / d.W);
+    const int px = col_of(v.p, d.W), py = row_of(v.p, d.W);
     const Refresh g = refresh_geometry<R>(d, px, py);
     int64_t key = -1, idx = INT64_MAX;
     uint64_t best = gather<R, true>(d, px, py, g, L, key, idx);
@@ -1769,7 +1774,7 @@ __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t 
         if (stop) break;
 
         // search-independent loads of the commit, overlapping the search
-        const int px = (int)(v.p % d.W), py = (int)(v.p / d.W);
+        const int px = col_of(v.p, d.W), py = row_of(v.p, d.W);
         const Refresh g = refresh_geometry<R>(d, px, py);
         int64_t key = -1, idx = INT64_MAX;
         gather<R, false, TB, BW>(d, px, py, g, L, key, idx);
@@ -1941,7 +1946,7 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit(JobDev d) {
     commit_body<R, ISECT>(d, s, L, &note);
     if (d.policy == INPAINT_SOURCE_CURRENT) {
         __syncthreads();
-        if (note.filled > 0) add_filled_sources<R, ISECT>(d, L, (int)(note.p % d.W), (int)(note.p / d.W));
+        if (note.filled > 0) add_filled_sources<R, ISECT>(d, L, col_of(note.p, d.W), row_of(note.p, d.W));
     }
 }
 
