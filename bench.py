@@ -355,8 +355,7 @@ def batch_bench(a):
     from paper_1403_4238_amd import binding as B
     from paper_1403_4238_amd import synth
     jobs = synth.batch()
-    tune = os.path.join(ROOT, "gpurun_out", "tune_cache.json") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) \
-        else None
+    tune = os.environ.get("INPAINT_TUNE_CACHE")   # optional file that keeps the autotuner's choices
 
     def make(form="plain"):
         return [B.Inpainter(j.rgb, j.mask, j.patch_radius, form=form, iters_per_check=a.iters_per_check)
