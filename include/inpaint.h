@@ -199,12 +199,18 @@ int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t target_x, int32_t target
                               int32_t patch_radius, inpaint_rect search_rect,
                               int64_t *source_index, uint32_t *ssd);
 
-/* One iteration (front, priority, search, copy) with the context's search
- * rectangle.  Fills *info (may be NULL).  Returns INPAINT_DONE without work
- * if the hole is already empty.  Synchronises. */
+/* One iteration of the fill loop of Section 3: compute the fill front, take
+ * the front pixel of maximum priority P = C D (Eq. 1-2; ties to the lowest
+ * raster index), find its best exemplar (Eq. 3-4) in the context's search
+ * rectangle, copy the exemplar into the target's hole pixels and give them
+ * the target's confidence.  Fills *info (may be NULL).  Returns INPAINT_DONE
+ * without work if the hole is already empty.  Synchronises. */
 int32_t inpaint_step(inpaint_ctx *ctx, inpaint_step_info *info);
 
-/* Iterates until the hole is empty or max_iters iterations (max_iters < 0:
+/* The fill loop of Section 3 (repeat the iteration of inpaint_step until the
+ * target region is empty; at most |Omega_0| iterations, Section 5.4 gives
+ * their rough count).  Iterates until the hole is empty or max_iters
+ * iterations (max_iters < 0:
  * no limit) have run, in the form chosen by params.form.  Writes the
  * number of iterations run to *iters_done and, when log is not NULL, the
  * first min(log_cap, iterations, log capacity) records of this call.  Returns

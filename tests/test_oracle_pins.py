@@ -286,6 +286,100 @@ def test_select_ties_lowest_index(O):
     assert i == 6 * 20 + 7 and p == 0.0
 
 
+def _front_np(hole):
+    """R5 by array shifts: hole pixels with an in-image known 4-neighbour."""
+    H, W = hole.shape
+    k = np.zeros((H + 2, W + 2), bool)
+    k[1:-1, 1:-1] = hole == 0
+    nb = k[:-2, 1:-1] | k[2:, 1:-1] | k[1:-1, :-2] | k[1:-1, 2:]
+    return np.flatnonzero((hole != 0) & nb)
+
+
+def test_select_is_maximum_hand_derived(O):
+    # Sec. 3 / Eq. 1: the front pixel of MAXIMUM priority is filled first.
+    # Two 2-pixel holes, each inside a purely vertical gray ramp: hole A
+    # (upper, earlier in raster order) in a ramp of slope 3, hole B (lower)
+    # in a ramp of slope 7.  Every known fully-supported pixel of each patch
+    # has gx = 0, gy = 2*slope; the normal at each hole pixel is horizontal
+    # (kn = 1), so a = |gy| and D = 0.5*2*slope/255.  Each patch holds two
+    # unknown pixels, so C = (P^2-2)/P^2 for all four front pixels.  B's two
+    # pixels tie at the maximum; the lower index is B's left pixel.  An
+    # argmin would pick A's left pixel, a last-on-ties rule B's right one.
+    W, H, r = 40, 40, 2
+    P = 2 * r + 1
+    y = np.arange(H)[:, None]
+    g = np.where(y < 16, 10 + 3 * y, 40 + 7 * (y - 16)) + np.zeros((1, W), int)
+    rgb = _gray_rgb(g)
+    mask = np.zeros((H, W), np.uint8)
+    mask[6, 10:12] = 1      # A: rows 3..9 of its supported patch lie in the slope-3 ramp
+    mask[28, 20:22] = 1     # B: rows 25..31 lie in the slope-7 ramp
+    o = O.Oracle(rgb, mask, r)
+    assert list(o.front()) == [6 * W + 10, 6 * W + 11, 28 * W + 20, 28 * W + 21]
+    c_want = (P * P - 2) / (P * P)
+    d_a, d_b = (0.5 * 6) / 255.0, (0.5 * 14) / 255.0
+    for x in (10, 11):
+        assert o.priority(x, 6) == (c_want, d_a, c_want * d_a)
+    for x in (20, 21):
+        assert o.priority(x, 28) == (c_want, d_b, c_want * d_b)
+    assert o.select() == (28 * W + 20, c_want, d_b, c_want * d_b)
+    assert o.step()["target_index"] == 28 * W + 20
+
+
+def _argmax_lowest(values, idx):
+    """Maximum of values, ties to the lowest index (idx ascending)."""
+    best = max(values)
+    return idx[values.index(best)], values.count(best)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_select_is_argmax_over_front_random(O, seed):
+    # select() against a numpy argmax over the front (found by array shifts)
+    # of the independently pinned per-pixel priorities, over the first
+    # iterations of random removals, so confidence is no longer uniform.
+    job = synth.random_small(100 + seed, 22, 18)
+    rng = np.random.default_rng(seed)
+    mask = job.mask.copy()
+    mask[rng.integers(3, 15), rng.integers(3, 19)] = 1
+    o = O.Oracle(job.rgb, mask, 1 + seed % 3)
+    for _ in range(6):
+        _, _, hole, _ = o.read()
+        front = _front_np(hole)
+        if front.size == 0:
+            break
+        assert list(o.front()) == list(front)
+        pr = [o.priority(int(i % 22), int(i // 22))[2] for i in front]
+        want, _ = _argmax_lowest(pr, list(front))
+        got = o.select()
+        assert got[0] == want and got[3] == max(pr)
+        assert o.step()["target_index"] == want
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_select_ties_at_the_maximum_go_to_lowest_index(O, seed):
+    # A left-right mirror-symmetric state (gray constant along each row, a
+    # hole symmetric about the vertical axis of an even-width image): every
+    # front pixel and its mirror have identical confidence sums (all 1.0 or
+    # 0.0) and identical |gy|, so the maximum is reached at least twice, and
+    # the lower raster index must win (R12).
+    rng = np.random.default_rng(seed)
+    W, H, r = 24, 20, 1 + seed
+    g = np.repeat(rng.integers(0, 256, size=(H, 1)), W, axis=1)
+    rgb = _gray_rgb(g)
+    mask = np.zeros((H, W), np.uint8)
+    half = (rng.random((6, 5)) < 0.6).astype(np.uint8)
+    half[2:4, 3:5] = 1
+    mask[7:13, 7:12] = half
+    mask[:, 12:] = mask[:, 11::-1]
+    assert (mask == mask[:, ::-1]).all()
+    o = O.Oracle(rgb, mask, r)
+    _, _, hole, _ = o.read()
+    front = _front_np(hole)
+    pr = [o.priority(int(i % W), int(i // W))[2] for i in front]
+    want, n_max = _argmax_lowest(pr, list(front))
+    assert n_max >= 2 and max(pr) > 0.0
+    assert o.select()[0] == want
+
+
 # ----------------------------------------------------------------- search
 
 def _brute_search(rgb, hole_now, hole0, tx, ty, r, rect):
