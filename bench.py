@@ -37,11 +37,16 @@ sys.path.insert(0, ROOT)
 CUS, LANES_PER_CU_CYCLE, CLOCK_HZ = 256, 64, 2.4e9
 VALU_LANE_OPS = CUS * LANES_PER_CU_CYCLE * CLOCK_HZ          # 39.32e12 lane-instructions/s
 # A term is one (offset, channel, candidate) product of the cross term.  The
-# least VALU work for it is one v_dot4_u32_u8 per (known offset, candidate),
-# i.e. 3 RGB terms per lane-instruction (the square term costs O(column runs)
-# by running sums and is not counted).
-TERMS_PER_VALU_OP = 3.0
-TERM_PEAK = VALU_LANE_OPS * TERMS_PER_VALU_OP                # 117.96e12 terms/s
+# SIMT search does one v_dot4_u32_u8 per (known offset, candidate); the
+# instruction forms 4 int8 products per lane, so the VALU's dot4 peak is
+# 4 products per lane-instruction (157.3e12/s), against which the SIMT
+# roofline fraction is reported.  The RGBX layout uses 3 of the 4 (the
+# fourth byte is 0), so 3 terms per lane-instruction (117.96e12/s) is the
+# layout-limited ceiling, reported beside it.  The square term costs
+# O(column runs) by running sums and is not counted.
+PRODUCTS_PER_DOT4 = 4.0
+TERM_PEAK = VALU_LANE_OPS * PRODUCTS_PER_DOT4                # 157.3e12 products/s
+TERM_PEAK_LAYOUT = VALU_LANE_OPS * 3.0                       # 117.96e12 RGB terms/s
 # int8 MFMA, dense: 5.0 POP/s = 2.5e15 multiply-accumulates (terms) per second.
 MFMA_TERM_PEAK = 2.5e15
 # The roofline is reported in ops: a term is two (a subtract and a
@@ -532,21 +537,38 @@ def main():
     # graph form replays them as a hipGraph (no events inside).
     others = {}
     if not a.no_other_form:
-        for form in ("stream", "graph"):
-            if form == res["run_form"]:
+        # (name, form, path): the same search path in the stream, graph and
+        # plain (one search launch and one host check per iteration) forms,
+        # and the persistent form on the other search path.
+        other_path = "simt" if a.path == "mfma" else "mfma"
+        variants = [("stream", "stream", a.path), ("graph", "graph", a.path), ("plain", "plain", a.path)]
+        if domain == ("original", "whole") and a.path != "direct" and (other_path == "simt" or r <= 6):
+            variants.append((f"persistent_{other_path}", "persistent", other_path))
+        for name, form, opath in variants:
+            if form == res["run_form"] and opath == a.path:
                 continue
-            o = timed_removals(job, 1, 0, form, a.iters_per_check, a.tile_rows, timing=(form == "stream"),
-                               path=a.path, domain=domain)
+            o = timed_removals(job, 1, 0, form, a.iters_per_check, a.tile_rows, timing=(form != "graph"),
+                               path=opath, domain=domain)
             rec = {"ms_per_removal": round(1000 * o["seconds"], 2),
-                   "patch_evals_per_s": round(sum(o["iters"]) * o["candidates"] / o["seconds"], 1)}
-            if form == "stream":
-                sk_ms = o["kernel_ms"] / max(o["searches"], 1)
-                sk_rate = terms_per_removal / max(len(log), 1) / (sk_ms * 1e-3)
-                rec["search_kernel"] = {
-                    "kernel": search_kernel_name(a.path, r, a.tile_rows),
-                    "avg_launch_us": round(1000 * sk_ms, 3), "achieved": round(OPS_PER_TERM * sk_rate / 1e12, 3),
-                    "peak": round(OPS_PER_TERM * peak / 1e12, 2), "unit": "TOP/s", "frac": round(sk_rate / peak, 5)}
-            others[form] = rec
+                   "patch_evals_per_s": round(sum(o["iters"]) * o["candidates"] / o["seconds"], 1),
+                   "form": o["run_form"], "path": opath,
+                   "bit_exact_vs_headline": bool(len(o["log"]) == len(log) and (o["log"] == log).all()
+                                                 and (o["image"] == res["image"]).all())}
+            opeak = MFMA_TERM_PEAK if opath == "mfma" else TERM_PEAK
+            if form != "graph":
+                k_ms = o["kernel_ms"] / max(o["searches"], 1)
+                k_terms = terms_per_removal / max(o["searches"], 1)
+                k_rate = k_terms / (k_ms * 1e-3)
+                kname = ((f"k_fill_mfma<R={r}>" if opath == "mfma" else f"k_fill<R={r}>")
+                         if o["run_form"] == "persistent" else search_kernel_name(opath, r, a.tile_rows))
+                rec["kernel"] = {
+                    "kernel": kname, "bound": "mfma" if opath == "mfma" else "alu",
+                    "avg_launch_us": round(1000 * k_ms, 3), "launches_timed": o["searches"],
+                    "achieved": round(OPS_PER_TERM * k_rate / 1e12, 3),
+                    "peak": round(OPS_PER_TERM * opeak / 1e12, 2), "unit": "TOP/s", "frac": round(k_rate / opeak, 5)}
+                if opath != "mfma":
+                    rec["kernel"]["frac_of_rgb_layout_ceiling"] = round(k_rate / TERM_PEAK_LAYOUT, 5)
+            others[name] = rec
 
     line = {
         "metric": "masked-SSD patch evals/s (ms per 1080p removal alongside)",
@@ -589,6 +611,10 @@ def main():
         },
         "other_forms": others,
     }
+    if "plain" in others:
+        line["speedup_vs_plain"] = round(others["plain"]["ms_per_removal"] / ms_per_step, 3)
+    if a.path != "mfma":
+        line["roofline"]["frac_of_rgb_layout_ceiling"] = round(achieved / TERM_PEAK_LAYOUT, 5)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(job, a.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -957,7 +957,7 @@ __device__ __forceinline__ int stage_target_lds(const LdsStage<R> &L, int px, in
 
 // ----------------------------------------------------------------- kernels
 
-__global__ void k_init_info(InitInfo *info) {
+__global__ void k_init_info(InitInfo *info, uint32_t nonce) {
     info->hole_count = 0;
     info->bad = 0;
     info->bx0 = INT32_MAX;
@@ -965,7 +965,12 @@ __global__ void k_init_info(InitInfo *info) {
     info->bx1 = INT32_MIN;
     info->by1 = INT32_MIN;
     info->valid_count = 0;
+    info->nonce = nonce;
+    info->seal = 0;
+    info->blocks = 0;
 }
+
+__global__ void k_seal(InitInfo *info, uint32_t nonce) { info->seal = nonce; }
 
 // Initialisation: zero the hole pixels, RGBX image, integer BT.601 gray
 // (299 R + 587 G + 114 B + 500) div 1000, hole map, confidence 1 / 0, hole
@@ -1009,6 +1014,7 @@ __global__ __launch_bounds__(256) void k_init_pixels(JobDev d, const uint8_t *rg
         atomicMax(&d.info->bx1, s_x1);
         atomicMax(&d.info->by1, s_y1);
     }
+    if (threadIdx.x == 0) atomicAdd(&d.info->blocks, 1u);
 }
 
 // ---- checkpoint import (resume / iterative editing) ------------------------
@@ -1026,6 +1032,7 @@ __global__ __launch_bounds__(256) void k_import_check(JobDev d, const uint8_t *h
         bad = (h && !h0) || (h0 && !h && !(c >= 0.0 && c <= 1.0));
     }
     if (bad) atomicAdd((unsigned long long *)&d.info->bad, 1ull);
+    if (threadIdx.x == 0) atomicAdd(&d.info->blocks, 1u);
 }
 
 // Overlays a checked checkpoint on the original-hole pixels: those still in
@@ -1049,11 +1056,15 @@ __global__ __launch_bounds__(256) void k_import_apply(JobDev d, const uint8_t *r
     }
     __syncthreads();
     if (threadIdx.x == 0 && s_cnt > 0) atomicAdd((unsigned long long *)&d.info->hole_count, (unsigned long long)s_cnt);
+    if (threadIdx.x == 0) atomicAdd(&d.info->blocks, 1u);
 }
 
-__global__ void k_import_reset(InitInfo *info) {
+__global__ void k_import_reset(InitInfo *info, uint32_t nonce) {
     info->hole_count = 0;
     info->bad = 0;
+    info->nonce = nonce;
+    info->seal = 0;
+    info->blocks = 0;
 }
 
 // Horizontal distance (capped at 10) from each pixel to the nearest hole or
@@ -2002,10 +2013,17 @@ __global__ void k_count_active(const JobDev *slots, int nslots, int64_t *out, in
 
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+uint32_t init_pixel_blocks(const JobDev &d) { return blocks_for((int64_t)d.W * d.H, 256); }
+
+hipError_t launch_seal(const JobDev &d, uint32_t nonce, hipStream_t s) {
+    hipLaunchKernelGGL(k_seal, dim3(1), dim3(1), 0, s, d.info, nonce);
+    return hipGetLastError();
+}
+
 hipError_t launch_init(const JobDev &d, const uint8_t *stage_rgb, int channels,
-                       const uint8_t *stage_mask, uint8_t *hdist, hipStream_t s) {
+                       const uint8_t *stage_mask, uint8_t *hdist, uint32_t nonce, hipStream_t s) {
     const int64_t n = (int64_t)d.W * d.H;
-    hipLaunchKernelGGL(k_init_info, dim3(1), dim3(1), 0, s, d.info);
+    hipLaunchKernelGGL(k_init_info, dim3(1), dim3(1), 0, s, d.info, nonce);
     hipLaunchKernelGGL(k_init_pixels, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, stage_rgb,
                        channels, stage_mask);
     hipLaunchKernelGGL(k_init_hdist, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, hdist);
@@ -2016,17 +2034,18 @@ hipError_t launch_init(const JobDev &d, const uint8_t *stage_rgb, int channels,
     return hipGetLastError();
 }
 
-hipError_t launch_import_check(const JobDev &d, const uint8_t *hole, const double *conf, hipStream_t s) {
+hipError_t launch_import_check(const JobDev &d, const uint8_t *hole, const double *conf, uint32_t nonce,
+                               hipStream_t s) {
     const int64_t n = (int64_t)d.W * d.H;
-    hipLaunchKernelGGL(k_import_reset, dim3(1), dim3(1), 0, s, d.info);
+    hipLaunchKernelGGL(k_import_reset, dim3(1), dim3(1), 0, s, d.info, nonce);
     hipLaunchKernelGGL(k_import_check, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, hole, conf);
     return hipGetLastError();
 }
 
 hipError_t launch_import_apply(const JobDev &d, const uint8_t *rgb, int channels, const uint8_t *hole,
-                               const double *conf, uint8_t *hdist, hipStream_t s) {
+                               const double *conf, uint8_t *hdist, uint32_t nonce, hipStream_t s) {
     const int64_t n = (int64_t)d.W * d.H;
-    hipLaunchKernelGGL(k_import_reset, dim3(1), dim3(1), 0, s, d.info);
+    hipLaunchKernelGGL(k_import_reset, dim3(1), dim3(1), 0, s, d.info, nonce);
     hipLaunchKernelGGL(k_import_apply, dim3(blocks_for(n, 256)), dim3(256), 0, s, d, rgb, channels, hole, conf);
     if (d.policy == INPAINT_SOURCE_CURRENT) {
         // the source region is the current known region: rebuild its planes

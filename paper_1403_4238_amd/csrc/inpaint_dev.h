@@ -125,11 +125,19 @@ struct BlockBest {
     int64_t idx;
 };
 
+// Results of the init, count and import kernels, read back by the host.
+// nonce is written by the first kernel of a sequence, seal by its last one,
+// and blocks counts the work-groups of the pixel pass that ran to the end,
+// so the host can tell "the kernels ran and found nothing" (a caller error)
+// from "the kernels did not run" (a device error).
 struct InitInfo {
     int64_t hole_count;
     int32_t bx0, by0, bx1, by1;  // bounding box of the hole, half-open
     int64_t valid_count;         // valid source centres in the search rect
     int64_t bad;                 // pixels of an imported checkpoint that fail its checks
+    uint32_t nonce, seal;        // per-call value, from the first and the last kernel
+    uint32_t blocks;             // work-groups of the pixel pass that completed
+    uint32_t pad;
 };
 
 // Everything a kernel needs about one job.  Passed by value to the
@@ -183,15 +191,20 @@ struct WorkItem {
 
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_init(const JobDev &d, const uint8_t *stage_rgb, int channels,
-                       const uint8_t *stage_mask, uint8_t *hdist, hipStream_t s);
+                       const uint8_t *stage_mask, uint8_t *hdist, uint32_t nonce, hipStream_t s);
+// Work-groups of the pixel pass of launch_init / launch_import_*.
+uint32_t init_pixel_blocks(const JobDev &d);
+// Writes info->seal = nonce once every earlier kernel on the stream is done.
+hipError_t launch_seal(const JobDev &d, uint32_t nonce, hipStream_t s);
 hipError_t launch_count_valid(const JobDev &d, hipStream_t s);
 // Checkpoint import: the checks (counted into info->bad, nothing written),
 // then the overlay of the original-hole pixels (remaining hole counted into
 // info->hole_count) and, under the CURRENT source policy, the rebuilt source
 // and validity planes.
-hipError_t launch_import_check(const JobDev &d, const uint8_t *hole, const double *conf, hipStream_t s);
+hipError_t launch_import_check(const JobDev &d, const uint8_t *hole, const double *conf, uint32_t nonce,
+                               hipStream_t s);
 hipError_t launch_import_apply(const JobDev &d, const uint8_t *rgb, int channels, const uint8_t *hole,
-                               const double *conf, uint8_t *hdist, hipStream_t s);
+                               const double *conf, uint8_t *hdist, uint32_t nonce, hipStream_t s);
 hipError_t launch_prio_init(const JobDev &d, hipStream_t s);
 hipError_t launch_commit(const JobDev &d, hipStream_t s);
 // SIMT search of one target; `d.isect` selects INTERSECT scoring.

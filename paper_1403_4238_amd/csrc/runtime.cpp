@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -21,6 +22,8 @@
 
 using namespace inpaint;
 
+static_assert(sizeof(InitInfo) <= 64, "InitInfo is read back through the 64-byte pinned key buffer");
+
 namespace {
 
 thread_local std::string g_create_error;
@@ -29,6 +32,24 @@ constexpr uint64_t kAlign = 256;
 constexpr int kDefaultTileRows = 8;
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Per-call values the init, count and import kernel sequences write into
+// InitInfo (never 0, which is what a fresh workspace holds).
+std::atomic<uint32_t> g_nonce{0};
+uint32_t next_nonce() {
+    uint32_t v;
+    do v = (g_nonce.fetch_add(1) + 1) * 2654435761u;
+    while (v == 0);
+    return v;
+}
+
+// Whether the kernel sequence stamped with `nonce` ran to its end: its first
+// kernel wrote the nonce, its last one the seal, and (blocks != 0) every
+// work-group of its pixel pass finished.  When it did not, what InitInfo
+// holds says nothing about the caller's input.
+bool sealed(const InitInfo &info, uint32_t nonce, uint32_t blocks) {
+    return info.nonce == nonce && info.seal == nonce && (blocks == 0 || info.blocks == blocks);
+}
 
 struct Layout {
     uint64_t img, gray, hole, hole0, vrad, conf, pcd, blk, partials, tgt, qtgt, frag, qfrag, srcw, srcq, srcp, vradp, hdist, st,
@@ -394,13 +415,17 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
                                     hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpy2DAsync(stage_mask, W, mask, mask_stride, W, H, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_init(d, stage_rgb, ch, stage_mask, hdist, s);
+    const uint32_t nonce = next_nonce();
+    if (e == hipSuccess) e = launch_init(d, stage_rgb, ch, stage_mask, hdist, nonce, s);
     if (e == hipSuccess && d.mfma) e = launch_mfma_planes(d, s);
+    if (e == hipSuccess) e = launch_seal(d, nonce, s);
     if (e == hipSuccess) e = hipMemcpyAsync(c->h_key, d.info, sizeof(InitInfo), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return create_fail(c, INPAINT_DEVICE, std::string("init: ") + hipGetErrorString(e));
     InitInfo info;
     std::memcpy(&info, c->h_key, sizeof(info));
+    if (!sealed(info, nonce, init_pixel_blocks(d)))
+        return create_fail(c, INPAINT_DEVICE, "init kernels did not run to completion (no error was reported)");
     if (info.hole_count <= 0) return create_fail(c, INPAINT_INVALID_ARGUMENT, "mask is empty");
     if (info.hole_count >= (int64_t)n) return create_fail(c, INPAINT_INVALID_ARGUMENT, "mask covers the whole image");
     c->hole0 = info.hole_count;
@@ -435,11 +460,15 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     d.pbx1 = (std::min(info.bx1 + reach, W) + kBlock - 1) / kBlock;
     d.pby1 = (std::min(info.by1 + reach, H) + kBlock - 1) / kBlock;
 
+    const uint32_t nonce2 = next_nonce();
     e = launch_count_valid(d, s);
+    if (e == hipSuccess) e = launch_seal(d, nonce2, s);
     if (e == hipSuccess) e = hipMemcpyAsync(c->h_key, d.info, sizeof(InitInfo), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return create_fail(c, INPAINT_DEVICE, std::string("count: ") + hipGetErrorString(e));
     std::memcpy(&info, c->h_key, sizeof(info));
+    if (info.seal != nonce2)
+        return create_fail(c, INPAINT_DEVICE, "the candidate count did not run to completion (no error was reported)");
     if (info.valid_count <= 0)
         return create_fail(c, INPAINT_INVALID_ARGUMENT, "no valid source centre in the search rectangle");
     c->candidates = info.valid_count;
@@ -457,6 +486,8 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     if (e == hipSuccess) e = c->pull_state();
     if (e != hipSuccess) return create_fail(c, INPAINT_DEVICE, std::string("first select: ") + hipGetErrorString(e));
     if (c->h_state->error) return create_fail(c, INPAINT_DEVICE, "device error during the first selection");
+    if (!c->h_state->pending && !c->h_state->done)
+        return create_fail(c, INPAINT_DEVICE, "the first selection did not run (no error was reported)");
     c->run_form = p->form;
     if (p->form == INPAINT_FORM_PERSISTENT && !persistent_fits(c)) c->run_form = INPAINT_FORM_STREAM;
     *out = c;
@@ -730,11 +761,15 @@ int32_t inpaint_import_state(inpaint_ctx *ctx, const uint8_t *rgb, int32_t rgb_s
                                       hipMemcpyHostToDevice, s), "upload");
     HIP_OR_FAIL(ctx, hipMemcpy2DAsync(s_hole, W, hole, hole_stride, W, H, hipMemcpyHostToDevice, s), "upload");
     HIP_OR_FAIL(ctx, hipMemcpyAsync(s_conf, conf, 8 * n, hipMemcpyHostToDevice, s), "upload");
-    HIP_OR_FAIL(ctx, launch_import_check(d, s_hole, s_conf, s), "check");
+    const uint32_t nonce = next_nonce();
+    HIP_OR_FAIL(ctx, launch_import_check(d, s_hole, s_conf, nonce, s), "check");
+    HIP_OR_FAIL(ctx, launch_seal(d, nonce, s), "check");
     HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_key, d.info, sizeof(InitInfo), hipMemcpyDeviceToHost, s), "check");
     HIP_OR_FAIL(ctx, hipStreamSynchronize(s), "check");
     InitInfo info;
     std::memcpy(&info, ctx->h_key, sizeof(info));
+    if (!sealed(info, nonce, init_pixel_blocks(d)))
+        return ctx->hip_fail(hipErrorUnknown, "checkpoint check kernels did not run to completion");
     if (info.bad != 0) {
         // nothing changed but the priority terms the staging overwrote
         HIP_OR_FAIL(ctx, launch_prio_init(d, s), "restore");
@@ -742,11 +777,15 @@ int32_t inpaint_import_state(inpaint_ctx *ctx, const uint8_t *rgb, int32_t rgb_s
         return ctx->fail(INPAINT_INVALID_ARGUMENT,
                          "checkpoint hole leaves the original hole, or a filled pixel's confidence is not in [0, 1]");
     }
-    HIP_OR_FAIL(ctx, launch_import_apply(d, s_rgb, channels, s_hole, s_conf, d.hdist ? d.hdist : s_hdist, s),
+    const uint32_t nonce2 = next_nonce();
+    HIP_OR_FAIL(ctx, launch_import_apply(d, s_rgb, channels, s_hole, s_conf, d.hdist ? d.hdist : s_hdist, nonce2, s),
                 "import");
+    HIP_OR_FAIL(ctx, launch_seal(d, nonce2, s), "import");
     HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_key, d.info, sizeof(InitInfo), hipMemcpyDeviceToHost, s), "import");
     HIP_OR_FAIL(ctx, hipStreamSynchronize(s), "import");
     std::memcpy(&info, ctx->h_key, sizeof(info));
+    if (!sealed(info, nonce2, init_pixel_blocks(d)))
+        return ctx->hip_fail(hipErrorUnknown, "checkpoint import kernels did not run to completion");
     IterState &h = *ctx->h_state;
     std::memset(&h, 0, sizeof(h));
     h.remaining = info.hole_count;

@@ -6,7 +6,7 @@ source hash, the iteration count, hashes of the final image and of the
 per-iteration log, and a sample of log records.  The GPU parity tests compare
 the HIP path's full runs against these.
 
-    python tests/golden/make_golden.py small vga hd9 hd9w hd13 hd13w batch:0-31
+    python tests/golden/make_golden.py small vga hd9 hd9w hd13 hd13w batch:0-31 serve:0-15
 """
 from __future__ import annotations
 
@@ -58,12 +58,13 @@ def workload(name: str):
         win = name.endswith("w")
         patch = int(name[2:].rstrip("w"))
         return [synth.hd(patch=patch, window=win)]
-    if name.startswith("batch"):
-        jobs = synth.batch()
-        if ":" in name:
-            lo, hi = (int(v) for v in name.split(":")[1].split("-"))
-            return [(i, jobs[i]) for i in range(lo, hi + 1)]
-        return list(enumerate(jobs))
+    for prefix, gen in (("batch", synth.batch), ("serve", synth.serving)):
+        if name.startswith(prefix):
+            jobs = gen()
+            if ":" in name:
+                lo, hi = (int(v) for v in name.split(":")[1].split("-"))
+                return [(prefix, i, jobs[i]) for i in range(lo, hi + 1)]
+            return [(prefix, i, j) for i, j in enumerate(jobs)]
     raise ValueError(name)
 
 
@@ -110,8 +111,8 @@ def main(names):
     for name in names:
         for item in workload(name):
             if isinstance(item, tuple):
-                i, job = item
-                run_one(f"batch{i:02d}", job)
+                prefix, i, job = item
+                run_one(f"{prefix}{i:02d}", job)
             else:
                 run_one(name, item)
 

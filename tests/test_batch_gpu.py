@@ -107,3 +107,27 @@ def test_batch_of_vga_sized_images_prefix():
         o = oracle.Oracle(j.rgb, j.mask, 4)
         want = o.run(max_iters=10)
         assert_logs_equal(c.read_log(0, 10), want, j.name)
+
+
+def test_batch_of_64_full_size_matches_stored_oracle(tmp_path):
+    # The seeded 64-image batch (320x240 .. 1280x720, 1-3 blobs covering
+    # 2-10%, 9x9 patch, full search), run to the end in the batched form with
+    # the autotuner on and hipGraph replays of 16 iterations: every image's
+    # whole fill log and final image equal its stored oracle result.
+    from _util import assert_matches_golden, load_golden
+    jobs = synth.batch()
+    golds = [load_golden(f"batch{i:02d}") for i in range(len(jobs))]
+    assert all(g is not None for g in golds), "stored oracle results missing"
+    for j, g in zip(jobs, golds):
+        assert g["input_sha256"] == j.sha256(), j.name
+    batch = B.Batch(capacity=len(jobs), graph_iters=16, autotune=True, tune_cache=str(tmp_path / "tune.json"))
+    ctxs = [B.Inpainter(j.rgb, j.mask, j.patch_radius) for j in jobs]
+    for c in ctxs:
+        batch.attach(c)
+    steps = 0
+    while batch.step() > 0:
+        steps += 1
+        assert steps < 2000
+    for j, g, c in zip(jobs, golds, ctxs):
+        assert c.remaining() == 0, j.name
+        assert_matches_golden(g, c.read_log(0, g["iterations"]), c.read_image(), j.name)
