@@ -199,6 +199,23 @@ int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t target_x, int32_t target
                               int32_t patch_radius, inpaint_rect search_rect,
                               int64_t *source_index, uint32_t *ssd);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * query as inpaint_find_exemplar, same arguments, results and errors, but
+ * its scratch (target stage, MFMA operands, one partial minimum per search
+ * tile, result key) lives in a static device array of the library (about
+ * 310 KB, one per GPU, held until the process ends) instead of the context's
+ * workspace.  The call allocates nothing.  A search rect that needs more
+ * than 32768 search tiles (about 67 M candidate centres with the default
+ * SIMT tile, 134 M with the MFMA tile) is rejected with INVALID_ARGUMENT.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (two threads, or two streams) race and must not be issued; it keeps
+ * only the last call's contents, none of which a call reads before writing.
+ * Synchronises. */
+int32_t inpaint_find_exemplar_static(inpaint_ctx *ctx, int32_t target_x, int32_t target_y,
+                                     int32_t patch_radius, inpaint_rect search_rect,
+                                     int64_t *source_index, uint32_t *ssd);
+
 /* One iteration of the fill loop of Section 3: compute the fill front, take
  * the front pixel of maximum priority P = C D (Eq. 1-2; ties to the lowest
  * raster index), find its best exemplar (Eq. 3-4) in the context's search

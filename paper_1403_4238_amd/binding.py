@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
         "inpaint_workspace_bytes": (i32, [i32, i32, P(inpaint_params), P(u64)]),
         "inpaint_create": (i32, [P(inpaint_image), vp, i32, P(inpaint_params), vp, u64, vp, P(vp)]),
         "inpaint_find_exemplar": (i32, [vp, i32, i32, i32, inpaint_rect, P(i64), P(ctypes.c_uint32)]),
+        "inpaint_find_exemplar_static": (i32, [vp, i32, i32, i32, inpaint_rect, P(i64), P(ctypes.c_uint32)]),
         "inpaint_step": (i32, [vp, vp]),
         "inpaint_run": (i32, [vp, i64, P(i64), vp, i64]),
         "inpaint_read_log": (i32, [vp, i64, i64, vp]),
@@ -214,6 +215,15 @@ class Inpainter:
         idx, ssd = ctypes.c_int64(), ctypes.c_uint32()
         self._check(lib().inpaint_find_exemplar(self.ctx, x, y, r, rc, ctypes.byref(idx),
                                                 ctypes.byref(ssd)), "inpaint_find_exemplar")
+        return idx.value, ssd.value
+
+    def find_exemplar_static(self, x: int, y: int, patch_radius: int | None = None, rect=None):
+        """find_exemplar through the allocation-free entry point."""
+        r = self.params.patch_radius if patch_radius is None else patch_radius
+        rc = inpaint_rect(*(rect if rect is not None else (0, 0, self.width, self.height)))
+        idx, ssd = ctypes.c_int64(), ctypes.c_uint32()
+        self._check(lib().inpaint_find_exemplar_static(self.ctx, x, y, r, rc, ctypes.byref(idx),
+                                                       ctypes.byref(ssd)), "inpaint_find_exemplar_static")
         return idx.value, ssd.value
 
     def step(self):

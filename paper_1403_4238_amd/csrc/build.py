@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libinpaint.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["fill.hip", "search.hip", "search_mfma.hip", "runtime.cpp"]
+SOURCES = ["fill.hip", "search.hip", "search_mfma.hip", "static_query.hip", "runtime.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

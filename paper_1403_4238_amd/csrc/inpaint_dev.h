@@ -236,4 +236,19 @@ hipError_t launch_fill(const JobDev &d, int ntiles, int n_iters, uint32_t epoch,
 
 inline int search_tile_h(int tile_rows) { return kSearchWaves * tile_rows; }
 
+// Allocation-free query (inpaint_find_exemplar_static): its target stage,
+// MFMA operands, per-tile partial minima and result key live in one static
+// device array of kStaticScratchBytes per GPU instead of the workspace.
+constexpr int kStaticMaxTiles = 32768;
+constexpr uint64_t kStaticStageOff = 0;
+constexpr uint64_t kStaticFragOff = (sizeof(TargetStage) + 255) / 256 * 256;
+constexpr uint64_t kStaticKeyOff = kStaticFragOff + (sizeof(MfmaFrags) + 255) / 256 * 256;
+constexpr uint64_t kStaticPartialsOff = kStaticKeyOff + 256;
+constexpr uint64_t kStaticScratchBytes = kStaticPartialsOff + 8ull * kStaticMaxTiles;
+// Takes the array's device address on `device`, which must be current
+// (once per device; later calls return the first result).
+hipError_t static_scratch_setup(int device);
+// The address static_scratch_setup took on `device`, or NULL.
+void *static_scratch(int device);
+
 }  // namespace inpaint

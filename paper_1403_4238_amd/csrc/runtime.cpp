@@ -142,6 +142,7 @@ struct inpaint_ctx {
     Layout L{};
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    int device = 0;           // device current at create (the workspace's)
     uint8_t *ws = nullptr;
     int64_t hole0 = 0;
     int64_t candidates = 0;
@@ -366,6 +367,10 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
         return create_fail(c, INPAINT_OUT_OF_MEMORY, "pinned host allocation failed");
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return create_fail(c, INPAINT_DEVICE, "stream creation failed");
+    if (hipGetDevice(&c->device) != hipSuccess) return create_fail(c, INPAINT_DEVICE, "no current device");
+    // Device address of the allocation-free query's scratch array on this
+    // device (taken once per device; a failure only disables that query).
+    static_scratch_setup(c->device);
 
     JobDev &d = c->d;
     uint8_t *ws = c->ws;
@@ -524,6 +529,56 @@ int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t tx, int32_t ty, int32_t 
     uint64_t *dkey = (uint64_t *)(ctx->ws + ctx->L.key);
     HIP_OR_FAIL(ctx, launch_stage_query(q, tx, ty, r, s), "stage");
     if (ctx->mfma && mfma_supported(r))
+        HIP_OR_FAIL(ctx, launch_search_mfma(q, true, r, q.rx0, q.ry0, q.rx1, q.ry1, q.ntx, q.nty, s), "search");
+    else if (ctx->direct)
+        HIP_OR_FAIL(ctx, launch_search_direct(q, true, r, q.rx0, q.ry0, q.rx1, q.ry1, q.tile_rows, q.ntx, q.nty, s),
+                    "search");
+    else
+        HIP_OR_FAIL(ctx, launch_search(q, true, r, q.rx0, q.ry0, q.rx1, q.ry1, q.tile_rows, q.ntx, q.nty, s), "search");
+    HIP_OR_FAIL(ctx, launch_reduce_partials(q, q.ntx * q.nty, dkey, s), "reduce");
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(ctx->h_key, dkey, 8, hipMemcpyDeviceToHost, s), "copy");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(s), "sync");
+    const uint64_t key = ctx->h_key[0];
+    if (key == ~0ull) return ctx->fail(INPAINT_NO_CANDIDATE, "no valid centre in the rect");
+    *source_index = (int64_t)(key & 0xffffffffu);
+    *ssd = (uint32_t)(key >> 32);
+    return INPAINT_OK;
+}
+
+// inpaint_find_exemplar with its scratch (target stage, MFMA operands, tile
+// partials, key) in the static device array instead of the workspace.
+int32_t inpaint_find_exemplar_static(inpaint_ctx *ctx, int32_t tx, int32_t ty, int32_t r, inpaint_rect rect,
+                                     int64_t *source_index, uint32_t *ssd) {
+    if (!ctx) return INPAINT_INVALID_ARGUMENT;
+    if (ctx->sticky) return ctx->sticky;
+    const JobDev &d = ctx->d;
+    if (!source_index || !ssd) return ctx->fail(INPAINT_INVALID_ARGUMENT, "NULL output");
+    if (tx < 0 || ty < 0 || tx >= d.W || ty >= d.H) return ctx->fail(INPAINT_INVALID_ARGUMENT, "target outside the image");
+    if (r < 1 || r > kMaxRadius) return ctx->fail(INPAINT_INVALID_ARGUMENT, "patch_radius must be in 1..8");
+    if (rect.x0 > rect.x1 || rect.y0 > rect.y1) return ctx->fail(INPAINT_INVALID_ARGUMENT, "x0 > x1 or y0 > y1");
+    inpaint_rect R{std::max(rect.x0, 0), std::max(rect.y0, 0), std::min(rect.x1, d.W), std::min(rect.y1, d.H)};
+    int k[4];
+    kernel_rect(d.W, d.H, d.isect ? 0 : r, R, k);
+    if (k[2] <= k[0] || k[3] <= k[1]) return ctx->fail(INPAINT_NO_CANDIDATE, "no valid centre in the rect");
+    uint8_t *base = (uint8_t *)static_scratch(ctx->device);
+    if (!base) return ctx->fail(INPAINT_DEVICE, "the static scratch array has no device address on this device");
+    JobDev q = d;
+    q.rx0 = k[0];
+    q.ry0 = k[1];
+    q.rx1 = k[2];
+    q.ry1 = k[3];
+    const bool mfma = ctx->mfma && mfma_supported(r);
+    set_tiles(q, d.tile_rows, mfma ? r : 0);
+    if ((int64_t)q.ntx * q.nty > kStaticMaxTiles)
+        return ctx->fail(INPAINT_INVALID_ARGUMENT, "search rect needs more than " + std::to_string(kStaticMaxTiles) +
+                                                       " search tiles (the static scratch limit)");
+    q.qtgt = (TargetStage *)(base + kStaticStageOff);
+    q.qfrag = (MfmaFrags *)(base + kStaticFragOff);
+    q.partials = (uint64_t *)(base + kStaticPartialsOff);
+    uint64_t *dkey = (uint64_t *)(base + kStaticKeyOff);
+    hipStream_t s = ctx->stream;
+    HIP_OR_FAIL(ctx, launch_stage_query(q, tx, ty, r, s), "stage");
+    if (mfma)
         HIP_OR_FAIL(ctx, launch_search_mfma(q, true, r, q.rx0, q.ry0, q.rx1, q.ry1, q.ntx, q.nty, s), "search");
     else if (ctx->direct)
         HIP_OR_FAIL(ctx, launch_search_direct(q, true, r, q.rx0, q.ry0, q.rx1, q.ry1, q.tile_rows, q.ntx, q.nty, s),
@@ -914,6 +969,7 @@ struct inpaint_batch {
     std::string cache_path;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    int device = 0;           // device current at create (the workspace's)
     std::vector<inpaint_ctx *> slots;
     JobDev *d_slots = nullptr;
     JobDev *h_slots = nullptr;      // pinned staging of the slot table
