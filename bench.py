@@ -87,7 +87,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="hd", choices=["hd", "vga", "small", "batch", "serve", "sweep", "copy", "resume"])
     ap.add_argument("--jobs", type=int, default=32, help="serve: number of jobs")
-    ap.add_argument("--graph-iters", type=int, default=16, help="batch / serve: iterations per replay")
+    ap.add_argument("--graph-iters", type=int, default=16, help="batch / serve: iterations per step")
+    ap.add_argument("--batch-form", default="auto", choices=["auto", "persistent", "graph"],
+                    help="batch: form of the batch steps")
     ap.add_argument("--capacity", type=int, default=16, help="serve: batch slots")
     ap.add_argument("--budget-gb", type=float, default=4.0, help="serve: device memory budget")
     ap.add_argument("--patch", type=int, default=9)
@@ -355,83 +357,101 @@ def copy_bench(a):
 
 
 def batch_bench(a):
-    """64 images of uneven size: batched persistent form vs one after another."""
+    """64 images of uneven size: the batched forms vs one image after another."""
     import torch
     from paper_1403_4238_amd import binding as B
     from paper_1403_4238_amd import synth
     jobs = synth.batch()
     tune = os.environ.get("INPAINT_TUNE_CACHE")   # optional file that keeps the autotuner's choices
-
-    def make(form="plain"):
-        return [B.Inpainter(j.rgb, j.mask, j.patch_radius, form=form, iters_per_check=a.iters_per_check)
-                for j in jobs]
-
-    batch = B.Batch(capacity=len(jobs), graph_iters=a.graph_iters, autotune=True, tune_cache=tune)
-    # warm-up set: first step tunes the tile shape / grid and captures the graph
-    warm = make()
-    for c in warm:
-        batch.attach(c)
-    batch.step()
-    for c in warm:
-        batch.detach(c)
-        c.close()
-    del warm
-    ctxs = make()
-    for c in ctxs:
-        batch.attach(c)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    steps = 0
-    while batch.step() > 0:
-        steps += 1
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    iters = [c.progress()[0] for c in ctxs]
-    cands = [c.search_info()[1] for c in ctxs]
-    evals = sum(i * n for i, n in zip(iters, cands))
-    # parity with the stored oracle results, where present
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from _util import load_golden, log_sha256
-    checked = ok = 0
-    for i, (j, c) in enumerate(zip(jobs, ctxs)):
-        gold = load_golden(f"batch{i:02d}")
-        if gold is None:
-            continue
-        checked += 1
-        log = c.read_log(0, iters[i])
-        ok += (gold["input_sha256"] == j.sha256() and gold["log_sha256"] == log_sha256(log)
-               and gold["final_rgb_sha256"] == hashlib.sha256(c.read_image().tobytes()).hexdigest())
-    for c in ctxs:
-        batch.detach(c)
-        c.close()
-    del ctxs
-    # the plain form: each image alone, two launches + one host check per iteration
-    plain = {}
-    for form in ("plain", "stream"):
+
+    def make(form="plain", path="mfma"):
+        return [B.Inpainter(j.rgb, j.mask, j.patch_radius, form=form, iters_per_check=a.iters_per_check,
+                            path=path_id(path)) for j in jobs]
+
+    def batched(bform, path):
+        """Runs the whole batch in one form; returns (seconds, iterations, evals, steps, ok, checked)."""
+        batch = B.Batch(capacity=len(jobs), graph_iters=a.graph_iters, autotune=True, tune_cache=tune, form=bform)
+        # warm-up set: the first step plans (and, in the graph form, tunes and captures)
+        warm = make(path=path)
+        for c in warm:
+            batch.attach(c)
+        batch.step()
+        for c in warm:
+            batch.detach(c)
+            c.close()
+        del warm
+        ctxs = make(path=path)
+        for c in ctxs:
+            batch.attach(c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = 0
+        while batch.step() > 0:
+            steps += 1
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ran = batch.last_form()
+        iters = [c.progress()[0] for c in ctxs]
+        cands = [c.search_info()[1] for c in ctxs]
+        evals = sum(i * n for i, n in zip(iters, cands))
+        checked = ok = 0
+        for i, (j, c) in enumerate(zip(jobs, ctxs)):
+            gold = load_golden(f"batch{i:02d}")
+            if gold is None:
+                continue
+            checked += 1
+            log = c.read_log(0, iters[i])
+            ok += (gold["input_sha256"] == j.sha256() and gold["log_sha256"] == log_sha256(log)
+                   and gold["final_rgb_sha256"] == hashlib.sha256(c.read_image().tobytes()).hexdigest())
+        for c in ctxs:
+            batch.detach(c)
+            c.close()
+        batch.close()
+        return dict(seconds=dt, iters=iters, evals=evals, steps=steps + 1, ok=ok, checked=checked, form=ran)
+
+    head = batched(a.batch_form, a.path)
+    forms = {}
+    if not a.no_other_form:
+        for name, bform, path in (("persistent_simt", "persistent", "simt"), ("graph_simt", "graph", "simt"),
+                                  ("graph_mfma", "graph", "mfma")):
+            if (bform, path) == (head["form"], a.path):
+                continue
+            r = batched(bform, path)
+            forms[name] = {"ms": round(1000 * r["seconds"], 2), "patch_evals_per_s": round(r["evals"] / r["seconds"], 1),
+                           "parity": f"{r['ok']}/{r['checked']} bit-exact vs stored oracle", "form": r["form"]}
+    # one image after another: two launches + one host check per iteration
+    # (plain), or the search and commit launches enqueued ahead (stream)
+    one = {}
+    for form in ("plain", "stream", "persistent"):
         cs = make(form)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for c in cs:
             c.run()
         torch.cuda.synchronize()
-        plain[form] = time.perf_counter() - t1
+        one[form] = time.perf_counter() - t1
         for c in cs:
             c.close()
+    dt, evals = head["seconds"], head["evals"]
     line = {
         "metric": "masked-SSD patch evals/s (batch of 64 images, batched persistent form)",
         "value": round(evals / dt, 1), "unit": "patch evals/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": round(1000 * dt, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8 (SSD: u8 x u8 -> u32 exact; priority: f64)", "data": "synthetic (seeded)",
         "config": {"workload": "batch of 64 RGB u8 images 320x240..1280x720, 1-3 blobs covering 2-10%, "
-                               "9x9 patch, full search; one persistent search launch + one commit launch "
-                               f"per iteration for all images, hipGraph of {a.graph_iters} iterations, "
-                               "autotuned tiles",
-                   "images": len(jobs), "total_iterations": int(sum(iters)), "batch_steps": steps + 1},
+                               f"9x9 patch, full search, {a.path} search; batch form {head['form']} "
+                               f"({a.graph_iters} iterations per step)",
+                   "images": len(jobs), "total_iterations": int(sum(head["iters"])), "batch_steps": head["steps"],
+                   "max_iterations_per_image": int(max(head["iters"]))},
         "batched_ms": round(1000 * dt, 2),
+        "other_batch_forms": forms,
         "one_by_one": {f: {"ms": round(1000 * t, 2), "patch_evals_per_s": round(evals / t, 1)}
-                       for f, t in plain.items()},
-        "speedup_vs_plain": round(plain["plain"] / dt, 3),
-        "parity": f"{ok}/{checked} images bit-exact vs stored oracle",
+                       for f, t in one.items()},
+        "speedup_vs_plain": round(one["plain"] / dt, 3),
+        "speedup_vs_one_by_one_persistent": round(one["persistent"] / dt, 3),
+        "parity": f"{head['ok']}/{head['checked']} images bit-exact vs stored oracle",
     }
     print(json.dumps(line), flush=True)
 

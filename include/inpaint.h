@@ -316,17 +316,28 @@ const char *inpaint_last_error(const inpaint_ctx *ctx);
 
 /* ------------------------------------------------------------------ batch */
 
-/* Many images advanced together: each batch iteration runs, for every
- * attached unfinished image, one fill iteration.  The search runs as a
- * persistent kernel pulling (image, tile) items from a static work list; the
- * per-image front/priority/copy step runs one work-group per image.  G
- * iterations are captured once into a hipGraph and replayed. */
+/* Many images advanced together: each batch step runs, for every attached
+ * unfinished image, G fill iterations (the fill loop of Section 3 per image).
+ * Two forms:
+ *  - PERSISTENT (the default when it fits): one cooperative dispatch per
+ *    step and patch radius runs all G iterations of every image; one
+ *    work-group per image commits (front, priority, copy), every other
+ *    co-resident work-group searches (image, tile) items of whichever image
+ *    has a staged target.  Images of up to 64 tiles per search work-group.
+ *  - GRAPH: per iteration, a persistent search kernel over a static (image,
+ *    tile) work list, then one commit work-group per image; G iterations are
+ *    captured once into a hipGraph and replayed.  Tile shape and grid may be
+ *    autotuned. */
 typedef struct {
     int32_t capacity;        /* maximum attached contexts (slots), >= 1     */
     int32_t graph_iters;     /* G: iterations per replay, >= 1              */
     int32_t autotune;        /* 1 = time tile shapes and the persistent grid */
-                             /*   on first use, 0 = defaults                */
-    int32_t reserved;
+                             /*   of the graph form on first use, 0 = defaults */
+    int32_t form;            /* 0 = PERSISTENT when the attached images fit */
+                             /*   one dispatch, else GRAPH; or               */
+                             /*   INPAINT_FORM_GRAPH / INPAINT_FORM_PERSISTENT */
+                             /*   (a step that does not fit then fails with  */
+                             /*   INVALID_ARGUMENT)                          */
     const char *tune_cache;  /* JSON file caching autotuned choices, or NULL */
 } inpaint_batch_params;
 
@@ -347,6 +358,10 @@ int32_t inpaint_batch_detach(inpaint_batch *b, inpaint_ctx *ctx);
 /* Runs G iterations for every attached image and writes the number of
  * attached images still unfinished to *active.  Synchronises once. */
 int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active);
+
+/* The form (INPAINT_FORM_PERSISTENT or INPAINT_FORM_GRAPH) the last step
+ * ran in. */
+int32_t inpaint_batch_form(const inpaint_batch *b, int32_t *form);
 
 /* State of a slot as of the end of the last inpaint_batch_step:
  * 0 empty, 1 running, 2 finished (hole empty), 3 device error.  No device

@@ -49,7 +49,7 @@ class inpaint_params(ctypes.Structure):
 
 class inpaint_batch_params(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_int32), ("graph_iters", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("form", ctypes.c_int32),
                 ("tune_cache", ctypes.c_char_p)]
 
 
@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
         "inpaint_batch_attach": (i32, [vp, vp, P(i32)]),
         "inpaint_batch_detach": (i32, [vp, vp]),
         "inpaint_batch_step": (i32, [vp, i32, P(i64)]),
+        "inpaint_batch_form": (i32, [vp, P(i32)]),
         "inpaint_batch_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -309,8 +310,9 @@ class Batch:
     """Many contexts advanced together by the persistent, graph-replayed form."""
 
     def __init__(self, capacity: int, graph_iters: int = 8, autotune: bool = True,
-                 tune_cache: str | None = None, stream=None):
-        self.params = inpaint_batch_params(capacity, graph_iters, 1 if autotune else 0, 0,
+                 tune_cache: str | None = None, stream=None, form: str = "auto"):
+        fid = {"auto": 0, "graph": FORMS["graph"], "persistent": FORMS["persistent"]}[form]
+        self.params = inpaint_batch_params(capacity, graph_iters, 1 if autotune else 0, fid,
                                            tune_cache.encode() if tune_cache else None)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
@@ -349,6 +351,14 @@ class Batch:
         for k, v in list(self.members.items()):
             if v is job:
                 del self.members[k]
+
+    def last_form(self) -> str:
+        """Form the last step ran in: "persistent" or "graph"."""
+        out = ctypes.c_int32()
+        st = lib().inpaint_batch_form(self.h, ctypes.byref(out))
+        if st != OK:
+            raise InpaintError(st, "inpaint_batch_form")
+        return {v: k for k, v in FORMS.items()}[out.value]
 
     def step(self, G: int | None = None) -> int:
         active = ctypes.c_int64()

@@ -1750,10 +1750,11 @@ template <int R, int TB, int BW, bool LEAN>
 __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t epoch, CommitLds<R> &C) {
     Scratch &s = C.s;
     LdsStage<R> &L = C.L;
-    // The search groups build their MFMA operands themselves; the commit
-    // writes the fragments of the staged target once, at the end.
-    JobDev d = d0;
-    d.mfma = 0;
+    // The search groups build their MFMA operands themselves (the lean
+    // staging builds none); the commit writes the fragments of the staged
+    // target once, at the end.  d is used in place: a copy of it would live
+    // in scratch memory when d0 is not a kernel argument.
+    const JobDev &d = d0;
     bool staged = false;
     FillSync *sy = d.sync;
     if (threadIdx.x == 0) s.snap = load_snap(d.st, d.tgt);
@@ -1946,6 +1947,201 @@ __global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(
         fill_commit<R, 2, 4, false>(d, ntiles, n_iters, epoch, lds.c);
     else
         fill_search<R, kFillTileRows>(d, ntiles, epoch, lds.s);
+}
+
+// ---- batched persistent fill: many jobs in one cooperative dispatch -----
+//
+// Work-groups [0, n_commit) each commit one job (fill_commit, exactly as in
+// the single-job kernels, on that job's own records and slot words).  Every
+// other work-group is a search group owning a list of (job, tile) items; a
+// job's tiles are spread over many groups and a group's items come from
+// many jobs.  Wave 0 keeps one item per lane -- its job, tile and the job
+// iteration it scores next -- and polls all its items' go words at once.
+// The group then serves one ready item, taken round-robin: stage the tile
+// unless it is the one already in LDS, read the job's record, score, and
+// write the job's slot word of that tile.  So a search group never waits on
+// one job while another has work for it, and a job's iteration is scored by
+// whichever groups are free.  A group with a single item keeps its tile in
+// LDS for the whole dispatch, as the single-job kernels do.  Every wait is
+// bounded as there: committers time out on their slots and publish stop; a
+// search group gives up after kSpinLimit empty polls in a row.
+
+struct MultiPick {
+    int32_t pick;       // item to serve, -1: none ready
+    int32_t all_done;   // every item's job published stop
+    int32_t slot, tile;
+    uint32_t k;
+};
+
+// Wave 0: polls the go words of this group's items (lane i: item i) and
+// publishes the next ready item after `rot` (round-robin) in *pk.  my_k is
+// the job iteration lane i's item scores next; it advances for the item
+// picked.  The caller's barrier publishes *pk.
+__device__ __forceinline__ void multi_poll(const uint64_t *my_go, int my_slot, int my_tile, uint32_t &my_k,
+                                           bool &my_done, int rot, uint32_t epoch, MultiPick *pk) {
+    const int lane = threadIdx.x & 63;
+    bool ready = false;
+    if (!my_done) {
+        const uint64_t v = __hip_atomic_load(my_go, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ready = v == go_word(epoch, my_k + 1);
+        my_done = v == go_word(epoch, 0xffffffffu);
+    }
+    const uint64_t rb = __ballot(ready), db = __ballot(my_done);
+    const uint64_t hi = rb & (~0ull << rot);
+    const int pick = hi ? __builtin_ctzll(hi) : (rb ? __builtin_ctzll(rb) : -1);
+    if (pick >= 0) {
+        // the record this item reads was written back before its go word was
+        // released; order this group's record loads after the go load
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    if (lane == 0) {
+        pk->pick = pick;
+        pk->all_done = db == ~0ull;
+    }
+    if (lane == pick) {
+        pk->slot = my_slot;
+        pk->tile = my_tile;
+        pk->k = my_k;
+        my_k += 1;
+    }
+}
+
+// Scores item (job d, tile t) for iteration k of the MFMA form and reports
+// in the job's slot word.  restage: the tile in LDS is not this item's.
+template <int R>
+__device__ __forceinline__ void multi_serve_mfma(const JobDev &d, int t, uint32_t k, bool restage, SearchLdsMfma<R> &S,
+                                 uint32_t &vmask, bool &anyv) {
+    int tx0, ty0;
+    mtile::tile_origin<R>(d.rx0, d.ry0, d.ntx, t, &tx0, &ty0);
+    if (restage) {
+        vmask = mtile::stage_tile<R>(d, tx0, ty0, d.rx0, d.rx1, d.ry1, S.tile);
+        anyv = __syncthreads_or(vmask != 0);
+    }
+    uint64_t best = ~0ull;
+    if (anyv) {
+        const FillRec *rec = &d.sync->rec[t % kGoCopies];
+        mtile::build_patch<R>(
+            &S.ft,
+            [&](int sl) { return __hip_atomic_load(&rec->tpix[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); },
+            [&](int sl) {
+                return (__hip_atomic_load(&rec->mbits[sl >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >>
+                        (sl & 31)) & 1u;
+            });
+        __syncthreads();
+        mtile::build_tables<R>(&S.ft);
+        __syncthreads();
+        mtile::BFrags<R> b;
+        mtile::load_frags<R>(&S.ft, b);
+        best = tile::wave_min_u64(mtile::score_tile<R>(d, b, tx0, ty0, vmask, S.tile));
+        if ((threadIdx.x & 63) == 0) S.red[threadIdx.x >> 6] = best;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int w = 0; w < kSearchWaves; ++w) best = S.red[w] < best ? S.red[w] : best;
+    }
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&d.fslot[t], slot_word(best, slot_tag(k)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The same for the SIMT form.
+template <int R>
+__device__ __forceinline__ void multi_serve_simt(const JobDev &d, int t, uint32_t k, bool restage,
+                                 SearchLds<R, kFillTileRows> &S, uint32_t &vmask, bool &anyv) {
+    constexpr int NY = kFillTileRows;
+    int tx0, ty0;
+    tile::tile_origin<R, NY>(d.rx0, d.ry0, d.ntx, t, &tx0, &ty0);
+    if (restage) {
+        vmask = tile::stage_tile<R, NY>(d, tx0, ty0, d.rx1, d.ry1, S.tile);
+        anyv = __syncthreads_or(vmask != 0);
+    }
+    uint64_t best = ~0ull;
+    if (anyv) {
+        load_record<R>(&d.sync->rec[t % kGoCopies], &S.tgt);
+        __syncthreads();
+        const tile::LdsTarget view{&S.tgt};
+        best = tile::wave_min_u64(tile::score_tile<R, NY>(d, view, tx0, ty0, vmask, S.tile));
+        if ((threadIdx.x & 63) == 0) S.red[threadIdx.x >> 6] = best;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int w = 0; w < kSearchWaves; ++w) best = S.red[w] < best ? S.red[w] : best;
+    }
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&d.fslot[t], slot_word(best, slot_tag(k)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Search group w of a batched dispatch; serve(d, tile, k, restage, vmask,
+// anyv) scores one item.
+template <class Serve>
+__device__ __forceinline__ void multi_search(const MultiPlan &m, int w, uint32_t epoch, MultiPick *pk, Serve serve) {
+    const int i0 = m.first[w], ni = m.first[w + 1] - i0;   // 0 <= ni <= kMultiMaxItems (host-checked)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int my_slot = 0, my_tile = 0;
+    uint32_t my_k = 0;
+    bool my_done = true;
+    const uint64_t *my_go = nullptr;   // go word of the record this lane's item reads
+    if (wave == 0 && lane < ni) {
+        const WorkItem it = m.items[i0 + lane];
+        my_slot = it.slot;
+        my_tile = it.tile;
+        my_go = &m.slots[my_slot].sync->rec[my_tile % kGoCopies].go;
+        my_done = false;
+    }
+    uint32_t vmask = 0;
+    bool anyv = false;
+    int staged = -1;   // item whose tile is in LDS
+    int rot = 0;
+    for (uint32_t spin = 0; spin < kSpinLimit;) {
+        if (wave == 0) multi_poll(my_go, my_slot, my_tile, my_k, my_done, rot, epoch, pk);
+        __syncthreads();
+        const int pick = pk->pick;
+        if (pick < 0) {
+            if (pk->all_done) break;
+            ++spin;
+            __builtin_amdgcn_s_sleep(1);
+            __syncthreads();   // wave 0 rewrites *pk only after everyone read it
+            continue;
+        }
+        spin = 0;
+        rot = pick + 1 < ni ? pick + 1 : 0;
+        // (by value: the fields the search reads become scalar registers)
+        const JobDev d = m.slots[pk->slot];
+        serve(d, pk->tile, pk->k, staged != pick, vmask, anyv);
+        staged = pick;
+        __syncthreads();
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_fill_multi_mfma(
+    MultiPlan m, int n_iters, uint32_t epoch) {
+    __shared__ FillLdsMfma<R> lds;
+    __shared__ MultiPick pk;
+    if ((int)blockIdx.x < m.n_commit) {
+        // by value: held through a reference to device memory, the job's
+        // fields would stay live in vector registers (and spill)
+        const JobDev d = m.slots[m.commit[blockIdx.x]];
+        fill_commit<R, 8, 12, true>(d, d.ntx * d.nty, n_iters, epoch, lds.c);
+        return;
+    }
+    multi_search(m, (int)blockIdx.x - m.n_commit, epoch, &pk,
+                 [&](const JobDev &d, int t, uint32_t k, bool restage, uint32_t &vmask, bool &anyv)
+                     __attribute__((always_inline)) { multi_serve_mfma<R>(d, t, k, restage, lds.s, vmask, anyv); });
+}
+
+template <int R>
+__global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fill_multi(
+    MultiPlan m, int n_iters, uint32_t epoch) {
+    __shared__ FillLds<R, kFillTileRows> lds;
+    __shared__ MultiPick pk;
+    if ((int)blockIdx.x < m.n_commit) {
+        const JobDev d = m.slots[m.commit[blockIdx.x]];   // by value, see k_fill_multi_mfma
+        fill_commit<R, 2, 4, false>(d, d.ntx * d.nty, n_iters, epoch, lds.c);
+        return;
+    }
+    multi_search(m, (int)blockIdx.x - m.n_commit, epoch, &pk,
+                 [&](const JobDev &d, int t, uint32_t k, bool restage, uint32_t &vmask, bool &anyv)
+                     __attribute__((always_inline)) {
+                     multi_serve_simt<R>(d, t, k, restage, lds.s, vmask, anyv);
+                 });
 }
 
 template <int R, bool ISECT>
@@ -2142,6 +2338,46 @@ hipError_t launch_fill(const JobDev &d, int ntiles, int n_iters, uint32_t epoch,
     JobDev dd = d;
     void *args[] = {&dd, &ntiles, &n_iters, &epoch};
     return hipLaunchCooperativeKernel(f, dim3(fill_grid(ntiles)), dim3(kCommitThreads), args, 0, s);
+}
+
+static const void *fill_multi_kernel(bool mfma, int r) {
+    if (mfma) {
+        switch (r) {
+            case 1: return (const void *)k_fill_multi_mfma<1>;
+            case 2: return (const void *)k_fill_multi_mfma<2>;
+            case 3: return (const void *)k_fill_multi_mfma<3>;
+            case 4: return (const void *)k_fill_multi_mfma<4>;
+            case 5: return (const void *)k_fill_multi_mfma<5>;
+            case 6: return (const void *)k_fill_multi_mfma<6>;
+            default: return nullptr;
+        }
+    }
+    switch (r) {
+        case 1: return (const void *)k_fill_multi<1>;
+        case 2: return (const void *)k_fill_multi<2>;
+        case 3: return (const void *)k_fill_multi<3>;
+        case 4: return (const void *)k_fill_multi<4>;
+        case 5: return (const void *)k_fill_multi<5>;
+        case 6: return (const void *)k_fill_multi<6>;
+        case 7: return (const void *)k_fill_multi<7>;
+        case 8: return (const void *)k_fill_multi<8>;
+        default: return nullptr;
+    }
+}
+
+hipError_t multi_blocks_per_cu(bool mfma, int r, int *blocks) {
+    const void *f = fill_multi_kernel(mfma, r);
+    if (!f) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, f, kCommitThreads, 0);
+}
+
+hipError_t launch_fill_multi(const MultiPlan &m, bool mfma, int r, int grid, int n_iters, uint32_t epoch,
+                             hipStream_t s) {
+    const void *f = fill_multi_kernel(mfma, r);
+    if (!f || grid <= m.n_commit) return hipErrorInvalidValue;
+    MultiPlan mm = m;
+    void *args[] = {&mm, &n_iters, &epoch};
+    return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kCommitThreads), args, 0, s);
 }
 
 hipError_t launch_stage_query(const JobDev &d, int tx, int ty, int r, hipStream_t s) {

@@ -189,6 +189,20 @@ struct WorkItem {
     int32_t tile;
 };
 
+// Work of one batched persistent dispatch (k_fill_multi*): committer group
+// c < n_commit commits the job in slot commit[c]; search group w (block
+// n_commit + w) scores items [first[w], first[w + 1]) of `items`, at most
+// kMultiMaxItems of them.  Each slot's JobDev carries the tiling of the
+// dispatch's search form.
+constexpr int kMultiMaxItems = 64;
+struct MultiPlan {
+    const JobDev *slots;
+    const int32_t *commit;
+    const WorkItem *items;
+    const int32_t *first;
+    int32_t n_commit;
+};
+
 // ---- launchers (defined in the .hip files) ----
 hipError_t launch_init(const JobDev &d, const uint8_t *stage_rgb, int channels,
                        const uint8_t *stage_mask, uint8_t *hdist, uint32_t nonce, hipStream_t s);
@@ -233,6 +247,13 @@ hipError_t launch_search_batched(const JobDev *slots, const WorkItem *items, con
 hipError_t fill_blocks_per_cu(int r, bool mfma, int *blocks);
 int fill_grid(int ntiles);
 hipError_t launch_fill(const JobDev &d, int ntiles, int n_iters, uint32_t epoch, hipStream_t s);
+// Batched persistent fill: up to n_iters iterations of every job of the plan
+// (all of patch radius r) in one cooperative dispatch of `grid` = n_commit +
+// search groups.  MFMA: r <= 6, the int8-MFMA tiling; SIMT: the SIMT tiling
+// of kFillTileRows.
+hipError_t multi_blocks_per_cu(bool mfma, int r, int *blocks);
+hipError_t launch_fill_multi(const MultiPlan &m, bool mfma, int r, int grid, int n_iters, uint32_t epoch,
+                             hipStream_t s);
 
 inline int search_tile_h(int tile_rows) { return kSearchWaves * tile_rows; }
 

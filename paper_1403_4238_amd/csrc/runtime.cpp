@@ -30,6 +30,7 @@ thread_local std::string g_create_error;
 
 constexpr uint64_t kAlign = 256;
 constexpr int kDefaultTileRows = 8;
+constexpr int kMaxGroups = 4096;   // work-groups of a persistent dispatch (co-resident: <= 4 per CU)
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -39,6 +40,17 @@ std::atomic<uint32_t> g_nonce{0};
 uint32_t next_nonce() {
     uint32_t v;
     do v = (g_nonce.fetch_add(1) + 1) * 2654435761u;
+    while (v == 0);
+    return v;
+}
+
+// Launch epochs of persistent dispatches, unique in the process: a job's
+// records and slot words may hold values from any earlier dispatch that ran
+// it (alone or in a batch), and only the current epoch's go words count.
+std::atomic<uint32_t> g_epoch{0};
+uint32_t next_epoch() {
+    uint32_t v;
+    do v = g_epoch.fetch_add(1) + 1;
     while (v == 0);
     return v;
 }
@@ -53,7 +65,7 @@ bool sealed(const InitInfo &info, uint32_t nonce, uint32_t blocks) {
 
 struct Layout {
     uint64_t img, gray, hole, hole0, vrad, conf, pcd, blk, partials, tgt, qtgt, frag, qfrag, srcw, srcq, srcp, vradp, hdist, st,
-        sync, fslot, info, key, log, total;
+        sync, fslot, info, key, mplan, log, total;
     int64_t log_cap;
     int max_tiles;
 };
@@ -103,6 +115,9 @@ Layout make_layout(int W, int H, const inpaint_params &p) {
     L.fslot = take(8 * (uint64_t)L.max_tiles);
     L.info = take(sizeof(InitInfo));
     L.key = take(8);
+    // one-job plan of the batched persistent dispatch (images whose tiles
+    // outnumber the co-resident work-groups): slot, committer id, items, first
+    L.mplan = take(sizeof(JobDev) + 256 + sizeof(WorkItem) * (uint64_t)L.max_tiles + 4ull * (kMaxGroups + 1));
     L.log_cap = log_capacity(W, H, p);
     L.log = take(sizeof(StepRec) * (uint64_t)L.log_cap);
     L.total = off;
@@ -150,7 +165,9 @@ struct inpaint_ctx {
     bool mfma = false;        // search on the matrix cores
     bool direct = false;      // SIMT search without LDS staging
     int32_t run_form = INPAINT_FORM_PLAIN;   // form inpaint_run uses
-    uint32_t epoch = 0;       // persistent dispatches so far
+    bool multi = false;       // persistent form through the batched dispatch (tiles > co-resident groups)
+    int multi_grid = 0;       // its grid
+    MultiPlan mplan{};        // its one-job plan (in the workspace)
     int32_t sticky = 0;
     std::string err;
     IterState *h_state = nullptr;   // pinned mirror of the device state
@@ -294,6 +311,66 @@ static bool persistent_fits(const inpaint_ctx *c) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
     if (fill_blocks_per_cu(d.r, c->mfma, &per_cu) != hipSuccess) return false;
     return (int64_t)fill_grid(ntiles) <= (int64_t)per_cu * cus;
+}
+
+// Search items of the batched persistent dispatch spread round-robin over
+// n_search groups: item i goes to group i % n_search, so a job's tiles land
+// on different groups.  Writes items grouped by search group and the CSR
+// offsets first[0..n_search].
+static void spread_items(const std::vector<WorkItem> &all, int n_search, std::vector<WorkItem> *items,
+                         std::vector<int32_t> *first) {
+    first->assign(n_search + 1, 0);
+    for (size_t i = 0; i < all.size(); ++i) (*first)[i % n_search + 1] += 1;
+    for (int w = 0; w < n_search; ++w) (*first)[w + 1] += (*first)[w];
+    items->resize(all.size());
+    std::vector<int32_t> pos(first->begin(), first->end() - 1);
+    for (size_t i = 0; i < all.size(); ++i) (*items)[pos[i % n_search]++] = all[i];
+}
+
+// Co-resident work-groups of the batched persistent kernel on this device
+// (0 if it cannot run: no cooperative launch).
+static int multi_capacity(bool mfma, int r) {
+    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (multi_blocks_per_cu(mfma, r, &per_cu) != hipSuccess) return 0;
+    return std::min(per_cu * cus, kMaxGroups);
+}
+
+// The persistent form for a job whose tiles outnumber the co-resident
+// work-groups: the batched dispatch with this one job, its tiles spread over
+// every other co-resident group.  Builds and uploads the plan into the
+// workspace.  Returns false when that does not fit either.
+static bool setup_multi(inpaint_ctx *c) {
+    const JobDev &d = c->d;
+    const int ntiles = d.ntx * d.nty;
+    if (c->direct || d.policy != INPAINT_SOURCE_ORIGINAL || d.isect) return false;
+    if (!c->mfma && d.tile_rows != kFillTileRows) return false;
+    if (ntiles <= 0 || ntiles > 32 * kCommitThreads || ntiles > c->L.max_tiles) return false;
+    if ((int64_t)d.W * d.H > (1ll << kSlotIndexBits)) return false;
+    const int cap = multi_capacity(c->mfma, d.r);
+    const int n_search = cap - 1;
+    if (n_search < 1 || ntiles > (int64_t)n_search * kMultiMaxItems) return false;
+    std::vector<WorkItem> all(ntiles), items;
+    std::vector<int32_t> first;
+    for (int t = 0; t < ntiles; ++t) all[t] = WorkItem{0, t};
+    spread_items(all, n_search, &items, &first);
+    uint8_t *base = c->ws + c->L.mplan;
+    JobDev *slot = (JobDev *)base;
+    int32_t *commit = (int32_t *)(base + sizeof(JobDev));
+    WorkItem *ditems = (WorkItem *)(base + sizeof(JobDev) + 256);
+    int32_t *dfirst = (int32_t *)(base + sizeof(JobDev) + 256 + sizeof(WorkItem) * (uint64_t)c->L.max_tiles);
+    const int32_t zero = 0;
+    hipError_t e = hipMemcpy(slot, &d, sizeof(JobDev), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(commit, &zero, 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ditems, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dfirst, first.data(), 4 * first.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return false;
+    c->mplan = MultiPlan{slot, commit, ditems, dfirst, 1};
+    c->multi_grid = 1 + n_search;
+    c->multi = true;
+    return true;
 }
 
 int32_t inpaint_workspace_bytes(int32_t W, int32_t H, const inpaint_params *p, uint64_t *bytes) {
@@ -494,7 +571,8 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     if (!c->h_state->pending && !c->h_state->done)
         return create_fail(c, INPAINT_DEVICE, "the first selection did not run (no error was reported)");
     c->run_form = p->form;
-    if (p->form == INPAINT_FORM_PERSISTENT && !persistent_fits(c)) c->run_form = INPAINT_FORM_STREAM;
+    if (p->form == INPAINT_FORM_PERSISTENT && !persistent_fits(c) && !setup_multi(c))
+        c->run_form = INPAINT_FORM_STREAM;
     *out = c;
     return INPAINT_OK;
 }
@@ -706,7 +784,11 @@ int32_t inpaint_run(inpaint_ctx *ctx, int64_t max_iters, int64_t *iters_done, in
             const int n = (int)std::min<int64_t>(G, limit - before);
             const JobDev &d = ctx->d;
             if (ctx->prof) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev0[0], s), "event");
-            HIP_OR_FAIL(ctx, launch_fill(d, d.ntx * d.nty, n, ++ctx->epoch, s), "persistent launch");
+            if (ctx->multi)
+                HIP_OR_FAIL(ctx, launch_fill_multi(ctx->mplan, ctx->mfma, d.r, ctx->multi_grid, n, next_epoch(), s),
+                            "persistent launch");
+            else
+                HIP_OR_FAIL(ctx, launch_fill(d, d.ntx * d.nty, n, next_epoch(), s), "persistent launch");
             if (ctx->prof) HIP_OR_FAIL(ctx, hipEventRecord(ctx->ev1[0], s), "event");
         } else {
             // Stop enqueueing at the iteration limit; past the end of the
@@ -964,6 +1046,19 @@ void write_cache(const char *path, const std::map<std::string, TuneChoice> &m) {
 
 }  // namespace
 
+// Device work tables of the batched persistent dispatch of one (search
+// form, radius) group, grown as needed.
+struct MultiBuf {
+    int32_t *commit = nullptr;
+    WorkItem *items = nullptr;
+    int32_t *first = nullptr;
+    size_t cap_commit = 0, cap_items = 0, cap_first = 0;
+    MultiPlan plan{};
+    int grid = 0;
+    bool mfma = false;
+    int r = 0;
+};
+
 struct inpaint_batch {
     inpaint_batch_params bp{};
     std::string cache_path;
@@ -981,6 +1076,13 @@ struct inpaint_batch {
     int graph_n = 0;
     std::string graph_sig;
     int cu_count = 256;
+    // batched persistent form
+    std::vector<MultiBuf> mbufs;   // one per (form, radius) group of running jobs
+    std::string multi_sig;         // running slots the uploaded plans were built for
+    std::string nofit_sig;         // running slots that did not fit one dispatch
+    std::map<std::pair<int, int>, int> mcap;   // co-resident groups per (form, radius)
+    int desc_form = -1;            // form the slot table's tilings were built for
+    int32_t last_form = INPAINT_FORM_GRAPH;
 };
 
 namespace {
@@ -1127,12 +1229,122 @@ hipError_t autotune_group(inpaint_batch *b, int r, RadiusGroup &g, std::map<std:
     return rebuild(b);
 }
 
+template <class T>
+hipError_t grow(T **p, size_t *cap, size_t n) {
+    if (*p && *cap >= n) return hipSuccess;
+    if (*p) hipFree(*p);
+    *p = nullptr;
+    *cap = std::max<size_t>(n, 64) * 2;
+    return hipMalloc((void **)p, *cap * sizeof(T));
+}
+
+bool multi_form(const inpaint_ctx *c) { return c->mfma && mfma_supported(c->d.r); }
+
+// Plans the batched persistent dispatches of the running jobs: one per
+// (search form, radius) group, its committers first, then every remaining
+// co-resident work-group searching.  Uploads the slot table with each job's
+// persistent tiling.  *fits = false when a group does not fit one dispatch
+// (the batch then steps in the graph form).  max_items: search items per
+// search group allowed (1: every tile stays in LDS for the whole dispatch).
+hipError_t plan_multi(inpaint_batch *b, int max_items, bool *fits) {
+    *fits = false;
+    const int32_t *state = (const int32_t *)(b->h_active + 1);
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    std::string sig = std::to_string(max_items) + "/";
+    for (size_t i = 0; i < b->slots.size(); ++i) {
+        const inpaint_ctx *c = b->slots[i];
+        if (c && state[i] == INPAINT_SLOT_RUNNING) {
+            groups[{multi_form(c) ? 1 : 0, c->d.r}].push_back((int)i);
+            sig += std::to_string(i) + ":" + std::to_string((uintptr_t)c) + ",";
+        }
+    }
+    if (!b->dirty && b->desc_form == INPAINT_FORM_PERSISTENT && sig == b->multi_sig) {
+        *fits = true;
+        return hipSuccess;
+    }
+    if (!b->dirty && sig == b->nofit_sig) return hipSuccess;
+    // the slot table with each job's persistent tiling, and the fit check,
+    // before anything is uploaded
+    std::vector<JobDev> desc(b->slots.size());
+    for (size_t i = 0; i < b->slots.size(); ++i) {
+        const inpaint_ctx *c = b->slots[i];
+        if (!c) continue;
+        desc[i] = c->d;
+        set_tiles(desc[i], multi_form(c) ? kMfmaTileRows : kFillTileRows, multi_form(c) ? c->d.r : 0);
+    }
+    struct Plan {
+        bool mfma;
+        int r, n_search;
+        std::vector<int> jobs;
+        std::vector<WorkItem> all;
+    };
+    std::vector<Plan> plans;
+    for (auto &kv : groups) {
+        Plan pl{kv.first.first != 0, kv.first.second, 0, kv.second, {}};
+        auto it = b->mcap.find(kv.first);
+        const int cap = it != b->mcap.end() ? it->second : (b->mcap[kv.first] = multi_capacity(pl.mfma, pl.r));
+        const int n_commit = (int)pl.jobs.size();
+        pl.n_search = cap - n_commit;
+        for (int slot : pl.jobs) {
+            const JobDev &d = desc[slot];
+            const int nt = d.ntx * d.nty;
+            if (nt > 32 * kCommitThreads || (int64_t)d.W * d.H > (1ll << kSlotIndexBits)) {
+                b->nofit_sig = sig;
+                return hipSuccess;
+            }
+            for (int t = 0; t < nt; ++t) pl.all.push_back(WorkItem{slot, t});
+        }
+        if (n_commit > cap / 2 || pl.n_search < 1 || (int64_t)pl.all.size() > (int64_t)pl.n_search * max_items) {
+            b->nofit_sig = sig;
+            return hipSuccess;
+        }
+        plans.push_back(std::move(pl));
+    }
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < b->slots.size() && e == hipSuccess; ++i) {
+        if (!b->slots[i]) continue;
+        b->h_slots[i] = desc[i];
+        e = upload_slot(b, (int)i);
+    }
+    if (e != hipSuccess) return e;
+    b->desc_form = INPAINT_FORM_PERSISTENT;
+    b->graph_sig.clear();   // the graph form rebuilds its tilings
+    b->mbufs.resize(plans.size());
+    for (size_t gi = 0; gi < plans.size(); ++gi) {
+        const Plan &pl = plans[gi];
+        MultiBuf &m = b->mbufs[gi];
+        m.mfma = pl.mfma;
+        m.r = pl.r;
+        std::vector<WorkItem> items;
+        std::vector<int32_t> first;
+        spread_items(pl.all, pl.n_search, &items, &first);
+        e = grow(&m.commit, &m.cap_commit, pl.jobs.size());
+        if (e == hipSuccess) e = grow(&m.items, &m.cap_items, items.size());
+        if (e == hipSuccess) e = grow(&m.first, &m.cap_first, first.size());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(m.commit, pl.jobs.data(), 4 * pl.jobs.size(), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(m.items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(m.first, first.data(), 4 * first.size(), hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);   // host vectors go out of scope
+        if (e != hipSuccess) return e;
+        m.plan = MultiPlan{b->d_slots, m.commit, m.items, m.first, (int32_t)pl.jobs.size()};
+        m.grid = (int)pl.jobs.size() + pl.n_search;
+    }
+    b->multi_sig = sig;
+    *fits = true;
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
 
 int32_t inpaint_batch_create(const inpaint_batch_params *bp, void *hip_stream, inpaint_batch **out) {
     if (!bp || !out || bp->capacity < 1 || bp->graph_iters < 1) return INPAINT_INVALID_ARGUMENT;
+    if (bp->form != 0 && bp->form != INPAINT_FORM_GRAPH && bp->form != INPAINT_FORM_PERSISTENT)
+        return INPAINT_INVALID_ARGUMENT;
     inpaint_batch *b = new (std::nothrow) inpaint_batch();
     if (!b) return INPAINT_OUT_OF_MEMORY;
     b->bp = *bp;
@@ -1199,11 +1411,56 @@ int32_t inpaint_batch_detach(inpaint_batch *b, inpaint_ctx *ctx) {
     return INPAINT_OK;
 }
 
+// One batch step in the batched persistent form: every planned group runs G
+// iterations of its jobs in one cooperative dispatch.
+static hipError_t step_multi(inpaint_batch *b, int32_t G) {
+    for (const MultiBuf &m : b->mbufs) {
+        hipError_t e = launch_fill_multi(m.plan, m.mfma, m.r, m.grid, G, next_epoch(), b->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static int32_t finish_step(inpaint_batch *b, int64_t *active) {
+    const int ns = (int)b->slots.size();
+    hipError_t e = launch_count_active(b->d_slots, ns, b->d_active, (int32_t *)(b->d_active + 1), b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->h_active, b->d_active, sizeof(int64_t) + sizeof(int32_t) * ns, hipMemcpyDeviceToHost,
+                           b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return INPAINT_DEVICE;
+    if (active) *active = *b->h_active;
+    return INPAINT_OK;
+}
+
 int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active) {
     if (!b || G < 1) return INPAINT_INVALID_ARGUMENT;
     hipError_t e = hipSuccess;
+    if (b->bp.form != INPAINT_FORM_GRAPH) {
+        // AUTO takes the persistent form only while every search tile of
+        // the running images can stay in LDS for the whole dispatch: with
+        // more tiles than search groups the tiles are re-staged for every
+        // target, and the graph form's many small search work-groups hide
+        // that latency better.  So a large batch starts in the graph form
+        // and its tail, when few images are left, runs persistent.
+        bool fits = false;
+        e = plan_multi(b, b->bp.form == INPAINT_FORM_PERSISTENT ? kMultiMaxItems : 1, &fits);
+        if (e != hipSuccess) return INPAINT_DEVICE;
+        if (fits) {
+            b->dirty = false;
+            b->last_form = INPAINT_FORM_PERSISTENT;
+            e = step_multi(b, G);
+            if (e != hipSuccess) return INPAINT_DEVICE;
+            return finish_step(b, active);
+        }
+        if (b->bp.form == INPAINT_FORM_PERSISTENT)
+            return INPAINT_INVALID_ARGUMENT;   // required, but the jobs do not fit one dispatch
+    }
+    b->last_form = INPAINT_FORM_GRAPH;
+    if (b->desc_form != INPAINT_FORM_GRAPH) b->dirty = true;
     if (b->dirty) e = rebuild(b);
     if (e != hipSuccess) return INPAINT_DEVICE;
+    b->desc_form = INPAINT_FORM_GRAPH;
     if (b->bp.autotune) {
         std::map<std::string, TuneChoice> cache;
         bool loaded = false, changed = false;
@@ -1239,15 +1496,13 @@ int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active) {
         b->graph_n = G;
     }
     e = hipGraphLaunch(b->graph, b->stream);
-    const int ns = (int)b->slots.size();
-    if (e == hipSuccess)
-        e = launch_count_active(b->d_slots, ns, b->d_active, (int32_t *)(b->d_active + 1), b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->h_active, b->d_active, sizeof(int64_t) + sizeof(int32_t) * ns, hipMemcpyDeviceToHost,
-                           b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return INPAINT_DEVICE;
-    if (active) *active = *b->h_active;
+    return finish_step(b, active);
+}
+
+int32_t inpaint_batch_form(const inpaint_batch *b, int32_t *form) {
+    if (!b || !form) return INPAINT_INVALID_ARGUMENT;
+    *form = b->last_form;
     return INPAINT_OK;
 }
 
@@ -1263,6 +1518,11 @@ int32_t inpaint_batch_destroy(inpaint_batch *b) {
         if (c) c->batch = nullptr;
     if (b->stream) hipStreamSynchronize(b->stream);
     if (b->graph) hipGraphExecDestroy(b->graph);
+    for (MultiBuf &m : b->mbufs) {
+        if (m.commit) hipFree(m.commit);
+        if (m.items) hipFree(m.items);
+        if (m.first) hipFree(m.first);
+    }
     for (auto &kv : b->groups) {
         if (kv.second.d_items) hipFree(kv.second.d_items);
         if (kv.second.d_n) hipFree(kv.second.d_n);

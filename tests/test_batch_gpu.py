@@ -36,25 +36,29 @@ def _oracle_result(job):
     return log, o.read()[0]
 
 
-@pytest.mark.parametrize("G,autotune", [(4, False), (7, True)])
-def test_batch_equals_alone(tmp_path, G, autotune):
+@pytest.mark.parametrize("G,autotune,form,path", [(4, False, "graph", "simt"), (7, True, "graph", "simt"),
+                                                   (5, False, "persistent", "simt"),
+                                                   (6, False, "persistent", "mfma")])
+def test_batch_equals_alone(tmp_path, G, autotune, form, path):
     jobs = _mixed_jobs()
     cache = str(tmp_path / "tune.json")
-    batch = B.Batch(capacity=len(jobs) + 2, graph_iters=G, autotune=autotune, tune_cache=cache)
-    ctxs = [B.Inpainter(j.rgb, j.mask, j.patch_radius) for j in jobs]
+    batch = B.Batch(capacity=len(jobs) + 2, graph_iters=G, autotune=autotune, tune_cache=cache, form=form)
+    pid = B.PATH_MFMA if path == "mfma" else B.PATH_SIMT
+    ctxs = [B.Inpainter(j.rgb, j.mask, j.patch_radius, path=pid) for j in jobs]
     for c in ctxs:
         batch.attach(c)
     steps = 0
     while batch.step() > 0:
         steps += 1
         assert steps < 10_000
+    assert batch.last_form() == form
     for j, c in zip(jobs, ctxs):
         want_log, want_img = _oracle_result(j)
         got = c.read_log(0, len(want_log))
         assert_logs_equal(got, want_log, j.name)
         assert c.remaining() == 0
         assert (c.read_image() == want_img).all(), j.name
-    if autotune:
+    if autotune and form == "graph":
         assert os.path.exists(cache)
         # a second batch picks its choices from the cache and still agrees
         b2 = B.Batch(capacity=2, graph_iters=G, autotune=True, tune_cache=cache)
@@ -66,9 +70,10 @@ def test_batch_equals_alone(tmp_path, G, autotune):
         assert_logs_equal(c2.read_log(0, len(want_log)), want_log, "cached tune")
 
 
-def test_attach_detach_mid_run():
+@pytest.mark.parametrize("form", ["graph", "persistent"])
+def test_attach_detach_mid_run(form):
     jobs = _mixed_jobs()
-    batch = B.Batch(capacity=4, graph_iters=3, autotune=False)
+    batch = B.Batch(capacity=4, graph_iters=3, autotune=False, form=form)
     ctxs = [B.Inpainter(j.rgb, j.mask, j.patch_radius) for j in jobs]
     batch.attach(ctxs[0])
     batch.attach(ctxs[1])
@@ -109,25 +114,31 @@ def test_batch_of_vga_sized_images_prefix():
         assert_logs_equal(c.read_log(0, 10), want, j.name)
 
 
-def test_batch_of_64_full_size_matches_stored_oracle(tmp_path):
+@pytest.mark.parametrize("form,path", [("persistent", "mfma"), ("persistent", "simt"), ("graph", "simt")])
+def test_batch_of_64_full_size_matches_stored_oracle(tmp_path, form, path):
     # The seeded 64-image batch (320x240 .. 1280x720, 1-3 blobs covering
-    # 2-10%, 9x9 patch, full search), run to the end in the batched form with
-    # the autotuner on and hipGraph replays of 16 iterations: every image's
-    # whole fill log and final image equal its stored oracle result.
+    # 2-10%, 9x9 patch, full search), run to the end with 16 iterations per
+    # step: in the batched persistent form (one cooperative dispatch per
+    # step advances every image) on either search path, and in the graph
+    # form with the autotuner on.  Every image's whole fill log and final
+    # image equal its stored oracle result.
     from _util import assert_matches_golden, load_golden
     jobs = synth.batch()
     golds = [load_golden(f"batch{i:02d}") for i in range(len(jobs))]
     assert all(g is not None for g in golds), "stored oracle results missing"
     for j, g in zip(jobs, golds):
         assert g["input_sha256"] == j.sha256(), j.name
-    batch = B.Batch(capacity=len(jobs), graph_iters=16, autotune=True, tune_cache=str(tmp_path / "tune.json"))
-    ctxs = [B.Inpainter(j.rgb, j.mask, j.patch_radius) for j in jobs]
+    batch = B.Batch(capacity=len(jobs), graph_iters=16, autotune=True, tune_cache=str(tmp_path / "tune.json"),
+                    form=form)
+    pid = B.PATH_MFMA if path == "mfma" else B.PATH_SIMT
+    ctxs = [B.Inpainter(j.rgb, j.mask, j.patch_radius, path=pid) for j in jobs]
     for c in ctxs:
         batch.attach(c)
     steps = 0
     while batch.step() > 0:
         steps += 1
         assert steps < 2000
+    assert batch.last_form() == form
     for j, g, c in zip(jobs, golds, ctxs):
         assert c.remaining() == 0, j.name
         assert_matches_golden(g, c.read_log(0, g["iterations"]), c.read_image(), j.name)

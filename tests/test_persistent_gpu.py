@@ -133,3 +133,22 @@ def test_hd_full_run_matches_stored_oracle(key, path):
     assert_matches_golden(gold, log, g.read_image(), f"{key} persistent {path}")
     if key == "hd9":
         assert g.run_form() == "persistent"
+
+
+@pytest.mark.parametrize("path", ["mfma", "simt"])
+def test_persistent_above_coresident_tiles_matches_stored_oracle(path):
+    # 1992x1221, 7x7 patch: more search tiles (640 MFMA / 1248 SIMT) than
+    # work-groups that can be co-resident with one tile each, so the
+    # persistent form spreads the tiles over the batched dispatch's search
+    # groups (several tiles per group) instead of falling back to the stream
+    # form.  The whole removal equals the stored oracle result.
+    from _util import assert_matches_golden, load_golden
+    job = synth.serving()[0]
+    gold = load_golden("serve00")
+    assert gold is not None and gold["input_sha256"] == job.sha256()
+    g = B.Inpainter(job.rgb, job.mask, job.patch_radius, form="persistent", iters_per_check=64,
+                    path=B.PATH_MFMA if path == "mfma" else B.PATH_SIMT)
+    assert g.run_form() == "persistent"
+    st, n, log = g.run(log_cap=gold["iterations"] + 8)
+    assert st == B.DONE
+    assert_matches_golden(gold, log, g.read_image(), f"{job.name} {path}")

@@ -61,3 +61,34 @@ def test_invalid_job_is_isolated():
     recs = srv.run(jobs)
     assert [r.status for r in recs].count("failed") == 1 and recs[2].status == "failed"
     assert all(r.status == "done" for k, r in enumerate(recs) if k != 2)
+
+
+def test_serving_workload_full_size():
+    # The seeded serving workload at its stated size: 128 Poisson arrivals
+    # (20 jobs/s), images 256x256 .. 2048x1536, holes 1-10% in 1-3 blobs,
+    # patches 7/9/11, full search, 16 slots under a 4 GiB workspace budget.
+    # The first 16 jobs equal their stored oracle results; every served job
+    # equals the same job run alone.
+    import hashlib
+    from _util import assert_matches_golden, load_golden, log_sha256
+    jobs = synth.serving()
+    golds = [load_golden(f"serve{i:02d}") for i in range(16)]
+    assert all(g is not None for g in golds), "stored oracle results missing"
+    eng = serve.GpuEngine(capacity=16, graph_iters=16, autotune=True)
+    srv = serve.Server(eng, 4 << 30, 16, graph_iters=16)
+    recs = srv.run(jobs)
+    assert all(r.status == "done" for r in recs), [(r.name, r.status, r.error) for r in recs if r.status != "done"]
+    assert srv.peak_active >= 2 and srv.peak_used <= 4 << 30
+    s = serve.summarize(recs)
+    assert s["completed"] == len(jobs) and s["p99_latency_ms"] >= s["p50_latency_ms"] > 0
+    for j, g, r in zip(jobs, golds, recs):
+        assert g["input_sha256"] == j.sha256(), j.name
+        assert_matches_golden(g, r.result["log"], r.result["image"], j.name)
+    for j, r in zip(jobs, recs):
+        alone = B.Inpainter(j.rgb, j.mask, j.patch_radius, log_capacity=int(j.mask.sum()))
+        st, n, log = alone.run(log_cap=int(j.mask.sum()))
+        assert st == B.DONE and n == len(r.result["log"]), j.name
+        assert log_sha256(log) == log_sha256(r.result["log"]), j.name + ": log differs from the job alone"
+        assert hashlib.sha256(alone.read_image().tobytes()).digest() == \
+            hashlib.sha256(r.result["image"].tobytes()).digest(), j.name + ": image differs from the job alone"
+        alone.close()
