@@ -86,7 +86,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="hd", choices=["hd", "vga", "small", "batch", "serve", "sweep", "copy", "resume"])
-    ap.add_argument("--jobs", type=int, default=32, help="serve: number of jobs")
+    ap.add_argument("--jobs", type=int, default=128, help="serve: number of jobs")
+    ap.add_argument("--workers", type=int, default=1, help="serve: admission worker threads (0: on the loop)")
     ap.add_argument("--graph-iters", type=int, default=16, help="batch / serve: iterations per step")
     ap.add_argument("--batch-form", default="auto", choices=["auto", "persistent", "graph"],
                     help="batch: form of the batch steps")
@@ -461,12 +462,15 @@ def serve_bench(a):
     import torch
     from paper_1403_4238_amd import binding as B
     from paper_1403_4238_amd import serve, synth
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from _util import load_golden, log_sha256
     jobs = synth.serving(n=a.jobs)
     budget = int(a.budget_gb * (1 << 30))
 
-    def run(js):
-        eng = serve.GpuEngine(capacity=a.capacity, graph_iters=a.graph_iters, autotune=True, log=False)
-        srv = serve.Server(eng, budget, a.capacity, a.graph_iters, keep_results=True)
+    def run(js, keep=False):
+        eng = serve.GpuEngine(capacity=a.capacity, graph_iters=a.graph_iters, autotune=True, log=keep,
+                              path=a.path)
+        srv = serve.Server(eng, budget, a.capacity, a.graph_iters, keep_results=True, workers=a.workers)
         torch.cuda.synchronize()
         recs = srv.run(js)
         torch.cuda.synchronize()
@@ -478,16 +482,47 @@ def serve_bench(a):
     srv_sat, recs_sat = run(sat_jobs)
     sat = serve.summarize(recs_sat)
     rate = 0.7 * sat["jobs_per_s"]
-    srv_p, recs_p = run(synth.rescaled_arrivals(jobs, rate))
+    srv_p, recs_p = run(synth.rescaled_arrivals(jobs, rate), keep=True)
     poisson = serve.summarize(recs_p)
-    # each served image equals the same job run alone (first jobs)
-    same = 0
-    n_check = min(4, len(jobs))
-    for j, r in zip(jobs[:n_check], recs_p[:n_check]):
-        alone = B.Inpainter(j.rgb, j.mask, j.patch_radius, log_capacity=0)
-        alone.run()
-        same += bool((alone.read_image() == r.result["image"]).all())
+    # the workload's own arrival rate (fixed)
+    srv_f, recs_f = run(jobs)
+    fixed = serve.summarize(recs_f)
+    # every served job equals the same job run alone; the first ones also
+    # equal their stored oracle results
+    same = gold_ok = gold_n = 0
+    differ = []
+
+    def alone_run(j, form):
+        alone = B.Inpainter(j.rgb, j.mask, j.patch_radius, form=form, iters_per_check=256,
+                            log_capacity=int(j.mask.sum()),
+                            path=B.PATH_MFMA if j.patch_radius <= 6 else B.PATH_SIMT)
+        st, n, log = alone.run(log_cap=int(j.mask.sum()))
+        img = alone.read_image()
         alone.close()
+        return log, img
+
+    for i, (j, r) in enumerate(zip(jobs, recs_p)):
+        log, img = alone_run(j, "persistent")
+        ok = bool(r.status == "done" and (img == r.result["image"]).all()
+                  and log_sha256(log) == log_sha256(r.result["log"]))
+        same += ok
+        if not ok and r.status == "done":
+            # where the two differ, and which side a third run (stream form) takes
+            from _util import log_matrix
+            a_m, b_m = log_matrix(log), log_matrix(r.result["log"])
+            n = min(len(a_m), len(b_m))
+            dv = np.nonzero((a_m[:n] != b_m[:n]).any(axis=1))[0]
+            log3, img3 = alone_run(j, "stream")
+            differ.append({"job": i, "name": j.name, "iters_alone": len(a_m), "iters_served": len(b_m),
+                           "first_divergence": int(dv[0]) if len(dv) else None,
+                           "image_equal": bool((img == r.result["image"]).all()),
+                           "stream_equals_alone": bool(log_sha256(log3) == log_sha256(log)),
+                           "stream_equals_served": bool(log_sha256(log3) == log_sha256(r.result["log"]))})
+        gold = load_golden(f"serve{i:02d}")
+        if gold is not None and r.status == "done":
+            gold_n += 1
+            gold_ok += (gold["input_sha256"] == j.sha256() and gold["log_sha256"] == log_sha256(r.result["log"])
+                        and gold["final_rgb_sha256"] == hashlib.sha256(r.result["image"].tobytes()).hexdigest())
     line = {
         "metric": "serving: jobs/s and p50/p99 latency (Poisson arrivals at 0.7x measured capacity)",
         "value": poisson["jobs_per_s"], "unit": "jobs/s", "n_gpus": 1, "steps": len(jobs), "warmup": 2,
@@ -496,11 +531,17 @@ def serve_bench(a):
         "data": "synthetic (seeded)",
         "config": {"workload": f"{len(jobs)} removal jobs, RGB u8 256x256..2048x1536, holes 1-10% (1-3 blobs), "
                                "patch 7/9/11, full search; admission by workspace bytes "
-                               f"(budget {a.budget_gb} GiB), {a.capacity} slots, G={a.graph_iters}",
-                   "rate_jobs_per_s": round(rate, 3)},
-        "poisson": poisson, "saturation": sat,
+                               f"(budget {a.budget_gb} GiB), {a.capacity} slots, G={a.graph_iters}, "
+                               f"{a.workers} admission worker(s), {a.path} search",
+                   "rate_jobs_per_s": round(rate, 3), "fixed_rate_jobs_per_s": 20.0},
+        "poisson": poisson, "fixed_rate": fixed, "saturation": sat,
         "peak_active": srv_p.peak_active, "peak_bytes": srv_p.peak_used,
-        "mix_equals_alone": f"{same}/{n_check}",
+        "mix_equals_alone": f"{same}/{len(jobs)}",
+        "mix_differs": differ,
+        "not_done": [{"run": name, "job": r.index, "name": r.name, "status": r.status, "error": r.error}
+                     for name, rs in (("saturation", recs_sat), ("poisson", recs_p), ("fixed_rate", recs_f))
+                     for r in rs if r.status != "done"],
+        "parity": f"{gold_ok}/{gold_n} served jobs bit-exact vs stored oracle",
     }
     print(json.dumps(line), flush=True)
 

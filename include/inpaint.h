@@ -65,11 +65,15 @@ extern "C" {
  * host drives them; kernels skip their work once the hole is empty or the
  * iteration limit is reached, so overshooting a batch of iterations is
  * harmless.  PERSISTENT runs up to iters_per_check whole iterations inside
- * one cooperative dispatch: one work-group commits while the others keep
- * their search tiles resident in LDS and score every target in turn, with
- * no kernel boundary between search and commit.  It needs every tile's
- * work-group co-resident (and the SIMT path with tile_rows 8); otherwise
- * inpaint_run uses STREAM instead -- inpaint_run_form tells which. */
+ * one dispatch whose work-groups are all resident at once: one work-group
+ * commits while the others keep their search tiles resident in LDS and
+ * score every target in turn, with no kernel boundary between search and
+ * commit.  When the tiles outnumber the work-groups that fit on the device,
+ * each search work-group takes several tiles (up to 64).  It needs the
+ * default candidate domain (and the SIMT path with tile_rows 8); otherwise
+ * inpaint_run uses STREAM instead -- inpaint_run_form tells which.
+ * Persistent dispatches of one process never overlap (the library
+ * serialises them; each call waits for its dispatch's end). */
 #define INPAINT_FORM_PLAIN  0    /* launch one iteration, host check, repeat  */
 #define INPAINT_FORM_STREAM 1    /* enqueue iters_per_check iterations, check */
 #define INPAINT_FORM_GRAPH  2    /* replay a hipGraph of iters_per_check      */
@@ -319,7 +323,7 @@ const char *inpaint_last_error(const inpaint_ctx *ctx);
 /* Many images advanced together: each batch step runs, for every attached
  * unfinished image, G fill iterations (the fill loop of Section 3 per image).
  * Two forms:
- *  - PERSISTENT (the default when it fits): one cooperative dispatch per
+ *  - PERSISTENT (the default when it fits): one persistent dispatch per
  *    step and patch radius runs all G iterations of every image; one
  *    work-group per image commits (front, priority, copy), every other
  *    co-resident work-group searches (image, tile) items of whichever image

@@ -1644,7 +1644,7 @@ __device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L, CommitN
     commit_finish<R, ISECT>(d, s, L, v, best, g, key, idx, &s.snap, nullptr, note);
 }
 
-// ---- persistent fill: one cooperative dispatch runs many iterations ------
+// ---- persistent fill: one dispatch runs many iterations ------------------
 //
 // Work-group 0 commits; work-group 1 + t owns search tile t for the whole
 // dispatch, staged in LDS once (its source pixels never change).  Per
@@ -1949,7 +1949,7 @@ __global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(
         fill_search<R, kFillTileRows>(d, ntiles, epoch, lds.s);
 }
 
-// ---- batched persistent fill: many jobs in one cooperative dispatch -----
+// ---- batched persistent fill: many jobs in one dispatch -----------------
 //
 // Work-groups [0, n_commit) each commit one job (fill_commit, exactly as in
 // the single-job kernels, on that job's own records and slot words).  Every
@@ -2030,9 +2030,7 @@ __device__ __forceinline__ void multi_serve_mfma(const JobDev &d, int t, uint32_
         __syncthreads();
         mtile::build_tables<R>(&S.ft);
         __syncthreads();
-        mtile::BFrags<R> b;
-        mtile::load_frags<R>(&S.ft, b);
-        best = tile::wave_min_u64(mtile::score_tile<R>(d, b, tx0, ty0, vmask, S.tile));
+        best = tile::wave_min_u64(mtile::score_tile_rows<R>(d, &S.ft, tx0, ty0, vmask, S.tile));
         if ((threadIdx.x & 63) == 0) S.red[threadIdx.x >> 6] = best;
         __syncthreads();
         if (threadIdx.x == 0)
@@ -2337,7 +2335,7 @@ hipError_t launch_fill(const JobDev &d, int ntiles, int n_iters, uint32_t epoch,
     if (!f) return hipErrorInvalidValue;
     JobDev dd = d;
     void *args[] = {&dd, &ntiles, &n_iters, &epoch};
-    return hipLaunchCooperativeKernel(f, dim3(fill_grid(ntiles)), dim3(kCommitThreads), args, 0, s);
+    return hipLaunchKernel(f, dim3(fill_grid(ntiles)), dim3(kCommitThreads), args, 0, s);
 }
 
 static const void *fill_multi_kernel(bool mfma, int r) {
@@ -2377,7 +2375,7 @@ hipError_t launch_fill_multi(const MultiPlan &m, bool mfma, int r, int grid, int
     if (!f || grid <= m.n_commit) return hipErrorInvalidValue;
     MultiPlan mm = m;
     void *args[] = {&mm, &n_iters, &epoch};
-    return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kCommitThreads), args, 0, s);
+    return hipLaunchKernel(f, dim3(grid), dim3(kCommitThreads), args, 0, s);
 }
 
 hipError_t launch_stage_query(const JobDev &d, int tx, int ty, int r, hipStream_t s) {

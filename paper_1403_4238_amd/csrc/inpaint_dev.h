@@ -242,13 +242,13 @@ hipError_t launch_commit_batched(const JobDev *slots, const int32_t *ids, const 
 hipError_t launch_count_active(const JobDev *slots, int nslots, int64_t *out, int32_t *status, hipStream_t s);
 hipError_t launch_search_batched(const JobDev *slots, const WorkItem *items, const int32_t *nitems,
                                  int r, int tile_rows, int grid, hipStream_t s);
-// Persistent fill (cooperative): runs up to n_iters iterations of the job in
+// Persistent fill: runs up to n_iters iterations of the job in
 // one dispatch; needs fill_grid(ntiles) co-resident work-groups.
 hipError_t fill_blocks_per_cu(int r, bool mfma, int *blocks);
 int fill_grid(int ntiles);
 hipError_t launch_fill(const JobDev &d, int ntiles, int n_iters, uint32_t epoch, hipStream_t s);
 // Batched persistent fill: up to n_iters iterations of every job of the plan
-// (all of patch radius r) in one cooperative dispatch of `grid` = n_commit +
+// (all of patch radius r) in one persistent dispatch of `grid` = n_commit +
 // search groups.  MFMA: r <= 6, the int8-MFMA tiling; SIMT: the SIMT tiling
 // of kFillTileRows.
 hipError_t multi_blocks_per_cu(bool mfma, int r, int *blocks);

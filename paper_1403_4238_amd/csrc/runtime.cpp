@@ -14,6 +14,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -43,6 +45,22 @@ uint32_t next_nonce() {
     while (v == 0);
     return v;
 }
+
+// Persistent dispatches (k_fill*, k_fill_multi*) need every work-group of
+// their grid resident at once: their groups wait on one another, and the
+// host sizes the grid from the occupancy API for an otherwise idle device.
+// Kernels of other streams running beside such a dispatch hold resources
+// its late groups need; while new ones keep arriving those groups can wait
+// past the dispatch's bounded waits (a device error), and with cooperative
+// launches results were seen to go wrong as well.  So a persistent dispatch
+// runs alone: it holds this lock exclusively from its launch until the host
+// has seen it end, and every other call of the library that puts work on the
+// device holds it shared until that work has ended (each such call
+// synchronises its stream before it returns).  Calls that do not run a
+// persistent dispatch still overlap one another freely.
+std::shared_mutex g_device_mu;
+typedef std::shared_lock<std::shared_mutex> SharedDevice;
+typedef std::unique_lock<std::shared_mutex> ExclusiveDevice;
 
 // Launch epochs of persistent dispatches, unique in the process: a job's
 // records and slot words may hold values from any earlier dispatch that ran
@@ -295,9 +313,9 @@ static int32_t check_params(int32_t W, int32_t H, const inpaint_params *p, std::
     return INPAINT_OK;
 }
 
-// Whether the persistent fill can run this job: the SIMT search with its
-// tile shape or the MFMA search, a device with cooperative launch, and every
-// work-group of the dispatch co-resident.
+// Whether the persistent fill with one tile per search work-group can run
+// this job: the SIMT search with its tile shape or the MFMA search, and
+// every work-group of the dispatch co-resident.
 static bool persistent_fits(const inpaint_ctx *c) {
     const JobDev &d = c->d;
     const int ntiles = d.ntx * d.nty;
@@ -305,9 +323,8 @@ static bool persistent_fits(const inpaint_ctx *c) {
     if (c->direct || c->d.policy != INPAINT_SOURCE_ORIGINAL || c->d.isect) return false;
     if ((!c->mfma && d.tile_rows != kFillTileRows) || ntiles <= 0 || ntiles > 32 * kCommitThreads) return false;
     if ((int64_t)d.W * d.H > (1ll << kSlotIndexBits)) return false;   // slot word index field
-    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return false;
-    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return false;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return false;
     if (fill_blocks_per_cu(d.r, c->mfma, &per_cu) != hipSuccess) return false;
     return (int64_t)fill_grid(ntiles) <= (int64_t)per_cu * cus;
@@ -327,12 +344,10 @@ static void spread_items(const std::vector<WorkItem> &all, int n_search, std::ve
     for (size_t i = 0; i < all.size(); ++i) (*items)[pos[i % n_search]++] = all[i];
 }
 
-// Co-resident work-groups of the batched persistent kernel on this device
-// (0 if it cannot run: no cooperative launch).
+// Co-resident work-groups of the batched persistent kernel on this device.
 static int multi_capacity(bool mfma, int r) {
-    int dev = 0, coop = 0, cus = 0, per_cu = 0;
+    int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     if (multi_blocks_per_cu(mfma, r, &per_cu) != hipSuccess) return 0;
     return std::min(per_cu * cus, kMaxGroups);
@@ -418,6 +433,7 @@ static int32_t create_fail(inpaint_ctx *c, int32_t st, const std::string &msg) {
 int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t mask_stride,
                        const inpaint_params *p, void *d_workspace, uint64_t ws_bytes, void *hip_stream,
                        inpaint_ctx **out) {
+    SharedDevice lock(g_device_mu);
     g_create_error.clear();
     if (!img || !img->data || !mask || !out || !d_workspace)
         return create_fail(nullptr, INPAINT_INVALID_ARGUMENT, "NULL argument");
@@ -586,6 +602,7 @@ int32_t inpaint_search_info(const inpaint_ctx *ctx, inpaint_rect *rect, int64_t 
 
 int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t tx, int32_t ty, int32_t r, inpaint_rect rect,
                               int64_t *source_index, uint32_t *ssd) {
+    SharedDevice lock(g_device_mu);
     if (!ctx) return INPAINT_INVALID_ARGUMENT;
     if (ctx->sticky) return ctx->sticky;
     const JobDev &d = ctx->d;
@@ -627,6 +644,7 @@ int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t tx, int32_t ty, int32_t 
 // partials, key) in the static device array instead of the workspace.
 int32_t inpaint_find_exemplar_static(inpaint_ctx *ctx, int32_t tx, int32_t ty, int32_t r, inpaint_rect rect,
                                      int64_t *source_index, uint32_t *ssd) {
+    SharedDevice lock(g_device_mu);
     if (!ctx) return INPAINT_INVALID_ARGUMENT;
     if (ctx->sticky) return ctx->sticky;
     const JobDev &d = ctx->d;
@@ -722,6 +740,7 @@ static int32_t check_device_state(inpaint_ctx *ctx) {
 }
 
 int32_t inpaint_step(inpaint_ctx *ctx, inpaint_step_info *info) {
+    SharedDevice lock(g_device_mu);
     if (!ctx) return INPAINT_INVALID_ARGUMENT;
     if (ctx->sticky) return ctx->sticky;
     if (ctx->batch) return ctx->fail(INPAINT_INVALID_ARGUMENT, "context is attached to a batch");
@@ -758,6 +777,11 @@ static hipError_t ensure_graph(inpaint_ctx *ctx, int G) {
 int32_t inpaint_run(inpaint_ctx *ctx, int64_t max_iters, int64_t *iters_done, inpaint_step_info *log,
                     int64_t log_cap) {
     if (!ctx) return INPAINT_INVALID_ARGUMENT;
+    // the persistent form's dispatches run alone on the device
+    SharedDevice shared(g_device_mu, std::defer_lock);
+    ExclusiveDevice excl(g_device_mu, std::defer_lock);
+    if (ctx->run_form == INPAINT_FORM_PERSISTENT) excl.lock();
+    else shared.lock();
     if (ctx->sticky) return ctx->sticky;
     if (ctx->batch) return ctx->fail(INPAINT_INVALID_ARGUMENT, "context is attached to a batch");
     const int64_t start = ctx->h_state->iter;
@@ -817,6 +841,7 @@ int32_t inpaint_run(inpaint_ctx *ctx, int64_t max_iters, int64_t *iters_done, in
 }
 
 int32_t inpaint_read_log(inpaint_ctx *ctx, int64_t first, int64_t count, inpaint_step_info *out) {
+    SharedDevice lock(g_device_mu);
     if (!ctx || !out || first < 0 || count < 0) return INPAINT_INVALID_ARGUMENT;
     if (ctx->sticky) return ctx->sticky;
     HIP_OR_FAIL(ctx, ctx->pull_state(), "state");
@@ -830,6 +855,7 @@ int32_t inpaint_read_log(inpaint_ctx *ctx, int64_t first, int64_t count, inpaint
 }
 
 int32_t inpaint_read_image(inpaint_ctx *ctx, uint8_t *rgb, int32_t stride) {
+    SharedDevice lock(g_device_mu);
     if (!ctx || !rgb) return INPAINT_INVALID_ARGUMENT;
     if (ctx->sticky) return ctx->sticky;
     const int W = ctx->d.W, H = ctx->d.H;
@@ -849,6 +875,7 @@ int32_t inpaint_read_image(inpaint_ctx *ctx, uint8_t *rgb, int32_t stride) {
 }
 
 int32_t inpaint_read_state(inpaint_ctx *ctx, uint8_t *mask, double *conf) {
+    SharedDevice lock(g_device_mu);
     if (!ctx) return INPAINT_INVALID_ARGUMENT;
     if (ctx->sticky) return ctx->sticky;
     const size_t n = (size_t)ctx->d.W * ctx->d.H;
@@ -859,6 +886,7 @@ int32_t inpaint_read_state(inpaint_ctx *ctx, uint8_t *mask, double *conf) {
 }
 
 int32_t inpaint_remaining(inpaint_ctx *ctx, int64_t *remaining) {
+    SharedDevice lock(g_device_mu);
     if (!ctx || !remaining) return INPAINT_INVALID_ARGUMENT;
     if (ctx->sticky) return ctx->sticky;
     HIP_OR_FAIL(ctx, ctx->pull_state(), "state");
@@ -867,6 +895,7 @@ int32_t inpaint_remaining(inpaint_ctx *ctx, int64_t *remaining) {
 }
 
 int32_t inpaint_progress(inpaint_ctx *ctx, int64_t *iterations, int64_t *remaining) {
+    SharedDevice lock(g_device_mu);
     if (!ctx) return INPAINT_INVALID_ARGUMENT;
     if (ctx->sticky) return ctx->sticky;
     HIP_OR_FAIL(ctx, ctx->pull_state(), "state");
@@ -877,6 +906,7 @@ int32_t inpaint_progress(inpaint_ctx *ctx, int64_t *iterations, int64_t *remaini
 
 int32_t inpaint_import_state(inpaint_ctx *ctx, const uint8_t *rgb, int32_t rgb_stride, int32_t channels,
                              const uint8_t *hole, int32_t hole_stride, const double *conf, int64_t iterations) {
+    SharedDevice lock(g_device_mu);
     if (!ctx) return INPAINT_INVALID_ARGUMENT;
     if (ctx->sticky) return ctx->sticky;
     if (ctx->batch) return ctx->fail(INPAINT_INVALID_ARGUMENT, "context is attached to a batch");
@@ -958,11 +988,16 @@ int32_t inpaint_run_form(const inpaint_ctx *ctx, int32_t *form) {
     return INPAINT_OK;
 }
 
-int32_t inpaint_batch_detach(inpaint_batch *b, inpaint_ctx *ctx);
+}  // extern "C"
+
+static int32_t batch_detach(inpaint_batch *b, inpaint_ctx *ctx);
+
+extern "C" {
 
 int32_t inpaint_destroy(inpaint_ctx *ctx) {
+    SharedDevice lock(g_device_mu);
     if (!ctx) return INPAINT_INVALID_ARGUMENT;
-    if (ctx->batch) inpaint_batch_detach(ctx->batch, ctx);
+    if (ctx->batch) batch_detach(ctx->batch, ctx);
     hipStreamSynchronize(ctx->stream);
     if (ctx->graph) hipGraphExecDestroy(ctx->graph);
     for (auto ev : ctx->ev0) hipEventDestroy(ev);
@@ -1376,6 +1411,7 @@ int32_t inpaint_batch_create(const inpaint_batch_params *bp, void *hip_stream, i
 }
 
 int32_t inpaint_batch_attach(inpaint_batch *b, inpaint_ctx *ctx, int32_t *slot) {
+    SharedDevice lock(g_device_mu);
     if (!b || !ctx || ctx->batch || ctx->sticky) return INPAINT_INVALID_ARGUMENT;
     if (ctx->d.policy != INPAINT_SOURCE_ORIGINAL || ctx->d.isect)
         return ctx->fail(INPAINT_INVALID_ARGUMENT, "a batch runs only the default candidate domain");
@@ -1396,6 +1432,13 @@ int32_t inpaint_batch_attach(inpaint_batch *b, inpaint_ctx *ctx, int32_t *slot) 
 }
 
 int32_t inpaint_batch_detach(inpaint_batch *b, inpaint_ctx *ctx) {
+    SharedDevice lock(g_device_mu);
+    return batch_detach(b, ctx);
+}
+
+}  // extern "C"
+
+static int32_t batch_detach(inpaint_batch *b, inpaint_ctx *ctx) {
     if (!b || !ctx || ctx->batch != b) return INPAINT_INVALID_ARGUMENT;
     for (size_t i = 0; i < b->slots.size(); ++i)
         if (b->slots[i] == ctx) {
@@ -1411,8 +1454,10 @@ int32_t inpaint_batch_detach(inpaint_batch *b, inpaint_ctx *ctx) {
     return INPAINT_OK;
 }
 
+extern "C" {
+
 // One batch step in the batched persistent form: every planned group runs G
-// iterations of its jobs in one cooperative dispatch.
+// iterations of its jobs in one persistent dispatch.
 static hipError_t step_multi(inpaint_batch *b, int32_t G) {
     for (const MultiBuf &m : b->mbufs) {
         hipError_t e = launch_fill_multi(m.plan, m.mfma, m.r, m.grid, G, next_epoch(), b->stream);
@@ -1435,6 +1480,7 @@ static int32_t finish_step(inpaint_batch *b, int64_t *active) {
 
 int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active) {
     if (!b || G < 1) return INPAINT_INVALID_ARGUMENT;
+    SharedDevice lock(g_device_mu);
     hipError_t e = hipSuccess;
     if (b->bp.form != INPAINT_FORM_GRAPH) {
         // AUTO takes the persistent form only while every search tile of
@@ -1449,6 +1495,9 @@ int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active) {
         if (fits) {
             b->dirty = false;
             b->last_form = INPAINT_FORM_PERSISTENT;
+            // the dispatches run alone on the device
+            lock.unlock();
+            ExclusiveDevice excl(g_device_mu);
             e = step_multi(b, G);
             if (e != hipSuccess) return INPAINT_DEVICE;
             return finish_step(b, active);
@@ -1513,6 +1562,7 @@ int32_t inpaint_batch_status(const inpaint_batch *b, int32_t slot, int32_t *stat
 }
 
 int32_t inpaint_batch_destroy(inpaint_batch *b) {
+    SharedDevice lock(g_device_mu);
     if (!b) return INPAINT_INVALID_ARGUMENT;
     for (auto *c : b->slots)
         if (c) c->batch = nullptr;

@@ -295,5 +295,77 @@ __device__ __forceinline__ uint64_t score_tile(const JobDev &d, const BFrags<R> 
     return best;
 }
 
+// The same scoring with the B operands read from the per-target tables in
+// LDS one patch row at a time (rows outer, the four 16-row blocks inner):
+// only one row's B operands and the 16 accumulators are live, not the B
+// operands of every row, so the register budget no longer grows with the
+// patch size, and the 16 independent accumulation chains keep the matrix
+// cores busy.  Same arithmetic and result as score_tile.
+template <int R>
+__device__ __forceinline__ uint64_t score_tile_rows(const JobDev &d, const FragTables<R> *ft, int tx0, int ty0,
+                                                    uint32_t vmask, const MfmaTile<R> &L) {
+    constexpr int P = 2 * R + 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = lane & 15, g = lane >> 4, s4 = n & 3;
+    const int W = d.W, cx = tx0 + 16 * wave + n;
+    int t2 = 0, kk = 0;
+#pragma unroll
+    for (int w = 0; w < kSearchWaves; ++w) {
+        t2 += ft->t2p[w];
+        kk += ft->k[w];
+    }
+    t2 = __builtin_amdgcn_readfirstlane(t2);
+    kk = __builtin_amdgcn_readfirstlane(kk);
+    v4i c0[kMfmaTilesPerWave], c1[kMfmaTilesPerWave], cl[kMfmaTilesPerWave], ch[kMfmaTilesPerWave];
+#pragma unroll
+    for (int t = 0; t < kMfmaTilesPerWave; ++t) {
+        c0[t] = v4i{0, 0, 0, 0};
+        c1[t] = v4i{0, 0, 0, 0};
+        cl[t] = v4i{0, 0, 0, 0};
+        ch[t] = v4i{0, 0, 0, 0};
+    }
+    const int base = n * kMfmaStrideA + 16 * wave + 4 * g;
+    const int qbase = n * kMfmaStrideQ + 32 * wave + 16 * g;
+#pragma unroll
+    for (int dy = 0; dy < P; ++dy) {
+        const v4i b0 = *(const v4i *)&ft->tc[s4][dy][4 * g + 16 - 4 * (n >> 2)];
+        const v4i b1 = *(const v4i *)&ft->tc[s4][dy][16 + 4 * g + 16 - 4 * (n >> 2)];
+        v4i bl, bh;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t w = ft->lw[dy][8 * g + 2 * j - n + 16];
+            bl[j] = (int)w;
+            bh[j] = (int)(w << 8);
+        }
+#pragma unroll
+        for (int t = 0; t < kMfmaTilesPerWave; ++t) {
+            const int row = (16 * t + dy);
+            const v4i a0 = *(const v4i *)&L.a[base + row * kMfmaStrideA];
+            const v4i a1 = *(const v4i *)&L.a[base + row * kMfmaStrideA + 16];
+            const v4i aq = *(const v4i *)&L.q[qbase + row * kMfmaStrideQ];
+            c0[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b0, c0[t], 0, 0, 0);
+            c1[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b1, c1[t], 0, 0, 0);
+            cl[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aq, bl, cl[t], 0, 0, 0);
+            ch[t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(aq, bh, ch[t], 0, 0, 0);
+        }
+    }
+    uint64_t best = ~0ull;
+#pragma unroll
+    for (int t = 0; t < kMfmaTilesPerWave; ++t) {
+        // C lane (n, g) holds rows 4g + i of column n.
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (vmask & (1u << (4 * t + i))) {
+                const int s2 = 256 * (ch[t][i] + 128 * kk) + cl[t][i] + 128 * kk;
+                const uint32_t ssd = (uint32_t)(t2 - 2 * (c0[t][i] + c1[t][i]) + s2);
+                const int y = ty0 + 16 * t + 4 * g + i;
+                const uint64_t key = ((uint64_t)ssd << 32) | (uint32_t)(y * W + cx);
+                best = key < best ? key : best;
+            }
+        }
+    }
+    return best;
+}
+
 }  // namespace mtile
 }  // namespace inpaint

@@ -2,18 +2,23 @@
 
 Jobs arrive over time (e.g. a Poisson process).  A job is admitted when a
 batch slot is free and its device footprint (the workspace its context needs)
-fits the memory budget; it is then created on a side stream and attached to
+fits the memory budget: both are reserved at once, and the job's context is
+prepared (upload and initialisation) on a worker thread with its own stream
+while the loop keeps stepping the running jobs.  A prepared job is attached to
 the running batch between two batch steps.  Every batch step advances every
-attached unfinished job by G fill iterations in one persistent, graph-replayed
-launch sequence, so jobs that arrive while others run share the device with
-them.  Finished jobs are read back, detached and their memory released,
-which may admit queued jobs.  Latency is completion time minus arrival time.
+attached unfinished job by G fill iterations, so jobs that arrive while others
+run share the device with them.  Finished jobs are read back, detached and
+their memory released, which may admit queued jobs.  Latency is completion
+time minus arrival time.
 
 The loop talks to an engine object; ``GpuEngine`` drives libinpaint through
 the binding, ``FakeEngine`` (tests) simulates iteration counts on the CPU.
+An engine with ``prepare`` / ``attach`` is admitted asynchronously (when the
+server has workers); otherwise ``admit`` runs on the loop.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import dataclasses
 import time
 from typing import Callable
@@ -45,9 +50,10 @@ class Server:
 
     def __init__(self, engine, budget_bytes: int, capacity: int, graph_iters: int = 8,
                  clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
-                 keep_results: bool = True):
-        if capacity < 1 or budget_bytes <= 0 or graph_iters < 1:
+                 keep_results: bool = True, workers: int = 0):
+        if capacity < 1 or budget_bytes <= 0 or graph_iters < 1 or workers < 0:
             raise ValueError("capacity, budget and graph_iters must be positive")
+        self.workers = workers if hasattr(engine, "prepare") else 0
         self.engine = engine
         self.budget = int(budget_bytes)
         self.capacity = int(capacity)
@@ -62,6 +68,12 @@ class Server:
 
     def run(self, jobs) -> list[JobRecord]:
         """Serves ``jobs`` (objects with .arrival_s) to completion."""
+        if self.workers:
+            with cf.ThreadPoolExecutor(self.workers, thread_name_prefix="admit") as pool:
+                return self._run(jobs, pool)
+        return self._run(jobs, None)
+
+    def _run(self, jobs, pool) -> list[JobRecord]:
         eng = self.engine
         recs = [JobRecord(i, getattr(j, "name", str(i)), float(j.arrival_s), int(eng.footprint(j)))
                 for i, j in enumerate(jobs)]
@@ -69,8 +81,15 @@ class Server:
         t0 = self.clock()
         nxt = 0
         queue: list[int] = []
+        preparing: dict[int, cf.Future] = {}   # admitted, context being prepared off the loop
         active: dict[int, object] = {}
-        while nxt < len(order) or queue or active:
+
+        def fail(i, e):
+            recs[i].status, recs[i].error = "failed", str(e)
+            recs[i].done_s = self.clock() - t0
+            self.used -= recs[i].footprint
+
+        while nxt < len(order) or queue or preparing or active:
             now = self.clock() - t0
             while nxt < len(order) and recs[order[nxt]].arrival_s <= now:
                 i = order[nxt]
@@ -81,16 +100,29 @@ class Server:
                     continue
                 queue.append(i)
             # admit in arrival order while a slot and memory are free
-            while queue and len(active) < self.capacity and self.used + recs[queue[0]].footprint <= self.budget:
+            while (queue and len(active) + len(preparing) < self.capacity
+                   and self.used + recs[queue[0]].footprint <= self.budget):
                 i = queue.pop(0)
-                try:
-                    h = eng.admit(jobs[i])
-                except Exception as e:  # invalid job: report it, keep serving the rest
-                    recs[i].status, recs[i].error = "failed", str(e)
-                    recs[i].done_s = self.clock() - t0
-                    continue
-                active[i] = h
                 self.used += recs[i].footprint
+                recs[i].status = "admitted"
+                if pool is not None:
+                    preparing[i] = pool.submit(eng.prepare, jobs[i])
+                    continue
+                try:
+                    active[i] = eng.admit(jobs[i])
+                except Exception as e:  # invalid job: report it, keep serving the rest
+                    fail(i, e)
+                    continue
+                recs[i].admit_s = self.clock() - t0
+                recs[i].status = "running"
+            # prepared jobs join the batch between two steps
+            for i in [i for i, f in preparing.items() if f.done()]:
+                f = preparing.pop(i)
+                try:
+                    active[i] = eng.attach(f.result())
+                except Exception as e:
+                    fail(i, e)
+                    continue
                 recs[i].admit_s = self.clock() - t0
                 recs[i].status = "running"
             self.peak_used = max(self.peak_used, self.used)
@@ -113,6 +145,8 @@ class Server:
                         eng.release(h)
                     r.done_s = now
                     self.used -= r.footprint
+            elif preparing:
+                cf.wait(list(preparing.values()), timeout=0.05, return_when=cf.FIRST_COMPLETED)
             elif nxt < len(order):
                 wait = recs[order[nxt]].arrival_s - (self.clock() - t0)
                 if wait > 0:
@@ -161,14 +195,20 @@ class FakeEngine:
     def footprint(self, job) -> int:
         return self._footprint(job)
 
-    def admit(self, job):
+    def prepare(self, job):
         if self.fail_on and self.fail_on(job):
             raise ValueError("invalid job")
+        return job
+
+    def attach(self, job):
         h = self._next
         self._next += 1
         self.live[h] = [job, 0, int(self.iterations(job))]
         self.max_live = max(self.max_live, len(self.live))
         return h
+
+    def admit(self, job):
+        return self.attach(self.prepare(job))
 
     def step(self, G: int) -> int:
         for st in self.live.values():
@@ -205,33 +245,57 @@ class FakeClock:
 
 
 class GpuEngine:
-    """libinpaint through the binding: one Batch, contexts created on a side
-    stream, their torch workspaces freed on release."""
+    """libinpaint through the binding: one Batch; contexts are prepared on a
+    side stream of the calling thread (a server worker, so the loop keeps
+    stepping meanwhile) and attached between steps; their torch workspaces
+    are freed on release."""
 
     def __init__(self, capacity: int, graph_iters: int = 8, autotune: bool = True, tune_cache: str | None = None,
-                 log: bool = True):
+                 log: bool = True, path: str = "mfma"):
+        import threading
+
         import torch
 
         from . import binding as B
         self.B = B
         self.torch = torch
         self.stream = torch.cuda.current_stream()
-        self.side = torch.cuda.Stream()
+        self.device = torch.cuda.current_device()
+        self._local = threading.local()
         self.batch = B.Batch(capacity, graph_iters, autotune, tune_cache, stream=self.stream)
         self.log = log
+        self.path = path
+
+    def _side(self):
+        s = getattr(self._local, "stream", None)
+        if s is None:
+            self.torch.cuda.set_device(self.device)
+            s = self._local.stream = self.torch.cuda.Stream()
+        return s
+
+    def _path_id(self, job):
+        # the int8-MFMA search serves patches up to 13x13
+        return self.B.PATH_MFMA if self.path == "mfma" and job.patch_radius <= 6 else self.B.PATH_SIMT
 
     def footprint(self, job) -> int:
-        p = self.B.make_params(job.patch_radius, job.search_mode, job.alpha, job.rect,
+        p = self.B.make_params(job.patch_radius, job.search_mode, job.alpha, job.rect, path=self._path_id(job),
                                log_capacity=int(np.count_nonzero(job.mask)) if self.log else 0)
         return self.B.inpaint_workspace_bytes(job.width, job.height, p)
 
-    def admit(self, job):
-        with self.torch.cuda.stream(self.side):
+    def prepare(self, job):
+        side = self._side()
+        with self.torch.cuda.stream(side):
             ctx = self.B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, job.rect,
                                    log_capacity=int(np.count_nonzero(job.mask)) if self.log else 0,
-                                   stream=self.side)
+                                   stream=side, path=self._path_id(job))
+        return ctx
+
+    def attach(self, ctx):
         self.batch.attach(ctx)
         return ctx
+
+    def admit(self, job):
+        return self.attach(self.prepare(job))
 
     def step(self, G: int) -> int:
         return self.batch.step(G)

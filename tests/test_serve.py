@@ -109,3 +109,31 @@ def test_bad_configuration():
         Server(FakeEngine(lambda j: 1, lambda j: 1), budget_bytes=0, capacity=1)
     with pytest.raises(ValueError):
         Server(FakeEngine(lambda j: 1, lambda j: 1), budget_bytes=10, capacity=0)
+
+
+def test_async_admission_matches_sync():
+    # Contexts prepared on worker threads join between steps: every job
+    # completes with its scripted iterations, the limits hold, and an invalid
+    # job fails alone, as with admission on the loop.
+    rng = np.random.default_rng(1)
+    t, jobs = 0.0, []
+    for i in range(60):
+        t += float(rng.exponential(0.005))
+        jobs.append(J(f"j{i}", t, int(rng.integers(1, 40)), int(rng.integers(1, 20)), bad=(i == 7)))
+    out = {}
+    for workers in (0, 2):
+        srv, eng, recs = _server(jobs, budget=50, capacity=6, G=3, workers=workers)
+        assert [r.status for r in recs].count("failed") == 1 and recs[7].status == "failed"
+        assert all(r.status == "done" for k, r in enumerate(recs) if k != 7)
+        assert all(r.iterations == j.iters for k, (r, j) in enumerate(zip(recs, jobs)) if k != 7)
+        assert srv.peak_used <= 50 and eng.max_live <= 6 and srv.used == 0
+        out[workers] = [r.iterations for r in recs]
+    assert out[0] == out[2]
+
+
+def test_async_admission_counts_preparing_jobs_against_the_limits():
+    jobs = [J(f"j{i}", 0.0, 5, 30) for i in range(5)]
+    srv, eng, recs = _server(jobs, budget=100, capacity=4, workers=3)
+    assert all(r.status == "done" for r in recs)
+    assert eng.max_live <= 3          # 3 x 30 bytes fit in 100, a fourth does not
+    assert srv.peak_used <= 100

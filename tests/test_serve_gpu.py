@@ -29,12 +29,13 @@ def _jobs(n=10, rate=400.0, seed=9):
     return jobs
 
 
-@pytest.mark.parametrize("capacity,budget_jobs", [(4, 3), (16, 16)])
-def test_served_results_equal_alone_and_oracle(capacity, budget_jobs):
+@pytest.mark.parametrize("capacity,budget_jobs,workers,path", [(4, 3, 0, "simt"), (16, 16, 0, "mfma"),
+                                                               (4, 3, 2, "mfma")])
+def test_served_results_equal_alone_and_oracle(capacity, budget_jobs, workers, path):
     jobs = _jobs()
-    eng = serve.GpuEngine(capacity=capacity, graph_iters=6, autotune=False)
+    eng = serve.GpuEngine(capacity=capacity, graph_iters=6, autotune=False, path=path)
     budget = budget_jobs * max(eng.footprint(j) for j in jobs)
-    srv = serve.Server(eng, budget, capacity, graph_iters=6)
+    srv = serve.Server(eng, budget, capacity, graph_iters=6, workers=workers)
     recs = srv.run(jobs)
     assert all(r.status == "done" for r in recs), [(r.name, r.status, r.error) for r in recs]
     assert srv.peak_active <= capacity and srv.peak_used <= budget
@@ -75,7 +76,7 @@ def test_serving_workload_full_size():
     golds = [load_golden(f"serve{i:02d}") for i in range(16)]
     assert all(g is not None for g in golds), "stored oracle results missing"
     eng = serve.GpuEngine(capacity=16, graph_iters=16, autotune=True)
-    srv = serve.Server(eng, 4 << 30, 16, graph_iters=16)
+    srv = serve.Server(eng, 4 << 30, 16, graph_iters=16, workers=1)
     recs = srv.run(jobs)
     assert all(r.status == "done" for r in recs), [(r.name, r.status, r.error) for r in recs if r.status != "done"]
     assert srv.peak_active >= 2 and srv.peak_used <= 4 << 30
@@ -85,7 +86,8 @@ def test_serving_workload_full_size():
         assert g["input_sha256"] == j.sha256(), j.name
         assert_matches_golden(g, r.result["log"], r.result["image"], j.name)
     for j, r in zip(jobs, recs):
-        alone = B.Inpainter(j.rgb, j.mask, j.patch_radius, log_capacity=int(j.mask.sum()))
+        alone = B.Inpainter(j.rgb, j.mask, j.patch_radius, log_capacity=int(j.mask.sum()), form="persistent",
+                            iters_per_check=256, path=B.PATH_MFMA if j.patch_radius <= 6 else B.PATH_SIMT)
         st, n, log = alone.run(log_cap=int(j.mask.sum()))
         assert st == B.DONE and n == len(r.result["log"]), j.name
         assert log_sha256(log) == log_sha256(r.result["log"]), j.name + ": log differs from the job alone"
