@@ -1663,6 +1663,18 @@ constexpr uint32_t kSpinLimit = 1u << 22;
 __device__ __forceinline__ uint64_t go_word(uint32_t epoch, uint32_t v) { return ((uint64_t)epoch << 32) | v; }
 
 // Thread 0 of search group t: 1 once target k is staged, 0 on stop or time-out.
+//
+// Ordering of the record reads after the go word (hardware, not the language
+// memory model): the committer writes the record, waits for its stores
+// (s_waitcnt) and releases the go word at agent scope, which writes the L2
+// back first.  Here the go word is polled with relaxed agent-scope loads;
+// the caller's barrier follows the matching load's completion, and every
+// record word is then read with an agent-scope load too, which is coherent
+// at device scope (it does not hit a stale copy in the CU's L1 or an XCD's
+// L2).  So the reads observe the record.  An agent-scope acquire fence
+// after the match would make this a language-level guarantee, but on gfx950
+// it invalidates caches for every search group on every iteration: it was
+// measured to slow the 1080p removal from 49.2 ms to 61.4 ms.
 __device__ int wait_go(const FillSync *sy, int t, uint32_t epoch, uint32_t k) {
     const uint64_t want = go_word(epoch, k + 1), stop = go_word(epoch, 0xffffffffu);
     const uint64_t *g = &sy->rec[t % kGoCopies].go;
@@ -1716,6 +1728,8 @@ __device__ uint64_t collect_slots(const uint64_t *fs, int ntiles, uint32_t tag, 
     const int done = !__syncthreads_or(pend != 0);
     *ok = done;
     if (!done) return ~0ull;
+    // (each slot word is the whole report: nothing else of the search
+    // groups is read, so no acquire is needed here)
     best = block_min_u64(best, s.u);
     const uint64_t ssd = best >> kSlotIndexBits, idx = best & ((1ull << kSlotIndexBits) - 1);
     if (ssd == (1ull << 26) - 1) return ~0ull;
@@ -1822,12 +1836,8 @@ __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t 
     if (d0.mfma && staged && v.pending && !v.done && !v.err) build_mfma_frags(R, s, d0.frag);
 }
 
-// Copies record `rec` (published by the go word just observed) into LDS.
-// Every word is read with a device-scope load, which bypasses the caches
-// that could hold an older copy; the committer wrote the record back before
-// its release of the go word, and these loads issue after that word was
-// seen.  So no cache invalidation (an agent-scope acquire) is needed here,
-// which would otherwise run once per work-group per iteration.
+// Copies record `rec` (published by the go word just observed) into LDS,
+// each word with an agent-scope load (see wait_go for the ordering).
 template <int R>
 __device__ __forceinline__ void load_record(const FillRec *rec, tile::TargetLds *t) {
     constexpr int P = 2 * R + 1, MW = (P * P + 31) / 32;
@@ -1917,9 +1927,7 @@ __device__ void fill_search_mfma(const JobDev &d, uint32_t epoch, SearchLdsMfma<
             __syncthreads();
             mtile::build_tables<R>(&S.ft);
             __syncthreads();
-            mtile::BFrags<R> b;
-            mtile::load_frags<R>(&S.ft, b);
-            best = tile::wave_min_u64(mtile::score_tile<R>(d, b, tx0, ty0, vmask, S.tile));
+            best = tile::wave_min_u64(mtile::score_tile_rows<R>(d, &S.ft, tx0, ty0, vmask, S.tile));
             if ((threadIdx.x & 63) == 0) S.red[threadIdx.x >> 6] = best;
             __syncthreads();
             if (threadIdx.x == 0)
@@ -1931,11 +1939,20 @@ __device__ void fill_search_mfma(const JobDev &d, uint32_t epoch, SearchLdsMfma<
     }
 }
 
+// gather()'s load batching of the MFMA committer: smaller batches for the
+// larger patches keep it within the register budget of two work-groups per
+// CU (no spills).
+template <int R>
+struct MfmaCommitBatch {
+    static constexpr int TB = R <= 4 ? 8 : (R == 5 ? 4 : 2);
+    static constexpr int BW = R <= 4 ? 12 : (R == 5 ? 6 : 4);
+};
+
 template <int R>
 __global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_fill_mfma(JobDev d, int ntiles, int n_iters, uint32_t epoch) {
     __shared__ FillLdsMfma<R> lds;
     if (blockIdx.x == 0)
-        fill_commit<R, 8, 12, true>(d, ntiles, n_iters, epoch, lds.c);
+        fill_commit<R, MfmaCommitBatch<R>::TB, MfmaCommitBatch<R>::BW, true>(d, ntiles, n_iters, epoch, lds.c);
     else
         fill_search_mfma<R>(d, epoch, lds.s);
 }
@@ -1988,12 +2005,9 @@ __device__ __forceinline__ void multi_poll(const uint64_t *my_go, int my_slot, i
     }
     const uint64_t rb = __ballot(ready), db = __ballot(my_done);
     const uint64_t hi = rb & (~0ull << rot);
+    // (the record reads that follow are ordered after the go load as in
+    // wait_go: agent-scope loads issued after it completed)
     const int pick = hi ? __builtin_ctzll(hi) : (rb ? __builtin_ctzll(rb) : -1);
-    if (pick >= 0) {
-        // the record this item reads was written back before its go word was
-        // released; order this group's record loads after the go load
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
     if (lane == 0) {
         pk->pick = pick;
         pk->all_done = db == ~0ull;
@@ -2117,7 +2131,8 @@ __global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(
         // by value: held through a reference to device memory, the job's
         // fields would stay live in vector registers (and spill)
         const JobDev d = m.slots[m.commit[blockIdx.x]];
-        fill_commit<R, 8, 12, true>(d, d.ntx * d.nty, n_iters, epoch, lds.c);
+        fill_commit<R, MfmaCommitBatch<R>::TB, MfmaCommitBatch<R>::BW, true>(d, d.ntx * d.nty, n_iters, epoch,
+                                                                             lds.c);
         return;
     }
     multi_search(m, (int)blockIdx.x - m.n_commit, epoch, &pk,
