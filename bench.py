@@ -85,7 +85,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="hd", choices=["hd", "vga", "small", "batch", "serve", "sweep", "copy", "resume"])
+    ap.add_argument("--workload", default="hd", choices=["hd", "vga", "small", "big", "batch", "serve", "sweep", "copy", "resume"])
     ap.add_argument("--jobs", type=int, default=128, help="serve: number of jobs")
     ap.add_argument("--workers", type=int, default=1, help="serve: admission worker threads (0: on the loop)")
     ap.add_argument("--graph-iters", type=int, default=16, help="batch / serve: iterations per step")
@@ -119,6 +119,10 @@ def make_job(a):
         return synth.hd(patch=a.patch, window=a.window)
     if a.workload == "vga":
         return synth.vga()
+    if a.workload == "big":
+        # the first serving job: 1992x1221, 7x7 patch, more search tiles than
+        # resident work-groups (the persistent form spreads them)
+        return synth.serving()[0]
     return synth.small()
 
 
@@ -209,7 +213,7 @@ def _cpu_name():
 def golden_check(job, a, log, image, workload=None):
     wl = workload or a.workload
     key = {("hd", 9, False): "hd9", ("hd", 9, True): "hd9w", ("hd", 13, False): "hd13",
-           ("hd", 13, True): "hd13w"}.get((wl, a.patch, a.window), wl)
+           ("hd", 13, True): "hd13w"}.get((wl, a.patch, a.window), "serve00" if wl == "big" else wl)
     path = os.path.join(ROOT, "tests", "golden", f"oracle_{key}.json")
     if not os.path.exists(path):
         return "no stored oracle result"

@@ -206,10 +206,10 @@ int32_t inpaint_find_exemplar(inpaint_ctx *ctx, int32_t target_x, int32_t target
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * query as inpaint_find_exemplar, same arguments, results and errors, but
- * its scratch (target stage, MFMA operands, one partial minimum per search
- * tile, result key) lives in a static device array of the library (about
- * 310 KB, one per GPU, held until the process ends) instead of the context's
- * workspace.  The call allocates nothing.  A search rect that needs more
+ * its scratch (target stage, one partial minimum per search tile, result
+ * key) lives in a static device array of the library (258 KiB, one per GPU,
+ * held until the process ends) instead of the context's workspace.  The
+ * call allocates nothing.  A search rect that needs more
  * than 32768 search tiles (about 67 M candidate centres with the default
  * SIMT tile, 134 M with the MFMA tile) is rejected with INVALID_ARGUMENT.
  * Every call on one GPU shares that GPU's array: calls that overlap on one

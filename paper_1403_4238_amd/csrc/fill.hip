@@ -374,65 +374,6 @@ struct Scratch {
     uint32_t tp[kMaxOffsets + 15];   // the staged target words (column-major slots)
 };
 
-// Writes the int8-MFMA B operands of the target just staged in s.tp /
-// s.mbits (see MfmaFrags), plus T2' = sum of |t - 128|^2, k and the row mask.
-__device__ void build_mfma_frags(int r, Scratch &s, MfmaFrags *f) {
-    const int P = 2 * r + 1;
-    auto known = [&](int slot) { return (s.mbits[slot >> 5] >> (slot & 31)) & 1u; };
-    const int nvec = 4 * P * 64;   // c: 2P x 64, l: P x 64, h: P x 64
-    for (int v = threadIdx.x; v < nvec; v += blockDim.x) {
-        const int lane = v & 63, q = v >> 6, n = lane & 15, g = lane >> 4;
-        int32_t w[4];
-        if (q < 2 * P) {                       // cross term, (dy, h) = (q / 2, q % 2)
-            const int dy = q >> 1, hh = q & 1;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int dxr = 16 * hh + 4 * g + j - n;
-                const int slot = dxr * P + dy;
-                w[j] = (dxr >= 0 && dxr < P && known(slot)) ? (int32_t)(s.tp[slot] ^ 0x00808080u) : 0;
-            }
-            int32_t *dst = f->c[dy][hh][lane];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) dst[j] = w[j];
-        } else {                               // square-term selectors, low (l) or high (h) byte
-            const int qq = q - 2 * P, dy = qq % P, high = qq / P;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                uint32_t m = 0;
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const int dxr = 8 * g + 2 * j + b - n;
-                    if (dxr >= 0 && dxr < P && known(dxr * P + dy)) m |= 1u << (16 * b + 8 * high);
-                }
-                w[j] = (int32_t)m;
-            }
-            int32_t *dst = high ? f->h[dy][lane] : f->l[dy][lane];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) dst[j] = w[j];
-        }
-    }
-    if (threadIdx.x < 64) {
-        int t2 = 0, kk = 0;
-        uint32_t rows = 0;
-        for (int sl = threadIdx.x; sl < P * P; sl += 64)
-            if (known(sl)) {
-                const uint32_t w = s.tp[sl];
-                const int a = (int)(w & 255) - 128, b = (int)((w >> 8) & 255) - 128, c = (int)((w >> 16) & 255) - 128;
-                t2 += a * a + b * b + c * c;
-                kk += 1;
-                rows |= 1u << (sl % P);
-            }
-        t2 = (int)dpp::sum_u32((uint32_t)t2);   // exact: 32-bit wrap-around sums
-        kk = (int)dpp::sum_u32((uint32_t)kk);
-        rows = dpp::or_u32(rows);
-        if (threadIdx.x == 0) {
-            f->t2p = t2;
-            f->k = kk;
-            f->rowmask = rows;
-        }
-    }
-}
-
 // Persistent fill: writes the target just staged (s.tp and the mask words,
 // published by the staging barriers) into every record of the handshake,
 // go words excluded.
@@ -515,7 +456,7 @@ __device__ __forceinline__ void run_bits(const uint32_t *mbits, int w, int mw, i
 // column is unknown or outside the patch, and ends one when the slot below
 // is.  Returns the known count k; T2 = sum of squared known values.
 template <class F>
-__device__ int stage_slots(int r, int tx, int ty, TargetStage *tg, Scratch &s, MfmaFrags *frag, FillSync *recs,
+__device__ int stage_slots(int r, int tx, int ty, TargetStage *tg, Scratch &s, FillSync *recs,
                            F slot) {
     const int P = 2 * r + 1, n = P * P, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t t2 = 0;
@@ -563,17 +504,18 @@ __device__ int stage_slots(int r, int tx, int ty, TargetStage *tg, Scratch &s, M
         tg->k = kk;
         tg->t2 = T2;
     }
-    if (frag || recs) __syncthreads();   // s.sbits / s.ebits
-    if (frag) build_mfma_frags(r, s, frag);
-    if (recs) write_records(recs, s, P, kk, T2);
+    if (recs) {
+        __syncthreads();   // s.sbits / s.ebits
+        write_records(recs, s, P, kk, T2);
+    }
     return kk;
 }
 
 __device__ int stage_target(const JobDev &d, int tx, int ty, int r, TargetStage *tg, Scratch &s,
-                            MfmaFrags *frag, FillSync *recs = nullptr) {
+                            FillSync *recs = nullptr) {
     const int P = 2 * r + 1;
     const GlobalView v{d};
-    return stage_slots(r, tx, ty, tg, s, frag, recs, [&](int t, uint32_t *pix) {
+    return stage_slots(r, tx, ty, tg, s, recs, [&](int t, uint32_t *pix) {
         const int x = tx + t / P - r, y = ty + t % P - r;
         if (!v.known(x, y)) return false;
         *pix = d.img[(int64_t)y * d.W + x] & 0x00ffffffu;
@@ -670,7 +612,7 @@ __device__ void select_and_stage(const JobDev &d, Scratch &s) {
         return;
     }
     const int px = col_of(idx, d.W), py = row_of(idx, d.W);
-    stage_target(d, px, py, d.r, d.tgt, s, d.mfma ? d.frag : nullptr);
+    stage_target(d, px, py, d.r, d.tgt, s);
     if (threadIdx.x == 0) {
         const double2 cd = d.pcd[idx];
         st->p_idx = idx;
@@ -942,10 +884,10 @@ __device__ void refresh_near(const JobDev &d, int px, int py, const Refresh &g, 
 // target (px, py); valid when the whole patch lies inside it.
 template <int R>
 __device__ __forceinline__ int stage_target_lds(const LdsStage<R> &L, int px, int py, int tx, int ty, TargetStage *tg,
-                                                Scratch &s, MfmaFrags *frag, FillSync *recs = nullptr) {
+                                                Scratch &s, FillSync *recs = nullptr) {
     using S = Stage<R>;
     constexpr int P = 2 * R + 1;
-    return stage_slots(R, tx, ty, tg, s, frag, recs, [&](int t, uint32_t *pix) {
+    return stage_slots(R, tx, ty, tg, s, recs, [&](int t, uint32_t *pix) {
         const int i = (ty + t % P - R - py + S::half) * S::side + (tx + t / P - R - px + S::half);
         if (L.st[i] != 0) return false;
         *pix = L.img[i] & 0x00ffffffu;
@@ -1588,17 +1530,17 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
             });
         }
     } else if (adx <= 2 * R + 2 && ady <= 2 * R + 2) {
-        kk = stage_target_lds<R>(L, px, py, tx, ty, d.tgt, s, d.mfma ? d.frag : nullptr, recs);
+        kk = stage_target_lds<R>(L, px, py, tx, ty, d.tgt, s, recs);
     } else if (far && far->idx == idx) {
         // the best pixel of the untouched blocks, copied before this
         // iteration's search ended: its patch is at least 2r + 2 pixels from
         // the filled one, so the copy did not change it
-        kk = stage_slots(R, tx, ty, d.tgt, s, d.mfma ? d.frag : nullptr, recs, [&](int t, uint32_t *pix) {
+        kk = stage_slots(R, tx, ty, d.tgt, s, recs, [&](int t, uint32_t *pix) {
             *pix = far->pix[t];
             return far->known[t] != 0;
         });
     } else {
-        kk = stage_target(d, tx, ty, R, d.tgt, s, d.mfma ? d.frag : nullptr, recs);
+        kk = stage_target(d, tx, ty, R, d.tgt, s, recs);
     }
     if (threadIdx.x == 0) {
         double2 cd;
@@ -1764,10 +1706,9 @@ template <int R, int TB, int BW, bool LEAN>
 __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t epoch, CommitLds<R> &C) {
     Scratch &s = C.s;
     LdsStage<R> &L = C.L;
-    // The search groups build their MFMA operands themselves (the lean
-    // staging builds none); the commit writes the fragments of the staged
-    // target once, at the end.  d is used in place: a copy of it would live
-    // in scratch memory when d0 is not a kernel argument.
+    // (Every MFMA search builds its B-operand tables from the staged words
+    // and known mask.)  d is used in place: a copy of it would live in
+    // scratch memory when d0 is not a kernel argument.
     const JobDev &d = d0;
     bool staged = false;
     FillSync *sy = d.sync;
@@ -1833,7 +1774,6 @@ __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t 
         finish_stage(R, d.tgt, s);
         __syncthreads();
     }
-    if (d0.mfma && staged && v.pending && !v.done && !v.err) build_mfma_frags(R, s, d0.frag);
 }
 
 // Copies record `rec` (published by the go word just observed) into LDS,
@@ -2186,7 +2126,7 @@ __global__ __launch_bounds__(kCommitThreads) void k_commit_batched(const JobDev 
 
 __global__ __launch_bounds__(kCommitThreads) void k_stage_query(JobDev d, int tx, int ty, int r) {
     __shared__ Scratch s;
-    stage_target(d, tx, ty, r, d.qtgt, s, d.mfma && r <= kMfmaMaxRadius ? d.qfrag : nullptr);
+    stage_target(d, tx, ty, r, d.qtgt, s);
 }
 
 __global__ __launch_bounds__(kCommitThreads) void k_reduce_partials(const uint64_t *partials, int n,

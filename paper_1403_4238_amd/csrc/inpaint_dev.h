@@ -51,25 +51,6 @@ struct alignas(256) TargetStage {
     uint32_t tpix[kMaxOffsets + 15];
 };
 
-// B operands of the int8-MFMA search for one staged target, in the exact
-// per-lane register layout of v_mfma_i32_16x16x64_i8 (16 bytes per lane):
-// lane (n = lane % 16, g = lane / 16) of
-//   c[dy][h]: target words t ^ 0x00808080 of patch pixels x = 16h + 4g + j,
-//             j = 0..3, of row dy, for candidate column n (banded Toeplitz);
-//   l[dy], h[dy]: 0/1 bytes selecting the low / high byte of |s'|^2 of
-//             pixels x = 8g + j, j = 0..7, where the target pixel is known.
-// Built once per target by the commit kernel; every search wave loads them.
-constexpr int kMfmaMaxPatch = 13;
-struct alignas(256) MfmaFrags {
-    int32_t c[kMfmaMaxPatch][2][64][4];
-    int32_t l[kMfmaMaxPatch][64][4];
-    int32_t h[kMfmaMaxPatch][64][4];
-    int32_t t2p;        // sum over known pixels of |t - 128|^2
-    int32_t k;          // known pixels
-    uint32_t rowmask;   // bit dy set if patch row dy has a known pixel
-    int32_t pad[61];
-};
-
 // One fill-iteration record, same layout as inpaint_step_info.
 struct StepRec {
     int64_t target_index, source_index;
@@ -163,8 +144,6 @@ struct JobDev {
                          // with INTERSECT scoring 1 on source pixels, 0 elsewhere
     uint8_t *hdist;      // CURRENT policy with WHOLE scoring: per pixel, the horizontal distance
                          // (capped at 10) to the nearest hole or out-of-image pixel of its row
-    MfmaFrags *frag;     // MFMA B operands of tgt (when mfma)
-    MfmaFrags *qfrag;    // MFMA B operands of qtgt (when mfma)
     IterState *st;
     FillSync *sync;
     uint64_t *fslot;     // one slot word per search tile
@@ -235,6 +214,10 @@ bool mfma_supported(int r);
 hipError_t launch_search_mfma(const JobDev &d, bool query, int r, int rx0, int ry0, int rx1, int ry1, int ntx, int nty,
                               hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 hipError_t launch_mfma_planes(const JobDev &d, hipStream_t s);
+// The batch's search over a static (slot, tile) list on the matrix cores;
+// each slot carries the MFMA tiling.
+hipError_t launch_search_batched_mfma(const JobDev *slots, const WorkItem *items, const int32_t *nitems, int r,
+                                      int grid, hipStream_t s);
 hipError_t launch_stage_query(const JobDev &d, int tx, int ty, int r, hipStream_t s);
 hipError_t launch_reduce_partials(const JobDev &d, int ntiles, uint64_t *out, hipStream_t s);
 hipError_t launch_commit_batched(const JobDev *slots, const int32_t *ids, const int32_t *n, int grid, int r,
@@ -258,12 +241,11 @@ hipError_t launch_fill_multi(const MultiPlan &m, bool mfma, int r, int grid, int
 inline int search_tile_h(int tile_rows) { return kSearchWaves * tile_rows; }
 
 // Allocation-free query (inpaint_find_exemplar_static): its target stage,
-// MFMA operands, per-tile partial minima and result key live in one static
-// device array of kStaticScratchBytes per GPU instead of the workspace.
+// per-tile partial minima and result key live in one static device array of
+// kStaticScratchBytes per GPU instead of the workspace.
 constexpr int kStaticMaxTiles = 32768;
 constexpr uint64_t kStaticStageOff = 0;
-constexpr uint64_t kStaticFragOff = (sizeof(TargetStage) + 255) / 256 * 256;
-constexpr uint64_t kStaticKeyOff = kStaticFragOff + (sizeof(MfmaFrags) + 255) / 256 * 256;
+constexpr uint64_t kStaticKeyOff = (sizeof(TargetStage) + 255) / 256 * 256;
 constexpr uint64_t kStaticPartialsOff = kStaticKeyOff + 256;
 constexpr uint64_t kStaticScratchBytes = kStaticPartialsOff + 8ull * kStaticMaxTiles;
 // Takes the array's device address on `device`, which must be current

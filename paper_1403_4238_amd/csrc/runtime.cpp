@@ -82,7 +82,7 @@ bool sealed(const InitInfo &info, uint32_t nonce, uint32_t blocks) {
 }
 
 struct Layout {
-    uint64_t img, gray, hole, hole0, vrad, conf, pcd, blk, partials, tgt, qtgt, frag, qfrag, srcw, srcq, srcp, vradp, hdist, st,
+    uint64_t img, gray, hole, hole0, vrad, conf, pcd, blk, partials, tgt, qtgt, srcw, srcq, srcp, vradp, hdist, st,
         sync, fslot, info, key, mplan, log, total;
     int64_t log_cap;
     int max_tiles;
@@ -118,8 +118,6 @@ Layout make_layout(int W, int H, const inpaint_params &p) {
     L.tgt = take(sizeof(TargetStage));
     L.qtgt = take(sizeof(TargetStage));
     const bool mfma = p.path == INPAINT_PATH_MFMA;
-    L.frag = mfma ? take(sizeof(MfmaFrags)) : 0;
-    L.qfrag = mfma ? take(sizeof(MfmaFrags)) : 0;
     const uint64_t np = (uint64_t)padded_pitch(W) * padded_rows(H);
     L.srcw = mfma ? take(4 * np) : 0;
     L.srcq = mfma ? take(2 * np) : 0;
@@ -479,8 +477,6 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     d.tgt = (TargetStage *)(ws + L.tgt);
     d.qtgt = (TargetStage *)(ws + L.qtgt);
     d.mfma = p->path == INPAINT_PATH_MFMA ? 1 : 0;
-    d.frag = d.mfma ? (MfmaFrags *)(ws + L.frag) : nullptr;
-    d.qfrag = d.mfma ? (MfmaFrags *)(ws + L.qfrag) : nullptr;
     d.srcw = d.mfma ? (uint32_t *)(ws + L.srcw) : nullptr;
     d.srcq = d.mfma ? (uint16_t *)(ws + L.srcq) : nullptr;
     d.srcp = (uint32_t *)(ws + L.srcp);
@@ -669,7 +665,6 @@ int32_t inpaint_find_exemplar_static(inpaint_ctx *ctx, int32_t tx, int32_t ty, i
         return ctx->fail(INPAINT_INVALID_ARGUMENT, "search rect needs more than " + std::to_string(kStaticMaxTiles) +
                                                        " search tiles (the static scratch limit)");
     q.qtgt = (TargetStage *)(base + kStaticStageOff);
-    q.qfrag = (MfmaFrags *)(base + kStaticFragOff);
     q.partials = (uint64_t *)(base + kStaticPartialsOff);
     uint64_t *dkey = (uint64_t *)(base + kStaticKeyOff);
     hipStream_t s = ctx->stream;
@@ -1017,7 +1012,8 @@ namespace {
 
 struct TuneChoice {
     int tile_rows = kDefaultTileRows;
-    int grid = 0;   // 0 = one work-group per item
+    int grid = 0;     // 0 = one work-group per item
+    int engine = 0;   // search engine: 0 SIMT (dot4), 1 int8 MFMA (contexts with the MFMA planes)
 };
 
 struct RadiusGroup {
@@ -1040,7 +1036,7 @@ std::string device_key() {
     return std::string(prop.gcnArchName) + "-cu" + std::to_string(prop.multiProcessorCount);
 }
 
-// Minimal flat JSON cache: {"key": [tile_rows, grid], ...}
+// Minimal flat JSON cache: {"key": [tile_rows, grid, engine], ...}
 std::map<std::string, TuneChoice> read_cache(const char *path) {
     std::map<std::string, TuneChoice> m;
     if (!path) return m;
@@ -1057,7 +1053,8 @@ std::map<std::string, TuneChoice> read_cache(const char *path) {
         if (end == std::string::npos) break;
         const std::string key = s.substr(pos + 1, end - pos - 1);
         TuneChoice t;
-        if (std::sscanf(s.c_str() + end + 1, " : [ %d , %d ]", &t.tile_rows, &t.grid) == 2 && tile_rows_ok(t.tile_rows))
+        if (std::sscanf(s.c_str() + end + 1, " : [ %d , %d , %d ]", &t.tile_rows, &t.grid, &t.engine) == 3 &&
+            tile_rows_ok(t.tile_rows) && (t.engine == 0 || t.engine == 1))
             m[key] = t;
         pos = end + 1;
     }
@@ -1072,8 +1069,8 @@ void write_cache(const char *path, const std::map<std::string, TuneChoice> &m) {
     std::fprintf(f, "{\n");
     size_t i = 0;
     for (const auto &kv : m)
-        std::fprintf(f, "  \"%s\": [%d, %d]%s\n", kv.first.c_str(), kv.second.tile_rows, kv.second.grid,
-                     ++i < m.size() ? "," : "");
+        std::fprintf(f, "  \"%s\": [%d, %d, %d]%s\n", kv.first.c_str(), kv.second.tile_rows, kv.second.grid,
+                     kv.second.engine, ++i < m.size() ? "," : "");
     std::fprintf(f, "}\n");
     std::fclose(f);
     std::rename(tmp.c_str(), path);
@@ -1126,10 +1123,24 @@ hipError_t upload_slot(inpaint_batch *b, int i) {
     return hipMemcpyAsync(b->d_slots + i, b->h_slots + i, sizeof(JobDev), hipMemcpyHostToDevice, b->stream);
 }
 
-JobDev slot_desc(const inpaint_ctx *c, int tile_rows) {
+// Graph-form groups: the images of one radius searched by the same kernel,
+// keyed r, or r + kMfmaGroup for contexts that carry the MFMA planes (their
+// group may search on the matrix cores, if the autotuner finds it faster).
+constexpr int kMfmaGroup = 16;
+int group_key(const inpaint_ctx *c) { return c->d.r + (c->mfma && mfma_supported(c->d.r) ? kMfmaGroup : 0); }
+bool key_mfma(int key) { return key >= kMfmaGroup; }
+int key_r(int key) { return key % kMfmaGroup; }
+
+JobDev slot_desc(const inpaint_ctx *c, const TuneChoice &t) {
     JobDev d = c->d;
-    set_tiles(d, tile_rows);
+    if (t.engine == 1) set_tiles(d, kMfmaTileRows, c->d.r);
+    else set_tiles(d, t.tile_rows);
     return d;
+}
+
+hipError_t launch_group_search(const inpaint_batch *b, int key, const RadiusGroup &g, int grid, hipStream_t s) {
+    if (g.tune.engine == 1) return launch_search_batched_mfma(b->d_slots, g.d_items, g.d_n, key_r(key), grid, s);
+    return launch_search_batched(b->d_slots, g.d_items, g.d_n, key_r(key), g.tune.tile_rows, grid, s);
 }
 
 hipError_t upload_group(inpaint_batch *b, RadiusGroup &g) {
@@ -1167,9 +1178,9 @@ hipError_t rebuild(inpaint_batch *b) {
     for (size_t i = 0; i < b->slots.size(); ++i) {
         inpaint_ctx *c = b->slots[i];
         if (!c) continue;
-        RadiusGroup &g = b->groups[c->d.r];
+        RadiusGroup &g = b->groups[group_key(c)];
         g.ids.push_back((int32_t)i);
-        b->h_slots[i] = slot_desc(c, g.tune.tile_rows);
+        b->h_slots[i] = slot_desc(c, g.tune);
         const int nt = b->h_slots[i].ntx * b->h_slots[i].nty;
         for (int t = 0; t < nt; ++t) g.items.push_back(WorkItem{(int32_t)i, t});
         hipError_t e = upload_slot(b, (int)i);
@@ -1196,14 +1207,12 @@ int grid_for(const inpaint_batch *b, const RadiusGroup &g) {
 // device, so the captured graph stays valid while slots come and go.
 hipError_t enqueue_batch_iteration(inpaint_batch *b, hipStream_t s) {
     for (auto &kv : b->groups) {
-        RadiusGroup &g = kv.second;
-        hipError_t e = launch_search_batched(b->d_slots, g.d_items, g.d_n, kv.first, g.tune.tile_rows,
-                                             grid_for(b, g), s);
+        hipError_t e = launch_group_search(b, kv.first, kv.second, grid_for(b, kv.second), s);
         if (e != hipSuccess) return e;
     }
     for (auto &kv : b->groups) {
         hipError_t e = launch_commit_batched(b->d_slots, kv.second.d_ids, kv.second.d_n + 1,
-                                             (int)b->slots.size(), kv.first, s);
+                                             (int)b->slots.size(), key_r(kv.first), s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1212,13 +1221,14 @@ hipError_t enqueue_batch_iteration(inpaint_batch *b, hipStream_t s) {
 // Times the batched search of one radius group for each tile shape and
 // persistent grid size, keeps the fastest.  The searches only rewrite the
 // images' partial results, which every real search rewrites before use.
-hipError_t autotune_group(inpaint_batch *b, int r, RadiusGroup &g, std::map<std::string, TuneChoice> &cache) {
+hipError_t autotune_group(inpaint_batch *b, int gkey, RadiusGroup &g, std::map<std::string, TuneChoice> &cache) {
     int64_t pixels = 0;
     for (auto *c : b->slots)
-        if (c && c->d.r == r) pixels += (int64_t)(c->d.rx1 - c->d.rx0) * (c->d.ry1 - c->d.ry0);
+        if (c && group_key(c) == gkey) pixels += (int64_t)(c->d.rx1 - c->d.rx0) * (c->d.ry1 - c->d.ry0);
     int lg = 0;
     while ((1ll << (lg + 1)) <= pixels) ++lg;
-    const std::string key = device_key() + "/r" + std::to_string(r) + "/px2^" + std::to_string(lg);
+    const std::string key = device_key() + "/r" + std::to_string(key_r(gkey)) + (key_mfma(gkey) ? "/mfma" : "") +
+                            "/px2^" + std::to_string(lg);
     auto it = cache.find(key);
     if (it != cache.end()) {
         g.tune = it->second;
@@ -1230,7 +1240,13 @@ hipError_t autotune_group(inpaint_batch *b, int r, RadiusGroup &g, std::map<std:
     hipEventCreate(&e1);
     float best_ms = 1e30f;
     TuneChoice best = g.tune;
-    for (int rows : {4, 8, 16}) {
+    // (engine, tile rows): the SIMT tile shapes, and the MFMA tile (one
+    // shape, only its grid is tuned) where the contexts carry its planes
+    std::vector<std::pair<int, int>> shapes = {{0, 4}, {0, 8}, {0, 16}};
+    if (key_mfma(gkey)) shapes.push_back({1, kMfmaTileRows});
+    for (const auto &shape : shapes) {
+        const int rows = shape.second;
+        g.tune.engine = shape.first;
         g.tune.tile_rows = rows;
         g.tune.grid = 0;
         hipError_t e = rebuild(b);
@@ -1242,7 +1258,7 @@ hipError_t autotune_group(inpaint_batch *b, int r, RadiusGroup &g, std::map<std:
             float ms_min = 1e30f;
             for (int rep = 0; rep < 3; ++rep) {
                 hipEventRecord(e0, b->stream);
-                e = launch_search_batched(b->d_slots, g.d_items, g.d_n, r, rows, grid_for(b, g), b->stream);
+                e = launch_group_search(b, gkey, g, grid_for(b, g), b->stream);
                 hipEventRecord(e1, b->stream);
                 if (e == hipSuccess) e = hipEventSynchronize(e1);
                 if (e != hipSuccess) return e;
@@ -1424,8 +1440,8 @@ int32_t inpaint_batch_attach(inpaint_batch *b, inpaint_ctx *ctx, int32_t *slot) 
     b->slots[i] = ctx;
     ((int32_t *)(b->h_active + 1))[i] = ctx->h_state->done ? INPAINT_SLOT_FINISHED : INPAINT_SLOT_RUNNING;
     ctx->batch = b;
-    if (b->groups.find(ctx->d.r) == b->groups.end()) b->graph_sig.clear();
-    b->groups[ctx->d.r];
+    if (b->groups.find(group_key(ctx)) == b->groups.end()) b->graph_sig.clear();
+    b->groups[group_key(ctx)];
     b->dirty = true;
     if (slot) *slot = i;
     return INPAINT_OK;
@@ -1528,7 +1544,8 @@ int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active) {
     }
     std::string sig = std::to_string(G);
     for (auto &kv : b->groups)
-        sig += "|" + std::to_string(kv.first) + ":" + std::to_string(kv.second.tune.tile_rows) + ":" +
+        sig += "|" + std::to_string(kv.first) + ":" + std::to_string(kv.second.tune.engine) + ":" +
+               std::to_string(kv.second.tune.tile_rows) + ":" +
                std::to_string(grid_for(b, kv.second));
     if (sig != b->graph_sig || !b->graph) {
         if (b->graph) hipGraphExecDestroy(b->graph);

@@ -43,33 +43,6 @@ struct MfmaTile {
     alignas(16) uint8_t q[MfmaGeom<R>::ROWS * kMfmaStrideQ + 32];  // (lo', hi') per pixel
 };
 
-// The B operands of one target in the v_mfma_i32_16x16x64_i8 register
-// layout (see MfmaFrags) plus T2' = sum of |t - 128|^2, k and the mask of
-// patch rows holding a known pixel.
-template <int R>
-struct BFrags {
-    static constexpr int P = 2 * R + 1;
-    v4i c[P][2], l[P], h[P];
-    int t2p, k;
-    uint32_t rowmask;
-};
-
-// From the fragments the commit kernel wrote.
-template <int R>
-__device__ __forceinline__ void load_frags(const MfmaFrags *fr, BFrags<R> &b) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int dy = 0; dy < 2 * R + 1; ++dy) {
-        b.c[dy][0] = *(const v4i *)fr->c[dy][0][lane];
-        b.c[dy][1] = *(const v4i *)fr->c[dy][1][lane];
-        b.l[dy] = *(const v4i *)fr->l[dy][lane];
-        b.h[dy] = *(const v4i *)fr->h[dy][lane];
-    }
-    b.t2p = fr->t2p;
-    b.k = fr->k;
-    b.rowmask = fr->rowmask;
-}
-
 // Per-target tables a work-group builds in LDS, from which every wave reads
 // its B operands with a few aligned LDS loads.  With T(dy, x) the target
 // word (RGB ^ 0x808080) at patch column x of row dy where known, 0 elsewhere
@@ -145,35 +118,6 @@ __device__ __forceinline__ void build_tables(FragTables<R> *ft) {
     }
 }
 
-// After a barrier that publishes the tables.
-template <int R>
-__device__ __forceinline__ void load_frags(const FragTables<R> *ft, BFrags<R> &b) {
-    constexpr int P = 2 * R + 1;
-    const int lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4, s = n & 3;
-#pragma unroll
-    for (int dy = 0; dy < P; ++dy) {
-#pragma unroll
-        for (int hh = 0; hh < 2; ++hh) b.c[dy][hh] = *(const v4i *)&ft->tc[s][dy][16 * hh + 4 * g + 16 - 4 * (n >> 2)];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t w = ft->lw[dy][8 * g + 2 * j - n + 16];
-            b.l[dy][j] = (int)w;
-            b.h[dy][j] = (int)(w << 8);
-        }
-    }
-    int t2 = 0, kk = 0;
-    uint32_t rows = 0;
-#pragma unroll
-    for (int w = 0; w < kSearchWaves; ++w) {
-        t2 += ft->t2p[w];
-        kk += ft->k[w];
-        rows |= ft->rowmask[w];
-    }
-    b.t2p = __builtin_amdgcn_readfirstlane(t2);
-    b.k = __builtin_amdgcn_readfirstlane(kk);
-    b.rowmask = __builtin_amdgcn_readfirstlane(rows);
-}
-
 // First tile column and row of tile `tile` of the MFMA tiling of the rect.
 template <int R>
 __device__ __forceinline__ void tile_origin(int rx0, int ry0, int ntx, int tile, int *tx0, int *ty0) {
@@ -242,65 +186,11 @@ __device__ __forceinline__ uint32_t stage_tile(const JobDev &d, int tx0, int ty0
 }
 
 // Scores this lane's candidates of a staged tile and returns their minimum
-// key (~0 if none is valid).
-template <int R>
-__device__ __forceinline__ uint64_t score_tile(const JobDev &d, const BFrags<R> &b, int tx0, int ty0, uint32_t vmask,
-                                               const MfmaTile<R> &L) {
-    constexpr int P = 2 * R + 1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int n = lane & 15, g = lane >> 4;
-    const int W = d.W, cx = tx0 + 16 * wave + n;
-    const int t2 = b.t2p, kk = b.k;
-    const uint32_t rowmask = b.rowmask;
-    uint64_t best = ~0ull;
-    (void)rowmask;
-#pragma unroll
-    for (int t = 0; t < kMfmaTilesPerWave; ++t) {
-        // four independent accumulation chains keep the MFMA pipeline busy
-        v4i c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0}, ch = {0, 0, 0, 0}, cl = {0, 0, 0, 0};
-        // Every patch row is multiplied (a row without a known pixel has
-        // zero B operands): without a branch per row the A loads of row
-        // dy + 1 are in flight while row dy is on the matrix cores.
-        const int base = (16 * t + n) * kMfmaStrideA + 16 * wave + 4 * g;
-        const int qbase = (16 * t + n) * kMfmaStrideQ + 32 * wave + 16 * g;
-        v4i a0 = *(const v4i *)&L.a[base], a1 = *(const v4i *)&L.a[base + 16], aq = *(const v4i *)&L.q[qbase];
-#pragma unroll
-        for (int dy = 0; dy < P; ++dy) {
-            v4i n0 = a0, n1 = a1, nq = aq;   // A row = candidate row n + dy + 1 of the tile
-            if (dy + 1 < P) {
-                n0 = *(const v4i *)&L.a[base + (dy + 1) * kMfmaStrideA];
-                n1 = *(const v4i *)&L.a[base + (dy + 1) * kMfmaStrideA + 16];
-                nq = *(const v4i *)&L.q[qbase + (dy + 1) * kMfmaStrideQ];
-            }
-            c0 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a0, b.c[dy][0], c0, 0, 0, 0);
-            c1 = __builtin_amdgcn_mfma_i32_16x16x64_i8(a1, b.c[dy][1], c1, 0, 0, 0);
-            cl = __builtin_amdgcn_mfma_i32_16x16x64_i8(aq, b.l[dy], cl, 0, 0, 0);
-            ch = __builtin_amdgcn_mfma_i32_16x16x64_i8(aq, b.h[dy], ch, 0, 0, 0);
-            a0 = n0;
-            a1 = n1;
-            aq = nq;
-        }
-        // C lane (n, g) holds rows 4g + i of column n.
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (vmask & (1u << (4 * t + i))) {
-                const int s2 = 256 * (ch[i] + 128 * kk) + cl[i] + 128 * kk;
-                const uint32_t ssd = (uint32_t)(t2 - 2 * (c0[i] + c1[i]) + s2);
-                const int y = ty0 + 16 * t + 4 * g + i;
-                const uint64_t key = ((uint64_t)ssd << 32) | (uint32_t)(y * W + cx);
-                best = key < best ? key : best;
-            }
-        }
-    }
-    return best;
-}
-
-// The same scoring with the B operands read from the per-target tables in
-// LDS one patch row at a time (rows outer, the four 16-row blocks inner):
-// only one row's B operands and the 16 accumulators are live, not the B
-// operands of every row, so the register budget no longer grows with the
-// patch size, and the 16 independent accumulation chains keep the matrix
-// cores busy.  Same arithmetic and result as score_tile.
+// key (~0 if none is valid).  The B operands are read from the per-target
+// tables in LDS one patch row at a time (rows outer, the four 16-row blocks
+// inner): only one row's B operands and the 16 accumulators are live, so
+// the register budget does not grow with the patch size, and the 16
+// independent accumulation chains keep the matrix cores busy.
 template <int R>
 __device__ __forceinline__ uint64_t score_tile_rows(const JobDev &d, const FragTables<R> *ft, int tx0, int ty0,
                                                     uint32_t vmask, const MfmaTile<R> &L) {
