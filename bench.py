@@ -88,7 +88,13 @@ def parse():
     ap.add_argument("--workload", default="hd", choices=["hd", "vga", "small", "big", "batch", "serve", "sweep", "copy", "resume"])
     ap.add_argument("--jobs", type=int, default=128, help="serve: number of jobs")
     ap.add_argument("--workers", type=int, default=1, help="serve: admission worker threads (0: on the loop)")
-    ap.add_argument("--graph-iters", type=int, default=16, help="batch / serve: iterations per step")
+    ap.add_argument("--graph-iters", type=int, default=16, help="batch: iterations per step")
+    ap.add_argument("--serve-iters", type=int, default=128, help="serve: iterations per batch step")
+    ap.add_argument("--serve-form", default="persistent", choices=["persistent", "graph", "auto"],
+                    help="serve: batch form")
+    ap.add_argument("--tiles-per-group", type=int, default=0,
+                    help="serve: attach a job only while the running jobs' search tiles fit this many per "
+                         "search work-group (0: whenever a slot is free)")
     ap.add_argument("--batch-form", default="auto", choices=["auto", "persistent", "graph"],
                     help="batch: form of the batch steps")
     ap.add_argument("--capacity", type=int, default=16, help="serve: batch slots")
@@ -472,9 +478,10 @@ def serve_bench(a):
     budget = int(a.budget_gb * (1 << 30))
 
     def run(js, keep=False):
-        eng = serve.GpuEngine(capacity=a.capacity, graph_iters=a.graph_iters, autotune=True, log=keep,
+        eng = serve.GpuEngine(capacity=a.capacity, graph_iters=a.serve_iters, autotune=True, log=keep,
+                              form=a.serve_form, tiles_per_group=a.tiles_per_group,
                               path=a.path)
-        srv = serve.Server(eng, budget, a.capacity, a.graph_iters, keep_results=True, workers=a.workers)
+        srv = serve.Server(eng, budget, a.capacity, a.serve_iters, keep_results=True, workers=a.workers)
         torch.cuda.synchronize()
         recs = srv.run(js)
         torch.cuda.synchronize()
@@ -535,7 +542,8 @@ def serve_bench(a):
         "data": "synthetic (seeded)",
         "config": {"workload": f"{len(jobs)} removal jobs, RGB u8 256x256..2048x1536, holes 1-10% (1-3 blobs), "
                                "patch 7/9/11, full search; admission by workspace bytes "
-                               f"(budget {a.budget_gb} GiB), {a.capacity} slots, G={a.graph_iters}, "
+                               f"(budget {a.budget_gb} GiB), {a.capacity} slots, {a.serve_form} form, G={a.serve_iters}, "
+                               f"tiles per search group {a.tiles_per_group or 'unbounded'}, "
                                f"{a.workers} admission worker(s), {a.path} search",
                    "rate_jobs_per_s": round(rate, 3), "fixed_rate_jobs_per_s": 20.0},
         "poisson": poisson, "fixed_rate": fixed, "saturation": sat,

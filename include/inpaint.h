@@ -367,6 +367,15 @@ int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active);
  * ran in. */
 int32_t inpaint_batch_form(const inpaint_batch *b, int32_t *form);
 
+/* *room = 1 when the batch's running images together with ctx (not yet
+ * attached) fit the persistent form with at most tiles_per_group search
+ * tiles per search work-group of each batched dispatch (1: every tile stays
+ * resident in LDS), else 0.  A scheduler that attaches only while this holds
+ * bounds how far sharing slows each image below its solo iteration time.
+ * No device work.  INVALID_ARGUMENT for NULL arguments, an attached ctx or
+ * tiles_per_group outside 1 .. 64. */
+int32_t inpaint_batch_room(inpaint_batch *b, const inpaint_ctx *ctx, int32_t tiles_per_group, int32_t *room);
+
 /* State of a slot as of the end of the last inpaint_batch_step:
  * 0 empty, 1 running, 2 finished (hole empty), 3 device error.  No device
  * work. */

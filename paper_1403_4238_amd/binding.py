@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
         "inpaint_batch_detach": (i32, [vp, vp]),
         "inpaint_batch_step": (i32, [vp, i32, P(i64)]),
         "inpaint_batch_form": (i32, [vp, P(i32)]),
+        "inpaint_batch_room": (i32, [vp, vp, i32, P(i32)]),
         "inpaint_batch_destroy": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -359,6 +360,16 @@ class Batch:
         if st != OK:
             raise InpaintError(st, "inpaint_batch_form")
         return {v: k for k, v in FORMS.items()}[out.value]
+
+    def room(self, job: Inpainter, tiles_per_group: int = 1) -> bool:
+        """Whether the running images and ``job`` (not attached) fit the
+        persistent form with at most ``tiles_per_group`` search tiles per
+        search work-group (1: every tile resident)."""
+        out = ctypes.c_int32()
+        st = lib().inpaint_batch_room(self.h, job.ctx, int(tiles_per_group), ctypes.byref(out))
+        if st != OK:
+            raise InpaintError(st, "inpaint_batch_room")
+        return bool(out.value)
 
     def step(self, G: int | None = None) -> int:
         active = ctypes.c_int64()

@@ -2097,6 +2097,57 @@ __global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(
                  });
 }
 
+// The MFMA form for jobs of several radii in one dispatch: the LDS of the
+// largest radius; each committer takes its job's radius, and each search
+// group the radius of its items (the plan gives a search group items of one
+// radius only), so every work-group runs the per-radius code of its own
+// radius for the whole dispatch.
+union MixLdsMfma {
+    FillLdsMfma<1> r1;
+    FillLdsMfma<2> r2;
+    FillLdsMfma<3> r3;
+    FillLdsMfma<4> r4;
+    FillLdsMfma<5> r5;
+};
+static_assert(kMultiMixMaxR == 5, "MixLdsMfma holds radii 1..5");
+
+template <int R>
+__device__ __forceinline__ void mixed_role(const MultiPlan &m, int n_iters, uint32_t epoch, FillLdsMfma<R> &lds,
+                                           MultiPick *pk) {
+    if ((int)blockIdx.x < m.n_commit) {
+        const JobDev d = m.slots[m.commit[blockIdx.x]];   // by value, see k_fill_multi_mfma
+        fill_commit<R, MfmaCommitBatch<R>::TB, MfmaCommitBatch<R>::BW, true>(d, d.ntx * d.nty, n_iters, epoch,
+                                                                             lds.c);
+        return;
+    }
+    multi_search(m, (int)blockIdx.x - m.n_commit, epoch, pk,
+                 [&](const JobDev &d, int t, uint32_t k, bool restage, uint32_t &vmask, bool &anyv)
+                     __attribute__((always_inline)) { multi_serve_mfma<R>(d, t, k, restage, lds.s, vmask, anyv); });
+}
+
+__global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_fill_multi_mfma_mixed(
+    MultiPlan m, int n_iters, uint32_t epoch) {
+    __shared__ MixLdsMfma lds;
+    __shared__ MultiPick pk;
+    // this work-group's radius: its job's, or its first item's (a search
+    // group without items has nothing to serve)
+    int r = 0;
+    if ((int)blockIdx.x < m.n_commit) {
+        r = m.slots[m.commit[blockIdx.x]].r;
+    } else {
+        const int w = (int)blockIdx.x - m.n_commit;
+        if (m.first[w + 1] > m.first[w]) r = m.slots[m.items[m.first[w]].slot].r;
+    }
+    switch (r) {
+        case 1: mixed_role<1>(m, n_iters, epoch, lds.r1, &pk); break;
+        case 2: mixed_role<2>(m, n_iters, epoch, lds.r2, &pk); break;
+        case 3: mixed_role<3>(m, n_iters, epoch, lds.r3, &pk); break;
+        case 4: mixed_role<4>(m, n_iters, epoch, lds.r4, &pk); break;
+        case 5: mixed_role<5>(m, n_iters, epoch, lds.r5, &pk); break;
+        default: break;   // no items; the host plan holds only radii 1 .. 5
+    }
+}
+
 template <int R, bool ISECT>
 __global__ __launch_bounds__(kCommitThreads) void k_commit(JobDev d) {
     __shared__ Scratch s;
@@ -2296,6 +2347,7 @@ hipError_t launch_fill(const JobDev &d, int ntiles, int n_iters, uint32_t epoch,
 static const void *fill_multi_kernel(bool mfma, int r) {
     if (mfma) {
         switch (r) {
+            case kMultiMixed: return (const void *)k_fill_multi_mfma_mixed;
             case 1: return (const void *)k_fill_multi_mfma<1>;
             case 2: return (const void *)k_fill_multi_mfma<2>;
             case 3: return (const void *)k_fill_multi_mfma<3>;

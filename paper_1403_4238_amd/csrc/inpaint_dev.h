@@ -233,7 +233,11 @@ hipError_t launch_fill(const JobDev &d, int ntiles, int n_iters, uint32_t epoch,
 // Batched persistent fill: up to n_iters iterations of every job of the plan
 // (all of patch radius r) in one persistent dispatch of `grid` = n_commit +
 // search groups.  MFMA: r <= 6, the int8-MFMA tiling; SIMT: the SIMT tiling
-// of kFillTileRows.
+// of kFillTileRows.  MFMA with r = kMultiMixed: one dispatch for jobs of any
+// radius up to kMultiMixMaxR, each committer and each served item taking
+// its job's radius.
+constexpr int kMultiMixed = 0;
+constexpr int kMultiMixMaxR = 5;
 hipError_t multi_blocks_per_cu(bool mfma, int r, int *blocks);
 hipError_t launch_fill_multi(const MultiPlan &m, bool mfma, int r, int grid, int n_iters, uint32_t epoch,
                              hipStream_t s);

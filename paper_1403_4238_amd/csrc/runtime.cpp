@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <set>
 #include <mutex>
 #include <shared_mutex>
 #include <string>
@@ -340,6 +341,55 @@ static void spread_items(const std::vector<WorkItem> &all, int n_search, std::ve
     items->resize(all.size());
     std::vector<int32_t> pos(first->begin(), first->end() - 1);
     for (size_t i = 0; i < all.size(); ++i) (*items)[pos[i % n_search]++] = all[i];
+}
+
+// spread_items for a dispatch whose jobs have several radii: every search
+// group gets items of one radius only.  The groups are shared out among the
+// radii in proportion to their items (each radius at least one; every item
+// its own group when all fit), then each radius spreads its items over its
+// groups.  radius[i]: the radius of all[i]'s job.  Returns false when there
+// are more radii than groups.
+static bool spread_items_by_radius(const std::vector<WorkItem> &all, const std::vector<int> &radius, int n_search,
+                                   std::vector<WorkItem> *items, std::vector<int32_t> *first) {
+    std::map<int, std::vector<WorkItem>> by_r;
+    for (size_t i = 0; i < all.size(); ++i) by_r[radius[i]].push_back(all[i]);
+    const int nr = (int)by_r.size();
+    if (nr > n_search) return false;
+    std::vector<int> groups;
+    if ((int64_t)all.size() <= n_search) {
+        for (auto &kv : by_r) groups.push_back((int)kv.second.size());
+    } else {
+        // largest remainders after a floor of max(1, proportional share)
+        std::vector<std::pair<double, int>> rem;
+        int used = 0, k = 0;
+        for (auto &kv : by_r) {
+            const double share = (double)n_search * kv.second.size() / all.size();
+            const int g = std::max(1, (int)share);
+            groups.push_back(g);
+            used += g;
+            rem.push_back({share - g, k++});
+        }
+        std::sort(rem.begin(), rem.end(), [](auto &x, auto &y) { return x.first > y.first || (x.first == y.first && x.second < y.second); });
+        for (size_t q = 0; used < n_search; q = (q + 1) % rem.size(), ++used) groups[rem[q].second] += 1;
+        while (used > n_search) {   // the floors of 1 overshot: take from the largest
+            const int big = (int)(std::max_element(groups.begin(), groups.end()) - groups.begin());
+            groups[big] -= 1;
+            used -= 1;
+        }
+    }
+    items->clear();
+    first->assign(1, 0);
+    int k = 0;
+    for (auto &kv : by_r) {
+        std::vector<WorkItem> its;
+        std::vector<int32_t> fst;
+        spread_items(kv.second, groups[k++], &its, &fst);
+        const int32_t base = first->back();
+        for (size_t w = 1; w < fst.size(); ++w) first->push_back(base + fst[w]);
+        items->insert(items->end(), its.begin(), its.end());
+    }
+    while ((int)first->size() < n_search + 1) first->push_back(first->back());   // idle groups
+    return true;
 }
 
 // Co-resident work-groups of the batched persistent kernel on this device.
@@ -1109,7 +1159,7 @@ struct inpaint_batch {
     std::string graph_sig;
     int cu_count = 256;
     // batched persistent form
-    std::vector<MultiBuf> mbufs;   // one per (form, radius) group of running jobs
+    std::vector<MultiBuf> mbufs;   // one per dispatch group of running jobs (mixed MFMA radii, or form and radius)
     std::string multi_sig;         // running slots the uploaded plans were built for
     std::string nofit_sig;         // running slots that did not fit one dispatch
     std::map<std::pair<int, int>, int> mcap;   // co-resident groups per (form, radius)
@@ -1291,66 +1341,105 @@ hipError_t grow(T **p, size_t *cap, size_t n) {
 
 bool multi_form(const inpaint_ctx *c) { return c->mfma && mfma_supported(c->d.r); }
 
-// Plans the batched persistent dispatches of the running jobs: one per
-// (search form, radius) group, its committers first, then every remaining
-// co-resident work-group searching.  Uploads the slot table with each job's
-// persistent tiling.  *fits = false when a group does not fit one dispatch
-// (the batch then steps in the graph form).  max_items: search items per
-// search group allowed (1: every tile stays in LDS for the whole dispatch).
+// A job's JobDev with the tiling of the batched persistent search.
+static JobDev multi_desc(const inpaint_ctx *c) {
+    JobDev d = c->d;
+    set_tiles(d, multi_form(c) ? kMfmaTileRows : kFillTileRows, multi_form(c) ? c->d.r : 0);
+    return d;
+}
+
+// One batched persistent dispatch: its kernel (form, radius or kMultiMixed),
+// search groups, jobs (batch slots) and (slot, tile) items with their radii.
+struct MultiGroupPlan {
+    bool mfma;
+    int r, n_search;
+    std::vector<int> jobs;
+    std::vector<WorkItem> all;
+    std::vector<int> radius;
+};
+
+// Splits jobs (slot, context) into batched persistent dispatches: the
+// MFMA-form jobs of radius up to kMultiMixMaxR share one (the mixed-radius
+// kernel) when they have several radii, the others go by (search form,
+// radius).  Each dispatch has its committers first, then every remaining
+// co-resident work-group searching, each with at most max_items items.
+// Returns false when a dispatch does not fit.
+static bool group_multi(inpaint_batch *b, const std::vector<std::pair<int, const inpaint_ctx *>> &jobs,
+                        int max_items, std::vector<MultiGroupPlan> *plans) {
+    std::set<int> mix_radii;
+    for (const auto &j : jobs)
+        if (multi_form(j.second) && j.second->d.r <= kMultiMixMaxR) mix_radii.insert(j.second->d.r);
+    std::map<std::pair<int, int>, std::vector<std::pair<int, const inpaint_ctx *>>> groups;
+    for (const auto &j : jobs) {
+        const inpaint_ctx *c = j.second;
+        const bool mixed = mix_radii.size() > 1 && multi_form(c) && c->d.r <= kMultiMixMaxR;
+        groups[{multi_form(c) ? 1 : 0, mixed ? kMultiMixed : c->d.r}].push_back(j);
+    }
+    plans->clear();
+    for (auto &kv : groups) {
+        MultiGroupPlan pl{kv.first.first != 0, kv.first.second, 0, {}, {}, {}};
+        auto it = b->mcap.find(kv.first);
+        const int cap = it != b->mcap.end() ? it->second : (b->mcap[kv.first] = multi_capacity(pl.mfma, pl.r));
+        const int n_commit = (int)kv.second.size();
+        pl.n_search = cap - n_commit;
+        for (const auto &j : kv.second) {
+            const JobDev d = multi_desc(j.second);
+            const int nt = d.ntx * d.nty;
+            if (nt > 32 * kCommitThreads || (int64_t)d.W * d.H > (1ll << kSlotIndexBits)) return false;
+            pl.jobs.push_back(j.first);
+            for (int t = 0; t < nt; ++t) {
+                pl.all.push_back(WorkItem{j.first, t});
+                pl.radius.push_back(d.r);
+            }
+        }
+        bool fit = n_commit <= cap / 2 && pl.n_search >= 1;
+        if (fit && pl.r == kMultiMixed) {
+            // each radius within its own share of the search groups
+            std::vector<WorkItem> items;
+            std::vector<int32_t> first;
+            fit = spread_items_by_radius(pl.all, pl.radius, pl.n_search, &items, &first);
+            for (int w = 0; fit && w < pl.n_search; ++w) fit = first[w + 1] - first[w] <= max_items;
+        } else if (fit) {
+            fit = (int64_t)pl.all.size() <= (int64_t)pl.n_search * max_items;
+        }
+        if (!fit) return false;
+        plans->push_back(std::move(pl));
+    }
+    return true;
+}
+
+// The running jobs of the batch as (slot, context).
+static std::vector<std::pair<int, const inpaint_ctx *>> running_jobs(const inpaint_batch *b) {
+    const int32_t *state = (const int32_t *)(b->h_active + 1);
+    std::vector<std::pair<int, const inpaint_ctx *>> jobs;
+    for (size_t i = 0; i < b->slots.size(); ++i)
+        if (b->slots[i] && state[i] == INPAINT_SLOT_RUNNING) jobs.push_back({(int)i, b->slots[i]});
+    return jobs;
+}
+
+// Plans the batched persistent dispatches of the running jobs (group_multi)
+// and uploads the slot table with each job's persistent tiling.  *fits =
+// false when a dispatch does not fit (the batch then steps in the graph
+// form).  max_items: search items per search group allowed (1: every tile
+// stays in LDS for the whole dispatch).
 hipError_t plan_multi(inpaint_batch *b, int max_items, bool *fits) {
     *fits = false;
-    const int32_t *state = (const int32_t *)(b->h_active + 1);
-    std::map<std::pair<int, int>, std::vector<int>> groups;
+    const auto jobs = running_jobs(b);
     std::string sig = std::to_string(max_items) + "/";
-    for (size_t i = 0; i < b->slots.size(); ++i) {
-        const inpaint_ctx *c = b->slots[i];
-        if (c && state[i] == INPAINT_SLOT_RUNNING) {
-            groups[{multi_form(c) ? 1 : 0, c->d.r}].push_back((int)i);
-            sig += std::to_string(i) + ":" + std::to_string((uintptr_t)c) + ",";
-        }
-    }
+    for (const auto &j : jobs) sig += std::to_string(j.first) + ":" + std::to_string((uintptr_t)j.second) + ",";
     if (!b->dirty && b->desc_form == INPAINT_FORM_PERSISTENT && sig == b->multi_sig) {
         *fits = true;
         return hipSuccess;
     }
     if (!b->dirty && sig == b->nofit_sig) return hipSuccess;
-    // the slot table with each job's persistent tiling, and the fit check,
-    // before anything is uploaded
+    std::vector<MultiGroupPlan> plans;
+    if (!group_multi(b, jobs, max_items, &plans)) {
+        b->nofit_sig = sig;
+        return hipSuccess;
+    }
     std::vector<JobDev> desc(b->slots.size());
-    for (size_t i = 0; i < b->slots.size(); ++i) {
-        const inpaint_ctx *c = b->slots[i];
-        if (!c) continue;
-        desc[i] = c->d;
-        set_tiles(desc[i], multi_form(c) ? kMfmaTileRows : kFillTileRows, multi_form(c) ? c->d.r : 0);
-    }
-    struct Plan {
-        bool mfma;
-        int r, n_search;
-        std::vector<int> jobs;
-        std::vector<WorkItem> all;
-    };
-    std::vector<Plan> plans;
-    for (auto &kv : groups) {
-        Plan pl{kv.first.first != 0, kv.first.second, 0, kv.second, {}};
-        auto it = b->mcap.find(kv.first);
-        const int cap = it != b->mcap.end() ? it->second : (b->mcap[kv.first] = multi_capacity(pl.mfma, pl.r));
-        const int n_commit = (int)pl.jobs.size();
-        pl.n_search = cap - n_commit;
-        for (int slot : pl.jobs) {
-            const JobDev &d = desc[slot];
-            const int nt = d.ntx * d.nty;
-            if (nt > 32 * kCommitThreads || (int64_t)d.W * d.H > (1ll << kSlotIndexBits)) {
-                b->nofit_sig = sig;
-                return hipSuccess;
-            }
-            for (int t = 0; t < nt; ++t) pl.all.push_back(WorkItem{slot, t});
-        }
-        if (n_commit > cap / 2 || pl.n_search < 1 || (int64_t)pl.all.size() > (int64_t)pl.n_search * max_items) {
-            b->nofit_sig = sig;
-            return hipSuccess;
-        }
-        plans.push_back(std::move(pl));
-    }
+    for (size_t i = 0; i < b->slots.size(); ++i)
+        if (b->slots[i]) desc[i] = multi_desc(b->slots[i]);
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < b->slots.size() && e == hipSuccess; ++i) {
         if (!b->slots[i]) continue;
@@ -1362,13 +1451,16 @@ hipError_t plan_multi(inpaint_batch *b, int max_items, bool *fits) {
     b->graph_sig.clear();   // the graph form rebuilds its tilings
     b->mbufs.resize(plans.size());
     for (size_t gi = 0; gi < plans.size(); ++gi) {
-        const Plan &pl = plans[gi];
+        const MultiGroupPlan &pl = plans[gi];
         MultiBuf &m = b->mbufs[gi];
         m.mfma = pl.mfma;
         m.r = pl.r;
         std::vector<WorkItem> items;
         std::vector<int32_t> first;
-        spread_items(pl.all, pl.n_search, &items, &first);
+        if (pl.r == kMultiMixed)
+            spread_items_by_radius(pl.all, pl.radius, pl.n_search, &items, &first);   // fits: checked above
+        else
+            spread_items(pl.all, pl.n_search, &items, &first);
         e = grow(&m.commit, &m.cap_commit, pl.jobs.size());
         if (e == hipSuccess) e = grow(&m.items, &m.cap_items, items.size());
         if (e == hipSuccess) e = grow(&m.first, &m.cap_first, first.size());
@@ -1569,6 +1661,17 @@ int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active) {
 int32_t inpaint_batch_form(const inpaint_batch *b, int32_t *form) {
     if (!b || !form) return INPAINT_INVALID_ARGUMENT;
     *form = b->last_form;
+    return INPAINT_OK;
+}
+
+int32_t inpaint_batch_room(inpaint_batch *b, const inpaint_ctx *ctx, int32_t tiles_per_group, int32_t *room) {
+    SharedDevice lock(g_device_mu);
+    if (!b || !ctx || !room || ctx->batch || tiles_per_group < 1 || tiles_per_group > kMultiMaxItems)
+        return INPAINT_INVALID_ARGUMENT;
+    auto jobs = running_jobs(b);
+    jobs.push_back({(int)b->slots.size(), ctx});   // (a slot index no running job uses)
+    std::vector<MultiGroupPlan> plans;
+    *room = group_multi(b, jobs, tiles_per_group, &plans) ? 1 : 0;
     return INPAINT_OK;
 }
 

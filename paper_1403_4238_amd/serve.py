@@ -5,9 +5,12 @@ batch slot is free and its device footprint (the workspace its context needs)
 fits the memory budget: both are reserved at once, and the job's context is
 prepared (upload and initialisation) on a worker thread with its own stream
 while the loop keeps stepping the running jobs.  A prepared job is attached to
-the running batch between two batch steps.  Every batch step advances every
-attached unfinished job by G fill iterations, so jobs that arrive while others
-run share the device with them.  Finished jobs are read back, detached and
+the running batch between two batch steps, in arrival order, once the engine
+has room for it (``GpuEngine``: every running image keeps its search tiles
+resident in the batched persistent dispatch, so each runs at about its solo
+iteration time; a job arriving at an empty batch always starts).  Every batch
+step advances every attached unfinished job by G fill iterations, so jobs that
+arrive while others run share the device with them.  Finished jobs are read back, detached and
 their memory released, which may admit queued jobs.  Latency is completion
 time minus arrival time.
 
@@ -82,14 +85,16 @@ class Server:
         nxt = 0
         queue: list[int] = []
         preparing: dict[int, cf.Future] = {}   # admitted, context being prepared off the loop
+        ready: list[tuple[int, object]] = []   # prepared, waiting for room in the batch
         active: dict[int, object] = {}
+        room = getattr(eng, "room", None)
 
         def fail(i, e):
             recs[i].status, recs[i].error = "failed", str(e)
             recs[i].done_s = self.clock() - t0
             self.used -= recs[i].footprint
 
-        while nxt < len(order) or queue or preparing or active:
+        while nxt < len(order) or queue or preparing or ready or active:
             now = self.clock() - t0
             while nxt < len(order) and recs[order[nxt]].arrival_s <= now:
                 i = order[nxt]
@@ -100,7 +105,7 @@ class Server:
                     continue
                 queue.append(i)
             # admit in arrival order while a slot and memory are free
-            while (queue and len(active) + len(preparing) < self.capacity
+            while (queue and len(active) + len(preparing) + len(ready) < self.capacity
                    and self.used + recs[queue[0]].footprint <= self.budget):
                 i = queue.pop(0)
                 self.used += recs[i].footprint
@@ -109,17 +114,30 @@ class Server:
                     preparing[i] = pool.submit(eng.prepare, jobs[i])
                     continue
                 try:
-                    active[i] = eng.admit(jobs[i])
+                    if room is None:
+                        active[i] = eng.admit(jobs[i])
+                    else:
+                        ready.append((i, eng.prepare(jobs[i])))
+                        continue
                 except Exception as e:  # invalid job: report it, keep serving the rest
                     fail(i, e)
                     continue
                 recs[i].admit_s = self.clock() - t0
                 recs[i].status = "running"
-            # prepared jobs join the batch between two steps
             for i in [i for i, f in preparing.items() if f.done()]:
                 f = preparing.pop(i)
                 try:
-                    active[i] = eng.attach(f.result())
+                    ready.append((i, f.result()))
+                except Exception as e:
+                    fail(i, e)
+            # prepared jobs join the batch between two steps, in arrival
+            # order, while the engine has room for them (always when the
+            # batch is empty); a job without room holds back the later ones
+            ready.sort(key=lambda ip: (recs[ip[0]].arrival_s, ip[0]))
+            while ready and (not active or room is None or room(ready[0][1])):
+                i, prepared = ready.pop(0)
+                try:
+                    active[i] = eng.attach(prepared)
                 except Exception as e:
                     fail(i, e)
                     continue
@@ -181,8 +199,10 @@ class FakeEngine:
     admitted job by G iterations and costs ``step_cost_s`` of (fake) time."""
 
     def __init__(self, iterations: Callable, footprint: Callable, clock=None, step_cost_s: float = 0.0,
-                 fail_on: Callable | None = None):
+                 fail_on: Callable | None = None, room: Callable | None = None):
         self.iterations = iterations
+        # room(running jobs, job) -> bool: the batch has room for job
+        self.room = None if room is None else (lambda job: room([st[0] for st in self.live.values()], job))
         self._footprint = footprint
         self.step_cost_s = step_cost_s
         self.clock = clock
@@ -245,13 +265,16 @@ class FakeClock:
 
 
 class GpuEngine:
-    """libinpaint through the binding: one Batch; contexts are prepared on a
-    side stream of the calling thread (a server worker, so the loop keeps
-    stepping meanwhile) and attached between steps; their torch workspaces
-    are freed on release."""
+    """libinpaint through the binding: one Batch (the batched persistent
+    form unless ``form`` says otherwise); contexts are prepared on a side
+    stream of the calling thread (a server worker, so the loop keeps stepping
+    meanwhile) and attached between steps while the batch has room for
+    their search tiles, at most ``tiles_per_group`` per search work-group
+    (``Batch.room``; 0: whenever a slot is free); their torch workspaces are
+    freed on release."""
 
     def __init__(self, capacity: int, graph_iters: int = 8, autotune: bool = True, tune_cache: str | None = None,
-                 log: bool = True, path: str = "mfma"):
+                 log: bool = True, path: str = "mfma", form: str = "persistent", tiles_per_group: int = 0):
         import threading
 
         import torch
@@ -262,9 +285,12 @@ class GpuEngine:
         self.stream = torch.cuda.current_stream()
         self.device = torch.cuda.current_device()
         self._local = threading.local()
-        self.batch = B.Batch(capacity, graph_iters, autotune, tune_cache, stream=self.stream)
+        self.batch = B.Batch(capacity, graph_iters, autotune, tune_cache, stream=self.stream, form=form)
         self.log = log
         self.path = path
+        self.tiles_per_group = tiles_per_group
+        if not tiles_per_group:
+            self.room = None   # attach whenever a slot is free
 
     def _side(self):
         s = getattr(self._local, "stream", None)
@@ -289,6 +315,9 @@ class GpuEngine:
                                    log_capacity=int(np.count_nonzero(job.mask)) if self.log else 0,
                                    stream=side, path=self._path_id(job))
         return ctx
+
+    def room(self, ctx) -> bool:
+        return self.batch.room(ctx, self.tiles_per_group)
 
     def attach(self, ctx):
         self.batch.attach(ctx)

@@ -137,3 +137,47 @@ def test_async_admission_counts_preparing_jobs_against_the_limits():
     assert all(r.status == "done" for r in recs)
     assert eng.max_live <= 3          # 3 x 30 bytes fit in 100, a fourth does not
     assert srv.peak_used <= 100
+
+
+def _room_server(jobs, limit, workers=0, capacity=8):
+    # room: the running jobs' "tiles" (J.nbytes here) plus the new job's fit
+    # under `limit`; every attach is recorded with the tiles then running
+    clock = FakeClock()
+    attached = []
+    eng = FakeEngine(lambda j: j.iters, lambda j: 1, clock=clock, step_cost_s=0.001,
+                     room=lambda running, j: sum(r.nbytes for r in running) + j.nbytes <= limit)
+    attach = eng.attach
+
+    def spy(job):
+        attached.append((job.name, sum(st[0].nbytes for st in eng.live.values())))
+        return attach(job)
+    eng.attach = spy
+    srv = Server(eng, 1 << 30, capacity, 1, clock=clock, sleep=clock.sleep, workers=workers)
+    return attached, srv.run(jobs)
+
+
+def test_attach_waits_for_room_in_arrival_order():
+    # tiles 6, 3, 5, 2 under a limit of 10: "c" (5) does not fit beside "a"
+    # and "b" (9), so it waits for room and "d", which would fit, waits
+    # behind it; a job larger than the limit starts alone.  (Synchronous
+    # preparation, so the attach times are exact.)
+    jobs = [J("a", 0.0, 20, 6), J("b", 0.0, 30, 3), J("c", 0.0, 10, 5), J("d", 0.0, 5, 2),
+            J("e", 0.001, 5, 12)]
+    attached, recs = _room_server(jobs, 10, 0)
+    assert all(r.status == "done" for r in recs)
+    assert [a[0] for a in attached] == ["a", "b", "c", "d", "e"]
+    limits = dict(attached)
+    assert limits["a"] == 0 and limits["b"] == 6
+    assert limits["c"] + 5 <= 10 and limits["d"] + 2 <= 10
+    assert limits["e"] == 0          # too large for any room: runs once the batch is empty
+    assert recs[2].admit_s >= recs[0].done_s - 1e-12   # "c" started only after "a" left
+
+
+def test_room_never_exceeded_with_several_running():
+    rng = np.random.default_rng(3)
+    jobs = [J(f"j{i}", float(i) * 0.002, int(rng.integers(1, 40)), int(rng.integers(1, 9))) for i in range(40)]
+    attached, recs = _room_server(jobs, 12, workers=1)
+    assert all(r.status == "done" for r in recs)
+    assert [a[0] for a in attached] == [j.name for j in jobs]   # arrival order
+    for (name, running), j in zip(attached, jobs):
+        assert running == 0 or running + j.nbytes <= 12, name

@@ -29,11 +29,14 @@ def _jobs(n=10, rate=400.0, seed=9):
     return jobs
 
 
-@pytest.mark.parametrize("capacity,budget_jobs,workers,path", [(4, 3, 0, "simt"), (16, 16, 0, "mfma"),
-                                                               (4, 3, 2, "mfma")])
-def test_served_results_equal_alone_and_oracle(capacity, budget_jobs, workers, path):
+@pytest.mark.parametrize("capacity,budget_jobs,workers,path,form,tpg", [(4, 3, 0, "simt", "persistent", 0),
+                                                                        (16, 16, 0, "mfma", "persistent", 0),
+                                                                        (4, 3, 2, "mfma", "persistent", 1),
+                                                                        (6, 6, 1, "mfma", "graph", 0)])
+def test_served_results_equal_alone_and_oracle(capacity, budget_jobs, workers, path, form, tpg):
     jobs = _jobs()
-    eng = serve.GpuEngine(capacity=capacity, graph_iters=6, autotune=False, path=path)
+    eng = serve.GpuEngine(capacity=capacity, graph_iters=6, autotune=False, path=path, form=form,
+                          tiles_per_group=tpg)
     budget = budget_jobs * max(eng.footprint(j) for j in jobs)
     srv = serve.Server(eng, budget, capacity, graph_iters=6, workers=workers)
     recs = srv.run(jobs)
@@ -51,6 +54,30 @@ def test_served_results_equal_alone_and_oracle(capacity, budget_jobs, workers, p
         assert_logs_equal(log, r.result["log"], j.name + " alone")
     if capacity == 4:
         assert srv.peak_active >= 2      # jobs did overlap on the device
+
+
+def test_batch_room_counts_resident_tiles():
+    # A 1080p 9x9 image has 510 MFMA search tiles: alone it keeps every tile
+    # resident, a second one beside it does not (unless two tiles may share
+    # a search work-group).
+    hd = synth.hd()
+    small = synth.small()
+    batch = B.Batch(capacity=4, graph_iters=8, form="persistent")
+    a = B.Inpainter(hd.rgb, hd.mask, hd.patch_radius, path=B.PATH_MFMA)
+    b = B.Inpainter(hd.rgb, hd.mask, hd.patch_radius, path=B.PATH_MFMA)
+    c = B.Inpainter(small.rgb, small.mask, small.patch_radius, path=B.PATH_MFMA)
+    assert batch.room(a) and batch.room(c)
+    batch.attach(a)
+    batch.step(1)
+    assert not batch.room(b)
+    assert batch.room(b, tiles_per_group=2)
+    with pytest.raises(B.InpaintError):
+        batch.room(a)   # already attached
+    with pytest.raises(B.InpaintError):
+        batch.room(b, tiles_per_group=0)
+    for x in (a, b, c):
+        x.close()
+    batch.close()
 
 
 def test_invalid_job_is_isolated():
