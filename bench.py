@@ -88,7 +88,7 @@ def parse():
     ap.add_argument("--workload", default="hd", choices=["hd", "vga", "small", "big", "batch", "serve", "sweep", "copy", "resume"])
     ap.add_argument("--jobs", type=int, default=128, help="serve: number of jobs")
     ap.add_argument("--workers", type=int, default=1, help="serve: admission worker threads (0: on the loop)")
-    ap.add_argument("--graph-iters", type=int, default=16, help="batch: iterations per step")
+    ap.add_argument("--graph-iters", type=int, default=64, help="batch: iterations per step")
     ap.add_argument("--serve-iters", type=int, default=128, help="serve: iterations per batch step")
     ap.add_argument("--serve-form", default="persistent", choices=["persistent", "graph", "auto"],
                     help="serve: batch form")

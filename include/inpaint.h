@@ -323,11 +323,12 @@ const char *inpaint_last_error(const inpaint_ctx *ctx);
 /* Many images advanced together: each batch step runs, for every attached
  * unfinished image, G fill iterations (the fill loop of Section 3 per image).
  * Two forms:
- *  - PERSISTENT (the default when it fits): one persistent dispatch per
- *    step and patch radius runs all G iterations of every image; one
- *    work-group per image commits (front, priority, copy), every other
- *    co-resident work-group searches (image, tile) items of whichever image
- *    has a staged target.  Images of up to 64 tiles per search work-group.
+ *  - PERSISTENT: one persistent dispatch per step (the int8-MFMA images of
+ *    radius 1..5 share one dispatch; the others one per search form and
+ *    radius) runs all G iterations of every image; one work-group per image
+ *    commits (front, priority, copy), every other co-resident work-group
+ *    searches (image, tile) items of whichever image has a staged target.
+ *    Images of up to 64 tiles per search work-group.
  *  - GRAPH: per iteration, a persistent search kernel over a static (image,
  *    tile) work list, then one commit work-group per image; G iterations are
  *    captured once into a hipGraph and replayed.  Tile shape and grid may be
@@ -337,8 +338,9 @@ typedef struct {
     int32_t graph_iters;     /* G: iterations per replay, >= 1              */
     int32_t autotune;        /* 1 = time tile shapes and the persistent grid */
                              /*   of the graph form on first use, 0 = defaults */
-    int32_t form;            /* 0 = PERSISTENT when the attached images fit */
-                             /*   one dispatch, else GRAPH; or               */
+    int32_t form;            /* 0 = PERSISTENT once the running images fit  */
+                             /*   a few tiles per search work-group (4),    */
+                             /*   else GRAPH; or                            */
                              /*   INPAINT_FORM_GRAPH / INPAINT_FORM_PERSISTENT */
                              /*   (a step that does not fit then fails with  */
                              /*   INVALID_ARGUMENT)                          */

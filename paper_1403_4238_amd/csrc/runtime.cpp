@@ -1417,6 +1417,12 @@ static std::vector<std::pair<int, const inpaint_ctx *>> running_jobs(const inpai
     return jobs;
 }
 
+// AUTO steps the batched persistent form once every search work-group has at
+// most this many (image, tile) items (a group with several restages a tile
+// per item and iteration; the graph form restages every tile every
+// iteration, so a few items per group are still the cheaper of the two).
+constexpr int kAutoPersistentItems = 4;
+
 // Plans the batched persistent dispatches of the running jobs (group_multi)
 // and uploads the slot table with each job's persistent tiling.  *fits =
 // false when a dispatch does not fit (the batch then steps in the graph
@@ -1598,7 +1604,7 @@ int32_t inpaint_batch_step(inpaint_batch *b, int32_t G, int64_t *active) {
         // that latency better.  So a large batch starts in the graph form
         // and its tail, when few images are left, runs persistent.
         bool fits = false;
-        e = plan_multi(b, b->bp.form == INPAINT_FORM_PERSISTENT ? kMultiMaxItems : 1, &fits);
+        e = plan_multi(b, b->bp.form == INPAINT_FORM_PERSISTENT ? kMultiMaxItems : kAutoPersistentItems, &fits);
         if (e != hipSuccess) return INPAINT_DEVICE;
         if (fits) {
             b->dirty = false;
