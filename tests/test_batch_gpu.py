@@ -118,7 +118,7 @@ def test_batch_of_vga_sized_images_prefix():
 def test_batch_of_64_full_size_matches_stored_oracle(tmp_path, form, path):
     # The seeded 64-image batch (320x240 .. 1280x720, 1-3 blobs covering
     # 2-10%, 9x9 patch, full search), run to the end with 16 iterations per
-    # step: in the batched persistent form (one cooperative dispatch per
+    # step: in the batched persistent form (one persistent dispatch per
     # step advances every image) on either search path, and in the graph
     # form with the autotuner on.  Every image's whole fill log and final
     # image equal its stored oracle result.
@@ -142,3 +142,34 @@ def test_batch_of_64_full_size_matches_stored_oracle(tmp_path, form, path):
     for j, g, c in zip(jobs, golds, ctxs):
         assert c.remaining() == 0, j.name
         assert_matches_golden(g, c.read_log(0, g["iterations"]), c.read_image(), j.name)
+
+
+def test_mixed_radii_beyond_resident_tiles_match_stored_oracle():
+    # Serving jobs 1, 2, 3 and 8 (7x7, 11x11, 9x9, 9x9 patches; about 1040
+    # int8-MFMA search tiles, twice the co-resident search work-groups) in
+    # the batched persistent form: every step is one mixed-radius dispatch
+    # whose search groups each hold tiles of one radius and restage them per
+    # iteration.  Every job's fill log and final image equal its stored
+    # oracle result.
+    from _util import assert_matches_golden, load_golden
+    jobs = synth.serving()
+    pick = [1, 2, 3, 8]
+    assert sorted({jobs[i].patch_radius for i in pick}) == [3, 4, 5]
+    golds = [load_golden(f"serve{i:02d}") for i in pick]
+    assert all(g is not None for g in golds), "stored oracle results missing"
+    batch = B.Batch(capacity=len(pick), graph_iters=32, autotune=False, form="persistent")
+    ctxs = [B.Inpainter(jobs[i].rgb, jobs[i].mask, jobs[i].patch_radius, path=B.PATH_MFMA,
+                        log_capacity=int(jobs[i].mask.sum())) for i in pick]
+    for c in ctxs:
+        batch.attach(c)
+    steps = 0
+    while batch.step() > 0:
+        steps += 1
+        assert steps < 1000
+    assert batch.last_form() == "persistent"
+    for i, g, c in zip(pick, golds, ctxs):
+        assert g["input_sha256"] == jobs[i].sha256(), jobs[i].name
+        it, _ = c.progress()
+        assert_matches_golden(g, c.read_log(0, it), c.read_image(), jobs[i].name)
+        c.close()
+    batch.close()
