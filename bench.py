@@ -408,19 +408,23 @@ def batch_bench(a):
         cands = [c.search_info()[1] for c in ctxs]
         evals = sum(i * n for i, n in zip(iters, cands))
         checked = ok = 0
+        terms = 0
         for i, (j, c) in enumerate(zip(jobs, ctxs)):
+            log = c.read_log(0, iters[i])
+            # Eq. 4's terms: 3 channels x known offsets x candidates, per iteration
+            terms += 3 * int(np.asarray(log["known_k"], dtype=np.int64).sum()) * cands[i]
             gold = load_golden(f"batch{i:02d}")
             if gold is None:
                 continue
             checked += 1
-            log = c.read_log(0, iters[i])
             ok += (gold["input_sha256"] == j.sha256() and gold["log_sha256"] == log_sha256(log)
                    and gold["final_rgb_sha256"] == hashlib.sha256(c.read_image().tobytes()).hexdigest())
         for c in ctxs:
             batch.detach(c)
             c.close()
         batch.close()
-        return dict(seconds=dt, iters=iters, evals=evals, steps=steps + 1, ok=ok, checked=checked, form=ran)
+        return dict(seconds=dt, iters=iters, evals=evals, terms=terms, steps=steps + 1, ok=ok, checked=checked,
+                    form=ran)
 
     head = batched(a.batch_form, a.path)
     forms = {}
@@ -457,6 +461,14 @@ def batch_bench(a):
                    "images": len(jobs), "total_iterations": int(sum(head["iters"])), "batch_steps": head["steps"],
                    "max_iterations_per_image": int(max(head["iters"]))},
         "batched_ms": round(1000 * dt, 2),
+        # over the whole batch's wall time (commits, host checks and the
+        # graph / persistent switch included), so a lower bound for its
+        # search kernels
+        "roofline": {"bound": "mfma", "kernel": "whole batch (graph steps: k_search_batched + k_commit_batched, "
+                                                "then k_fill_multi_mfma)",
+                     "achieved": round(OPS_PER_TERM * head["terms"] / dt / 1e12, 3), "peak": MFMA_TERM_PEAK * OPS_PER_TERM / 1e12,
+                     "unit": "TOP/s", "frac": round(head["terms"] / dt / MFMA_TERM_PEAK, 5),
+                     "frac_of_valu_dot4": round(head["terms"] / dt / TERM_PEAK, 5), "traffic": None},
         "other_batch_forms": forms,
         "one_by_one": {f: {"ms": round(1000 * t, 2), "patch_evals_per_s": round(evals / t, 1)}
                        for f, t in one.items()},

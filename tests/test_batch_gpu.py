@@ -114,22 +114,25 @@ def test_batch_of_vga_sized_images_prefix():
         assert_logs_equal(c.read_log(0, 10), want, j.name)
 
 
-@pytest.mark.parametrize("form,path", [("persistent", "mfma"), ("persistent", "simt"), ("graph", "simt")])
+@pytest.mark.parametrize("form,path", [("persistent", "mfma"), ("persistent", "simt"), ("graph", "simt"),
+                                       ("auto", "mfma")])
 def test_batch_of_64_full_size_matches_stored_oracle(tmp_path, form, path):
     # The seeded 64-image batch (320x240 .. 1280x720, 1-3 blobs covering
     # 2-10%, 9x9 patch, full search), run to the end with 16 iterations per
     # step: in the batched persistent form (one persistent dispatch per
     # step advances every image) on either search path, and in the graph
-    # form with the autotuner on.  Every image's whole fill log and final
-    # image equal its stored oracle result.
+    # form with the autotuner on; and as the bench runs it, AUTO with 64
+    # iterations per step (graph form, then persistent once the running
+    # tiles fit four per search group).  Every image's whole fill log and
+    # final image equal its stored oracle result.
     from _util import assert_matches_golden, load_golden
     jobs = synth.batch()
     golds = [load_golden(f"batch{i:02d}") for i in range(len(jobs))]
     assert all(g is not None for g in golds), "stored oracle results missing"
     for j, g in zip(jobs, golds):
         assert g["input_sha256"] == j.sha256(), j.name
-    batch = B.Batch(capacity=len(jobs), graph_iters=16, autotune=True, tune_cache=str(tmp_path / "tune.json"),
-                    form=form)
+    batch = B.Batch(capacity=len(jobs), graph_iters=64 if form == "auto" else 16, autotune=True,
+                    tune_cache=str(tmp_path / "tune.json"), form=form)
     pid = B.PATH_MFMA if path == "mfma" else B.PATH_SIMT
     ctxs = [B.Inpainter(j.rgb, j.mask, j.patch_radius, path=pid) for j in jobs]
     for c in ctxs:
@@ -138,7 +141,7 @@ def test_batch_of_64_full_size_matches_stored_oracle(tmp_path, form, path):
     while batch.step() > 0:
         steps += 1
         assert steps < 2000
-    assert batch.last_form() == form
+    assert batch.last_form() == (form if form != "auto" else "persistent")
     for j, g, c in zip(jobs, golds, ctxs):
         assert c.remaining() == 0, j.name
         assert_matches_golden(g, c.read_log(0, g["iterations"]), c.read_image(), j.name)
