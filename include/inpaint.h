@@ -139,7 +139,8 @@ typedef struct {
     int32_t form;          /* inpaint_run execution form, INPAINT_FORM_*     */
     int32_t iters_per_check; /* STREAM / GRAPH forms: iterations enqueued   */
                            /*   (or replayed as one hipGraph) between two   */
-                           /*   host checks of termination (>= 1)           */
+                           /*   host checks of termination; PERSISTENT:     */
+                           /*   iterations per dispatch (1 .. 33554430)     */
     int32_t log_capacity;  /* device log records kept (>= 0), one per fill   */
                            /*   iteration; -1 = width*height, enough for    */
                            /*   any mask (a removal never needs more than   */
@@ -335,7 +336,7 @@ const char *inpaint_last_error(const inpaint_ctx *ctx);
  *    autotuned. */
 typedef struct {
     int32_t capacity;        /* maximum attached contexts (slots), >= 1     */
-    int32_t graph_iters;     /* G: iterations per replay, >= 1              */
+    int32_t graph_iters;     /* G: iterations per step, 1 .. 33554430       */
     int32_t autotune;        /* 1 = time tile shapes and the persistent grid */
                              /*   of the graph form on first use, 0 = defaults */
     int32_t form;            /* 0 = PERSISTENT once the running images fit  */

@@ -414,6 +414,25 @@ __device__ void write_records(FillSync *sy, const TargetStage *tg, int P) {
     }
 }
 
+// Records of the MFMA (lean) form carry their own freshness: each word is
+// the target word (RGB) with a 7-bit tag of the fill iteration it belongs
+// to in bits 24-30 and its known flag in bit 31.  Consecutive iterations of
+// a job have different tags, and every word of a record is rewritten each
+// iteration, so a word that carries the expected tag is that iteration's.
+__device__ __forceinline__ uint32_t rec_tag(int64_t iter) { return (uint32_t)(iter % 127) + 1u; }
+__device__ __forceinline__ uint32_t lean_word(uint32_t pix, bool known, uint32_t tag) {
+    return (pix & 0x00ffffffu) | (tag << 24) | (known ? 0x80000000u : 0u);
+}
+
+// The lean records from a target staged by an earlier dispatch.
+__device__ void write_records_lean(FillSync *sy, const TargetStage *tg, int P, uint32_t tag) {
+    const int n = P * P;
+    for (int i = threadIdx.x; i < kGoCopies * n; i += blockDim.x) {
+        const int c = i / n, t = i - c * n;
+        sy->rec[c].tpix[t] = lean_word(tg->tpix[t], (tg->mbits[t >> 5] >> (t & 31)) & 1u, tag);
+    }
+}
+
 // One wave recomputes the maximum of the 8x8 priority block (bx, by).
 __device__ void refresh_block_wave(const JobDev &d, int bx, int by) {
     const int lane = threadIdx.x & 63;
@@ -524,12 +543,14 @@ __device__ int stage_target(const JobDev &d, int tx, int ty, int r, TargetStage 
 }
 
 // Persistent fill with the MFMA search: stages only what its search groups
-// read -- the words and the known mask -- into the target and every record
-// (the words straight from the slot pass, no barrier in between).  T2 and the
+// read -- the words with their known flags, tagged for iteration `tag` (see
+// lean_word) -- into every record, and the words and the known mask into the
+// target (the words straight from the slot pass, no barrier in between).  T2 and the
 // column-run bits of the target follow once, for the last target staged in a
 // dispatch (finish_stage).  Returns k.
 template <class F>
-__device__ int stage_slots_lean(int r, int tx, int ty, TargetStage *tg, Scratch &s, FillSync *recs, F slot) {
+__device__ int stage_slots_lean(int r, int tx, int ty, TargetStage *tg, Scratch &s, FillSync *recs, uint32_t tag,
+                                F slot) {
     const int P = 2 * r + 1, n = P * P, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int base = 0; base < n; base += blockDim.x) {
         const int t = base + threadIdx.x;
@@ -538,8 +559,9 @@ __device__ int stage_slots_lean(int r, int tx, int ty, TargetStage *tg, Scratch 
         if (t < n) {
             tg->tpix[t] = pix;
             s.tp[t] = pix;
+            const uint32_t w = lean_word(pix, kn, tag);
 #pragma unroll
-            for (int c = 0; c < kGoCopies; ++c) recs->rec[c].tpix[t] = pix;
+            for (int c = 0; c < kGoCopies; ++c) recs->rec[c].tpix[t] = w;
         }
         const uint64_t bal = __ballot(kn);
         const int w0 = (base >> 5) + 2 * wave;
@@ -552,10 +574,6 @@ __device__ int stage_slots_lean(int r, int tx, int ty, TargetStage *tg, Scratch 
     const int mw = (n + 31) / 32;
     int kk = 0;
     for (int w = 0; w < mw; ++w) kk += __popc(s.mbits[w]);
-    for (int i = threadIdx.x; i < kGoCopies * 16; i += blockDim.x) {   // (copy, word) pairs
-        const int w = i & 15;
-        if (w < mw) recs->rec[i >> 4].mbits[w] = s.mbits[w];
-    }
     if ((int)threadIdx.x < mw) tg->mbits[threadIdx.x] = s.mbits[threadIdx.x];
     if (threadIdx.x == 0) {
         tg->tx = tx;
@@ -1509,20 +1527,20 @@ __device__ void commit_finish(const JobDev &d, Scratch &s, LdsStage<R> &L, const
         using S = Stage<R>;
         constexpr int P = 2 * R + 1;
         if (adx <= 2 * R + 2 && ady <= 2 * R + 2) {
-            kk = stage_slots_lean(R, tx, ty, d.tgt, s, recs, [&](int t, uint32_t *pix) {
+            kk = stage_slots_lean(R, tx, ty, d.tgt, s, recs, rec_tag(v.iter + 1), [&](int t, uint32_t *pix) {
                 const int i = (ty + t % P - R - py + S::half) * S::side + (tx + t / P - R - px + S::half);
                 if (L.st[i] != 0) return false;
                 *pix = L.img[i] & 0x00ffffffu;
                 return true;
             });
         } else if (far && far->idx == idx) {
-            kk = stage_slots_lean(R, tx, ty, d.tgt, s, recs, [&](int t, uint32_t *pix) {
+            kk = stage_slots_lean(R, tx, ty, d.tgt, s, recs, rec_tag(v.iter + 1), [&](int t, uint32_t *pix) {
                 *pix = far->pix[t];
                 return far->known[t] != 0;
             });
         } else {
             const GlobalView gv{d};
-            kk = stage_slots_lean(R, tx, ty, d.tgt, s, recs, [&](int t, uint32_t *pix) {
+            kk = stage_slots_lean(R, tx, ty, d.tgt, s, recs, rec_tag(v.iter + 1), [&](int t, uint32_t *pix) {
                 const int x = tx + t / P - R, y = ty + t % P - R;
                 if (!gv.known(x, y)) return false;
                 *pix = d.img[(int64_t)y * d.W + x] & 0x00ffffffu;
@@ -1602,7 +1620,19 @@ __device__ void commit_body(const JobDev &d, Scratch &s, LdsStage<R> &L, CommitN
 
 constexpr uint32_t kSpinLimit = 1u << 22;
 
-__device__ __forceinline__ uint64_t go_word(uint32_t epoch, uint32_t v) { return ((uint64_t)epoch << 32) | v; }
+// Go words: the launch epoch in the high half; in the low half either stop
+// (all ones) or k + 1 (k < 2^25 - 1, the dispatch's iteration) in bits 0-24
+// with the record tag of that iteration (lean records; 0 otherwise) in bits
+// 25-31.
+constexpr uint32_t kGoK = (1u << 25) - 1;
+__device__ __forceinline__ uint64_t go_word(uint32_t epoch, uint32_t k1, uint32_t tag = 0) {
+    return ((uint64_t)epoch << 32) | (tag << 25) | k1;
+}
+__device__ __forceinline__ uint64_t go_stop(uint32_t epoch) { return ((uint64_t)epoch << 32) | 0xffffffffu; }
+__device__ __forceinline__ bool go_is(uint64_t v, uint32_t epoch, uint32_t k1) {
+    return (v >> 32) == epoch && (uint32_t)v != 0xffffffffu && (v & kGoK) == k1;
+}
+__device__ __forceinline__ uint32_t go_tag(uint64_t v) { return (uint32_t)(v >> 25) & 0x7fu; }
 
 // Thread 0 of search group t: 1 once target k is staged, 0 on stop or time-out.
 //
@@ -1616,13 +1646,16 @@ __device__ __forceinline__ uint64_t go_word(uint32_t epoch, uint32_t v) { return
 // L2).  So the reads observe the record.  An agent-scope acquire fence
 // after the match would make this a language-level guarantee, but on gfx950
 // it invalidates caches for every search group on every iteration: it was
-// measured to slow the 1080p removal from 49.2 ms to 61.4 ms.
+// measured to slow the 1080p removal from 49.2 ms to 61.4 ms.  (The MFMA
+// form does not depend on this order: its lean records tag every word with
+// the iteration, and its search groups check the tag of each word they use
+// and read stale words again.)
 __device__ int wait_go(const FillSync *sy, int t, uint32_t epoch, uint32_t k) {
-    const uint64_t want = go_word(epoch, k + 1), stop = go_word(epoch, 0xffffffffu);
+    const uint64_t stop = go_stop(epoch);
     const uint64_t *g = &sy->rec[t % kGoCopies].go;
     for (uint32_t spin = 0; spin < kSpinLimit; ++spin) {
         const uint64_t v = __hip_atomic_load(g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (v == want) return 1;
+        if (go_is(v, epoch, k + 1)) return 1;
         if (v == stop) return 0;
         __builtin_amdgcn_s_sleep(1);
     }
@@ -1722,7 +1755,12 @@ __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t 
         __syncthreads();
         v = s.snap;
     }
-    if (!v.done && !v.err && v.pending) write_records(sy, d.tgt, 2 * R + 1);
+    if (!v.done && !v.err && v.pending) {
+        if (LEAN)
+            write_records_lean(sy, d.tgt, 2 * R + 1, rec_tag(v.iter));
+        else
+            write_records(sy, d.tgt, 2 * R + 1);
+    }
     for (int i = threadIdx.x; i < ntiles; i += blockDim.x)
         __hip_atomic_store(&d.fslot[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     bool fresh = false;   // s.snap holds the state commit_finish left
@@ -1737,7 +1775,7 @@ __device__ void fill_commit(const JobDev &d0, int ntiles, int n_iters, uint32_t 
         if (fresh) v = s.snap;
         fresh = false;
         const bool stop = v.done || v.err || !v.pending || v.iter >= v.limit || (int)k >= n_iters;
-        publish_go(sy, go_word(epoch, stop ? 0xffffffffu : k + 1));
+        publish_go(sy, stop ? go_stop(epoch) : go_word(epoch, k + 1, LEAN ? rec_tag(v.iter) : 0u));
         if (stop) break;
 
         // search-independent loads of the commit, overlapping the search
@@ -1828,6 +1866,7 @@ struct SearchLdsMfma {
     mtile::FragTables<R> ft;
     uint64_t red[kSearchWaves];
     int32_t flag;
+    uint32_t tag;
 };
 
 template <int R>
@@ -1847,23 +1886,42 @@ __device__ void fill_search_mfma(const JobDev &d, uint32_t epoch, SearchLdsMfma<
     const uint32_t vmask = mtile::stage_tile<R>(d, tx0, ty0, d.rx0, d.rx1, d.ry1, S.tile);
     const bool anyv = __syncthreads_or(vmask != 0);
     FillSync *sy = d.sync;
+    const FillRec *rec = &sy->rec[t % kGoCopies];
+    constexpr int N = (2 * R + 1) * (2 * R + 1);
+    static_assert(N <= kSearchWaves * 64, "one record word per thread");
     for (uint32_t k = 0;; ++k) {
-        if (threadIdx.x == 0) S.flag = wait_go(sy, t, epoch, k);
-        __syncthreads();
-        if (!S.flag) break;
+        // Each poll reads the go word (thread 0) and this group's record
+        // words (thread i: word i) together, so the target arrives with the
+        // go word instead of one memory round trip after it.  Once go shows
+        // iteration k, a word counts only with the tag go carries; stale
+        // words (the previous iteration's) are read again.
+        uint32_t w = 0;
+        uint32_t spin = 0;
+        for (;; ++spin) {
+            uint64_t gv = 0;
+            if (threadIdx.x == 0) gv = __hip_atomic_load(&rec->go, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (anyv && (int)threadIdx.x < N)
+                w = __hip_atomic_load(&rec->tpix[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (threadIdx.x == 0) {
+                // 1: go for iteration k (its tag in S.tag), 0: stop or time-out, -1: not yet
+                S.flag = go_is(gv, epoch, k + 1) ? 1 : (gv == go_stop(epoch) ? 0 : -1);
+                if (spin >= kSpinLimit) S.flag = 0;
+                S.tag = go_tag(gv);
+            }
+            __syncthreads();
+            const int f = S.flag;
+            if (f == 1 && __syncthreads_and(!anyv || (int)threadIdx.x >= N || ((w >> 24) & 0x7fu) == S.tag)) break;
+            if (f == 0) break;
+            if (f == -1) __builtin_amdgcn_s_sleep(1);
+            __syncthreads();   // thread 0 rewrites S.flag only after everyone read it
+        }
+        if (S.flag == 0) break;
         uint64_t best = ~0ull;
         if (anyv) {
-            // the target straight from this group's record (device-scope
-            // loads, see load_record) into the patch tables, then the
-            // shifted tables
-            const FillRec *rec = &sy->rec[t % kGoCopies];
+            // the target from the record words into the patch tables, then
+            // the shifted tables
             mtile::build_patch<R>(
-                &S.ft,
-                [&](int sl) { return __hip_atomic_load(&rec->tpix[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); },
-                [&](int sl) {
-                    return (__hip_atomic_load(&rec->mbits[sl >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >>
-                            (sl & 31)) & 1u;
-                });
+                &S.ft, [&](int) { return w & 0x00ffffffu; }, [&](int) { return w >> 31; });
             __syncthreads();
             mtile::build_tables<R>(&S.ft);
             __syncthreads();
@@ -1928,6 +1986,7 @@ struct MultiPick {
     int32_t all_done;   // every item's job published stop
     int32_t slot, tile;
     uint32_t k;
+    uint32_t tag;       // record tag the item's go word carries
 };
 
 // Wave 0: polls the go words of this group's items (lane i: item i) and
@@ -1938,10 +1997,11 @@ __device__ __forceinline__ void multi_poll(const uint64_t *my_go, int my_slot, i
                                            bool &my_done, int rot, uint32_t epoch, MultiPick *pk) {
     const int lane = threadIdx.x & 63;
     bool ready = false;
+    uint64_t v = 0;
     if (!my_done) {
-        const uint64_t v = __hip_atomic_load(my_go, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ready = v == go_word(epoch, my_k + 1);
-        my_done = v == go_word(epoch, 0xffffffffu);
+        v = __hip_atomic_load(my_go, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ready = go_is(v, epoch, my_k + 1);
+        my_done = v == go_stop(epoch);
     }
     const uint64_t rb = __ballot(ready), db = __ballot(my_done);
     const uint64_t hi = rb & (~0ull << rot);
@@ -1956,6 +2016,7 @@ __device__ __forceinline__ void multi_poll(const uint64_t *my_go, int my_slot, i
         pk->slot = my_slot;
         pk->tile = my_tile;
         pk->k = my_k;
+        pk->tag = go_tag(v);
         my_k += 1;
     }
 }
@@ -1963,8 +2024,8 @@ __device__ __forceinline__ void multi_poll(const uint64_t *my_go, int my_slot, i
 // Scores item (job d, tile t) for iteration k of the MFMA form and reports
 // in the job's slot word.  restage: the tile in LDS is not this item's.
 template <int R>
-__device__ __forceinline__ void multi_serve_mfma(const JobDev &d, int t, uint32_t k, bool restage, SearchLdsMfma<R> &S,
-                                 uint32_t &vmask, bool &anyv) {
+__device__ __forceinline__ void multi_serve_mfma(const JobDev &d, int t, uint32_t k, uint32_t tag, bool restage,
+                                                 SearchLdsMfma<R> &S, uint32_t &vmask, bool &anyv) {
     int tx0, ty0;
     mtile::tile_origin<R>(d.rx0, d.ry0, d.ntx, t, &tx0, &ty0);
     if (restage) {
@@ -1973,14 +2034,21 @@ __device__ __forceinline__ void multi_serve_mfma(const JobDev &d, int t, uint32_
     }
     uint64_t best = ~0ull;
     if (anyv) {
+        // the record words of iteration k: read until every one carries the
+        // go word's tag (bounded; on a time-out no slot word is written, and
+        // the committer's bounded wait reports the device error)
         const FillRec *rec = &d.sync->rec[t % kGoCopies];
+        constexpr int N = (2 * R + 1) * (2 * R + 1);
+        static_assert(N <= kSearchWaves * 64, "one record word per thread");
+        uint32_t w = 0;
+        for (uint32_t spin = 0;; ++spin) {
+            if ((int)threadIdx.x < N)
+                w = __hip_atomic_load(&rec->tpix[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__syncthreads_and((int)threadIdx.x >= N || ((w >> 24) & 0x7fu) == tag)) break;
+            if (spin >= kSpinLimit) return;
+        }
         mtile::build_patch<R>(
-            &S.ft,
-            [&](int sl) { return __hip_atomic_load(&rec->tpix[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); },
-            [&](int sl) {
-                return (__hip_atomic_load(&rec->mbits[sl >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >>
-                        (sl & 31)) & 1u;
-            });
+            &S.ft, [&](int) { return w & 0x00ffffffu; }, [&](int) { return w >> 31; });
         __syncthreads();
         mtile::build_tables<R>(&S.ft);
         __syncthreads();
@@ -2020,8 +2088,8 @@ __device__ __forceinline__ void multi_serve_simt(const JobDev &d, int t, uint32_
         __hip_atomic_store(&d.fslot[t], slot_word(best, slot_tag(k)), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Search group w of a batched dispatch; serve(d, tile, k, restage, vmask,
-// anyv) scores one item.
+// Search group w of a batched dispatch; serve(d, tile, k, tag, restage,
+// vmask, anyv) scores one item (tag: the record tag its go word carried).
 template <class Serve>
 __device__ __forceinline__ void multi_search(const MultiPlan &m, int w, uint32_t epoch, MultiPick *pk, Serve serve) {
     const int i0 = m.first[w], ni = m.first[w + 1] - i0;   // 0 <= ni <= kMultiMaxItems (host-checked)
@@ -2056,7 +2124,7 @@ __device__ __forceinline__ void multi_search(const MultiPlan &m, int w, uint32_t
         rot = pick + 1 < ni ? pick + 1 : 0;
         // (by value: the fields the search reads become scalar registers)
         const JobDev d = m.slots[pk->slot];
-        serve(d, pk->tile, pk->k, staged != pick, vmask, anyv);
+        serve(d, pk->tile, pk->k, pk->tag, staged != pick, vmask, anyv);
         staged = pick;
         __syncthreads();
     }
@@ -2076,8 +2144,8 @@ __global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(
         return;
     }
     multi_search(m, (int)blockIdx.x - m.n_commit, epoch, &pk,
-                 [&](const JobDev &d, int t, uint32_t k, bool restage, uint32_t &vmask, bool &anyv)
-                     __attribute__((always_inline)) { multi_serve_mfma<R>(d, t, k, restage, lds.s, vmask, anyv); });
+                 [&](const JobDev &d, int t, uint32_t k, uint32_t tag, bool restage, uint32_t &vmask, bool &anyv)
+                     __attribute__((always_inline)) { multi_serve_mfma<R>(d, t, k, tag, restage, lds.s, vmask, anyv); });
 }
 
 template <int R>
@@ -2091,7 +2159,7 @@ __global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(
         return;
     }
     multi_search(m, (int)blockIdx.x - m.n_commit, epoch, &pk,
-                 [&](const JobDev &d, int t, uint32_t k, bool restage, uint32_t &vmask, bool &anyv)
+                 [&](const JobDev &d, int t, uint32_t k, uint32_t, bool restage, uint32_t &vmask, bool &anyv)
                      __attribute__((always_inline)) {
                      multi_serve_simt<R>(d, t, k, restage, lds.s, vmask, anyv);
                  });
@@ -2121,8 +2189,8 @@ __device__ __forceinline__ void mixed_role(const MultiPlan &m, int n_iters, uint
         return;
     }
     multi_search(m, (int)blockIdx.x - m.n_commit, epoch, pk,
-                 [&](const JobDev &d, int t, uint32_t k, bool restage, uint32_t &vmask, bool &anyv)
-                     __attribute__((always_inline)) { multi_serve_mfma<R>(d, t, k, restage, lds.s, vmask, anyv); });
+                 [&](const JobDev &d, int t, uint32_t k, uint32_t tag, bool restage, uint32_t &vmask, bool &anyv)
+                     __attribute__((always_inline)) { multi_serve_mfma<R>(d, t, k, tag, restage, lds.s, vmask, anyv); });
 }
 
 __global__ __launch_bounds__(kCommitThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_fill_multi_mfma_mixed(

@@ -174,6 +174,9 @@ struct WorkItem {
 // kMultiMaxItems of them.  Each slot's JobDev carries the tiling of the
 // dispatch's search form.
 constexpr int kMultiMaxItems = 64;
+// Iterations one persistent dispatch may run: its go words count them in
+// 25 bits (k + 1 < 2^25 - 1).
+constexpr int kMaxDispatchIters = (1 << 25) - 2;
 struct MultiPlan {
     const JobDev *slots;
     const int32_t *commit;

@@ -272,8 +272,8 @@ static int32_t check_params(int32_t W, int32_t H, const inpaint_params *p, std::
         *why = "unknown form";
         return INPAINT_INVALID_ARGUMENT;
     }
-    if (p->form != INPAINT_FORM_PLAIN && p->iters_per_check < 1) {
-        *why = "iters_per_check must be >= 1 in the stream and graph forms";
+    if (p->form != INPAINT_FORM_PLAIN && (p->iters_per_check < 1 || p->iters_per_check > kMaxDispatchIters)) {
+        *why = "iters_per_check must be in 1 .. 33554430 in the stream, graph and persistent forms";
         return INPAINT_INVALID_ARGUMENT;
     }
     if (p->log_capacity < -1) {
@@ -1491,7 +1491,8 @@ hipError_t plan_multi(inpaint_batch *b, int max_items, bool *fits) {
 extern "C" {
 
 int32_t inpaint_batch_create(const inpaint_batch_params *bp, void *hip_stream, inpaint_batch **out) {
-    if (!bp || !out || bp->capacity < 1 || bp->graph_iters < 1) return INPAINT_INVALID_ARGUMENT;
+    if (!bp || !out || bp->capacity < 1 || bp->graph_iters < 1 || bp->graph_iters > kMaxDispatchIters)
+        return INPAINT_INVALID_ARGUMENT;
     if (bp->form != 0 && bp->form != INPAINT_FORM_GRAPH && bp->form != INPAINT_FORM_PERSISTENT)
         return INPAINT_INVALID_ARGUMENT;
     inpaint_batch *b = new (std::nothrow) inpaint_batch();

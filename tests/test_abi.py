@@ -84,6 +84,12 @@ def test_library_loads_and_host_only_calls(so):
     p.alpha_den = 1
     p.reserved[0] = 3
     assert f(100, 100, ctypes.byref(p), ctypes.byref(b)) == -1
+    p.reserved[0] = 0
+    # iterations per dispatch: a persistent dispatch counts them in 25 bits
+    p.form = 3
+    for ipc, ok in ((1, True), ((1 << 25) - 2, True), ((1 << 25) - 1, False), (0, False)):
+        p.iters_per_check = ipc
+        assert (f(100, 100, ctypes.byref(p), ctypes.byref(b)) == 0) == ok, ipc
 
 
 def test_step_record_layout():
