@@ -6,13 +6,13 @@ fits the memory budget: both are reserved at once, and the job's context is
 prepared (upload and initialisation) on a worker thread with its own stream
 while the loop keeps stepping the running jobs.  A prepared job is attached to
 the running batch between two batch steps, in arrival order, once the engine
-has room for it (``GpuEngine``: every running image keeps its search tiles
-resident in the batched persistent dispatch, so each runs at about its solo
-iteration time; a job arriving at an empty batch always starts).  Every batch
-step advances every attached unfinished job by G fill iterations, so jobs that
-arrive while others run share the device with them.  Finished jobs are read back, detached and
-their memory released, which may admit queued jobs.  Latency is completion
-time minus arrival time.
+has room for it (an engine may gate this: ``GpuEngine(tiles_per_group=N)``
+attaches a job only while every search work-group of the batched persistent
+dispatch would hold at most N tiles; a job arriving at an empty batch always
+starts).  Every batch step advances every attached unfinished job by G fill
+iterations, so jobs that arrive while others run share the device with them.
+Finished jobs are read back, detached and their memory released, which may
+admit queued jobs.  Latency is completion time minus arrival time.
 
 The loop talks to an engine object; ``GpuEngine`` drives libinpaint through
 the binding, ``FakeEngine`` (tests) simulates iteration counts on the CPU.
