@@ -369,7 +369,9 @@ static bool spread_items_by_radius(const std::vector<WorkItem> &all, const std::
             used += g;
             rem.push_back({share - g, k++});
         }
-        std::sort(rem.begin(), rem.end(), [](auto &x, auto &y) { return x.first > y.first || (x.first == y.first && x.second < y.second); });
+        std::sort(rem.begin(), rem.end(), [](const auto &x, const auto &y) {
+            return x.first > y.first || (x.first == y.first && x.second < y.second);
+        });
         for (size_t q = 0; used < n_search; q = (q + 1) % rem.size(), ++used) groups[rem[q].second] += 1;
         while (used > n_search) {   // the floors of 1 overshot: take from the largest
             const int big = (int)(std::max_element(groups.begin(), groups.end()) - groups.begin());
