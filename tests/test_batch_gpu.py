@@ -176,3 +176,30 @@ def test_mixed_radii_beyond_resident_tiles_match_stored_oracle():
         assert_matches_golden(g, c.read_log(0, it), c.read_image(), jobs[i].name)
         c.close()
     batch.close()
+
+
+def test_persistent_batch_with_mixed_and_per_radius_dispatches():
+    # MFMA contexts of radius 2 and 5 share the mixed-radius dispatch; a
+    # radius-6 MFMA context and a radius-7 context (SIMT: past the MFMA
+    # form's radii) get a dispatch each.  Every image equals the oracle.
+    jobs = []
+    for seed, (W, H, r) in enumerate([(70, 60, 2), (96, 80, 5), (110, 90, 6), (120, 100, 7)]):
+        rng = np.random.default_rng(400 + seed)
+        rgb = rng.integers(0, 256, size=(H, W, 3)).astype(np.uint8)
+        mask = np.zeros((H, W), np.uint8)
+        mask[H // 3:H // 3 + H // 6, W // 3:W // 3 + W // 6] = 1
+        jobs.append(synth.Job(f"pr{seed}-r{r}", rgb, mask, r))
+    batch = B.Batch(capacity=len(jobs), graph_iters=8, autotune=False, form="persistent")
+    ctxs = [B.Inpainter(j.rgb, j.mask, j.patch_radius, path=B.PATH_MFMA if j.patch_radius <= 6 else B.PATH_SIMT)
+            for j in jobs]
+    for c in ctxs:
+        batch.attach(c)
+    steps = 0
+    while batch.step() > 0:
+        steps += 1
+        assert steps < 10_000
+    assert batch.last_form() == "persistent"
+    for j, c in zip(jobs, ctxs):
+        want_log, want_img = _oracle_result(j)
+        assert_logs_equal(c.read_log(0, len(want_log)), want_log, j.name)
+        assert (c.read_image() == want_img).all(), j.name
