@@ -202,7 +202,42 @@ def cpu_baseline(job, seconds):
                   f"oracle create excluded ({t_create:.2f}s)",
         "ms_per_iteration": round(1000 * dt / max(n, 1), 2),
         "host_cpu": _cpu_name(), "host_nproc": os.cpu_count(),
+        "all_cores": cpu_baseline_all_cores(job, 2.0, min(16, os.cpu_count() or 1), ncand),
     }
+
+
+def cpu_baseline_all_cores(job, seconds, threads, ncand):
+    """The same oracle on `threads` host threads at once, each running its own
+    copy of the removal from the start for `seconds` (the C oracle holds no
+    global state and ctypes releases the GIL during its calls): the host's
+    aggregate oracle rate."""
+    import threading
+    import oracle
+    olist = [None] * threads
+    counts = [0] * threads
+
+    def make(i):
+        olist[i] = oracle.Oracle(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, rect=job.rect)
+
+    def run(i):
+        t1 = time.perf_counter()
+        while time.perf_counter() - t1 < seconds:
+            if olist[i].step() is None:
+                break
+            counts[i] += 1
+
+    for fn in (make, run):
+        ts = [threading.Thread(target=fn, args=(i,)) for i in range(threads)]
+        t0 = time.perf_counter()
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        dt = time.perf_counter() - t0
+    n = sum(counts)
+    return {"value": round(n * ncand / dt, 1), "unit": "patch evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{threads} threads, each the first {min(counts)}-{max(counts)} fill iterations of its own "
+                      f"copy of the removal ({n * ncand} patch evals in {dt:.2f}s)"}
 
 
 def _cpu_name():
