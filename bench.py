@@ -180,6 +180,27 @@ def timed_removals(job, n_steps, n_warmup, form, iters_per_check, tile_rows, tim
                 candidates=cands, rect=rect, ws_bytes=ctxs[0].ws_bytes, run_form=run_form)
 
 
+def end_to_end_removal(job, form, iters_per_check, tile_rows, path, n=2):
+    """Wall time of whole removals from host buffers: create (upload and
+    initialisation), run, and read-back of the final image and the fill log,
+    each synchronised; the mean over n (after the timed region)."""
+    import torch
+    from paper_1403_4238_amd import binding as B
+    ts = []
+    for _ in range(n):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c = B.Inpainter(job.rgb, job.mask, job.patch_radius, job.search_mode, job.alpha, rect=job.rect, form=form,
+                        iters_per_check=iters_per_check, tile_rows=tile_rows, path=path_id(path))
+        st, it, _ = c.run()
+        c.read_image()
+        c.read_log(0, it)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+        c.close()
+    return round(1000 * sum(ts) / len(ts), 3)
+
+
 def cpu_baseline(job, seconds):
     """The oracle as it stands, single-threaded, on a prefix of the removal."""
     import oracle
@@ -714,7 +735,13 @@ def main():
             "workspace_bytes": res["ws_bytes"],
         },
         "ms_per_removal": round(ms_per_step, 3),
+        # the same removal from host buffers: create, upload and read-back included
+        "ms_per_removal_end_to_end": end_to_end_removal(job, a.form, a.iters_per_check, a.tile_rows, a.path),
         "iterations_per_s": round(sum(res["iters"]) / res["seconds"], 1),
+        # Eq. 4's terms (3 channels x known offsets) and the dense equivalent
+        # (3 x P^2 per candidate), per second over the timed removals
+        "algorithmic_terms_per_s": round(terms_per_removal * n_steps / res["seconds"], 1),
+        "dense_equivalent_terms_per_s": round(3 * (2 * r + 1) ** 2 * evals / res["seconds"], 1),
         "parity": (golden_check(job, a, log, res["image"]) if domain == ("original", "whole")
                    else "no stored oracle result for this candidate domain (parity: tests/test_domains_gpu.py)"),
         "roofline": {
