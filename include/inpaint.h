@@ -188,7 +188,9 @@ int32_t inpaint_workspace_bytes(int32_t width, int32_t height, const inpaint_par
  * inpaint_destroy.  hip_stream is a hipStream_t (NULL = default stream).
  * Synchronises.  Errors: INVALID_ARGUMENT (bad sizes or params, empty hole,
  * no known pixel, no valid source centre in the search rectangle),
- * OUT_OF_MEMORY (workspace too small), DEVICE. */
+ * OUT_OF_MEMORY (workspace too small), DEVICE (also when the hole the
+ * device counted in the uploaded mask, or its bounding box, differs from
+ * the caller's mask: the initialisation did not read the caller's bytes). */
 int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t mask_stride,
                        const inpaint_params *p, void *d_workspace, uint64_t ws_bytes,
                        void *hip_stream, inpaint_ctx **out);
@@ -285,6 +287,9 @@ int32_t inpaint_progress(inpaint_ctx *ctx, int64_t *iterations, int64_t *remaini
  *   - a filled pixel's confidence is not in [0, 1];
  *   - iterations < 0;
  *   - a pointer is NULL, channels is wrong or a stride is too small.
+ * DEVICE (sticky) if a kernel did not run to completion, or if the hole the
+ * device counted after the overlay differs from the caller's hole map (the
+ * import did not read the caller's bytes).
  * Synchronises. */
 int32_t inpaint_import_state(inpaint_ctx *ctx, const uint8_t *rgb, int32_t rgb_stride, int32_t channels,
                              const uint8_t *hole, int32_t hole_stride, const double *conf, int64_t iterations);

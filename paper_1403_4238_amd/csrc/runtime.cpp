@@ -82,6 +82,36 @@ bool sealed(const InitInfo &info, uint32_t nonce, uint32_t blocks) {
     return info.nonce == nonce && info.seal == nonce && (blocks == 0 || info.blocks == blocks);
 }
 
+// The nonzero bytes of a caller's W x H mask and their bounding box
+// (half-open).  Create and import compare the device's count (and box) of
+// the uploaded mask with these, so a pass that read anything but the
+// caller's bytes is reported as a device failure instead of being run.
+struct MaskStats {
+    int64_t count = 0;
+    int x0 = INT32_MAX, y0 = INT32_MAX, x1 = INT32_MIN, y1 = INT32_MIN;
+};
+static MaskStats mask_stats(const uint8_t *m, int stride, int W, int H) {
+    MaskStats r;
+    for (int y = 0; y < H; ++y) {
+        const uint8_t *row = m + (int64_t)y * stride;
+        int first = -1, last = -1;
+        int64_t c = 0;
+        for (int x = 0; x < W; ++x)
+            if (row[x]) {
+                if (first < 0) first = x;
+                last = x;
+                ++c;
+            }
+        if (c == 0) continue;
+        r.count += c;
+        r.x0 = std::min(r.x0, first);
+        r.x1 = std::max(r.x1, last + 1);
+        r.y0 = std::min(r.y0, y);
+        r.y1 = y + 1;
+    }
+    return r;
+}
+
 struct Layout {
     uint64_t img, gray, hole, hole0, vrad, conf, pcd, blk, partials, tgt, qtgt, srcw, srcq, srcp, vradp, hdist, st,
         sync, fslot, info, key, mplan, log, total;
@@ -498,6 +528,9 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
         return create_fail(nullptr, INPAINT_INVALID_ARGUMENT, "workspace not 256-byte aligned");
     const Layout L = make_layout(W, H, *p);
     if (ws_bytes < L.total) return create_fail(nullptr, INPAINT_OUT_OF_MEMORY, "workspace too small");
+    const MaskStats hm = mask_stats(mask, mask_stride, W, H);
+    if (hm.count == 0) return create_fail(nullptr, INPAINT_INVALID_ARGUMENT, "mask is empty");
+    if (hm.count >= (int64_t)W * H) return create_fail(nullptr, INPAINT_INVALID_ARGUMENT, "mask covers the whole image");
 
     inpaint_ctx *c = new (std::nothrow) inpaint_ctx();
     if (!c) return create_fail(nullptr, INPAINT_OUT_OF_MEMORY, "host allocation failed");
@@ -572,8 +605,10 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     std::memcpy(&info, c->h_key, sizeof(info));
     if (!sealed(info, nonce, init_pixel_blocks(d)))
         return create_fail(c, INPAINT_DEVICE, "init kernels did not run to completion (no error was reported)");
-    if (info.hole_count <= 0) return create_fail(c, INPAINT_INVALID_ARGUMENT, "mask is empty");
-    if (info.hole_count >= (int64_t)n) return create_fail(c, INPAINT_INVALID_ARGUMENT, "mask covers the whole image");
+    if (info.hole_count != hm.count || info.bx0 != hm.x0 || info.bx1 != hm.x1 || info.by0 != hm.y0 ||
+        info.by1 != hm.y1)
+        return create_fail(c, INPAINT_DEVICE, "the initialisation read a mask other than the caller's "
+                                              "(its upload had not landed)");
     c->hole0 = info.hole_count;
 
     // Search rectangle.
@@ -964,6 +999,7 @@ int32_t inpaint_import_state(inpaint_ctx *ctx, const uint8_t *rgb, int32_t rgb_s
     if (rgb_stride < W * channels || hole_stride < W)
         return ctx->fail(INPAINT_INVALID_ARGUMENT, "row stride smaller than a row");
     if (iterations < 0) return ctx->fail(INPAINT_INVALID_ARGUMENT, "iterations must be >= 0");
+    const MaskStats hm = mask_stats(hole, hole_stride, W, H);
     hipStream_t s = ctx->stream;
     // Staging in the priority-term plane (16 bytes per pixel, rebuilt below):
     // colours [0, 4n), hole [4n, 5n), row distances [5n, 6n), confidences [8n, 16n).
@@ -1000,6 +1036,11 @@ int32_t inpaint_import_state(inpaint_ctx *ctx, const uint8_t *rgb, int32_t rgb_s
     std::memcpy(&info, ctx->h_key, sizeof(info));
     if (!sealed(info, nonce2, init_pixel_blocks(d)))
         return ctx->hip_fail(hipErrorUnknown, "checkpoint import kernels did not run to completion");
+    // (the check passed: every hole pixel of the checkpoint is in the
+    // original hole, so the overlay counted all of them)
+    if (info.hole_count != hm.count)
+        return ctx->hip_fail(hipErrorUnknown, "the import read a hole map other than the caller's "
+                                              "(its upload had not landed)");
     IterState &h = *ctx->h_state;
     std::memset(&h, 0, sizeof(h));
     h.remaining = info.hole_count;
