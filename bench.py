@@ -60,17 +60,27 @@ HBM_PEAK_GBS = 8000.0
 # (`--workload copy`: FETCH x 2.0, WRITE x 1.0).  Each entry holds the hash of
 # the kernel's sources it was taken on; once they change it reports null.
 TRAFFIC_BYTES_PER_LAUNCH = {
-    ("k_fill_mfma<R=4>", "hd-1920x1080-p9-full"): {
+    ("k_fill_mfma<R=4>", "hd-1920x1080-p9-full", 128): {
         "bytes": 36393574, "fetch_kib": 16208.05, "write_kib": 3124.5,
+        "sources": ["inpaint_dev.h", "search_tile.h", "search_mfma_tile.h", "fill.hip"],
+        "sha256_16": "af19dc1c885c4e90"},
+    ("k_fill_mfma<R=4>", "hd-1920x1080-p9-full", 1024): {
+        "bytes": 70608384, "fetch_kib": 22792.69, "write_kib": 23368.12,
         "sources": ["inpaint_dev.h", "search_tile.h", "search_mfma_tile.h", "fill.hip"],
         "sha256_16": "af19dc1c885c4e90"},
 }
 
 
-def traffic_for(kernel, workload):
+def checks(a, form):
+    """Iterations per host check of a form: the persistent form's dispatch
+    length, or what the stream and graph forms enqueue per check."""
+    return a.dispatch_iters if form == "persistent" else a.iters_per_check
+
+
+def traffic_for(kernel, workload, iters_per_launch):
     """Calibrated HBM bytes per launch, or None if not measured on the
     current kernel sources."""
-    e = TRAFFIC_BYTES_PER_LAUNCH.get((kernel, workload))
+    e = TRAFFIC_BYTES_PER_LAUNCH.get((kernel, workload, iters_per_launch))
     if e is None:
         return None
     h = hashlib.sha256()
@@ -103,7 +113,10 @@ def parse():
     ap.add_argument("--window", action="store_true", help="alpha = 1 search window (3x the hole bbox)")
     ap.add_argument("--form", default="persistent", choices=["persistent", "stream", "plain"],
                     help="timed form (kernel events need a non-graph form)")
-    ap.add_argument("--iters-per-check", type=int, default=128)
+    ap.add_argument("--iters-per-check", type=int, default=128,
+                    help="stream / graph forms: iterations enqueued per host check")
+    ap.add_argument("--dispatch-iters", type=int, default=1024,
+                    help="persistent form: iterations per dispatch (one host check each)")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--path", default="mfma", choices=["mfma", "simt", "direct"],
                     help="exemplar-search kernel (direct: SIMT without LDS staging)")
@@ -115,6 +128,8 @@ def parse():
                     help="sweep: the persistent alpha x P timings, the LDS staging study, or both")
     ap.add_argument("--no-other-form", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-end-to-end", action="store_true",
+                    help="skip the removal from host buffers (create, upload, read-back)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
@@ -649,7 +664,7 @@ def main():
     if domain != ("original", "whole") and (a.path == "mfma" or a.form == "persistent"):
         sys.exit("the candidate-domain variants run on the SIMT search (--path simt|direct) in the "
                  "plain / stream / graph forms")
-    res = timed_removals(job, a.steps, a.warmup, a.form, a.iters_per_check, a.tile_rows, path=a.path,
+    res = timed_removals(job, a.steps, a.warmup, a.form, checks(a, a.form), a.tile_rows, path=a.path,
                          domain=domain)
     n_steps = a.steps
     evals = sum(res["iters"]) * res["candidates"]
@@ -688,7 +703,7 @@ def main():
         for name, form, opath in variants:
             if form == res["run_form"] and opath == a.path:
                 continue
-            o = timed_removals(job, 1, 0, form, a.iters_per_check, a.tile_rows, timing=(form != "graph"),
+            o = timed_removals(job, 1, 0, form, checks(a, form), a.tile_rows, timing=(form != "graph"),
                                path=opath, domain=domain)
             rec = {"ms_per_removal": round(1000 * o["seconds"], 2),
                    "patch_evals_per_s": round(sum(o["iters"]) * o["candidates"] / o["seconds"], 1),
@@ -727,7 +742,7 @@ def main():
                         f"{'int8-MFMA' if a.path == 'mfma' else 'SIMT dot4'} search, "
                         + ("" if domain == ("original", "whole") else
                            f"candidate domain {a.source_policy} sources / {a.scoring} scoring, ") +
-                        f"{res['run_form']} form" + (f" ({a.iters_per_check} iterations per host check)"
+                        f"{res['run_form']} form" + (f" ({checks(a, a.form)} iterations per host check)"
                                                      if a.form != "plain" else ""),
             "width": job.width, "height": job.height, "patch": 2 * r + 1,
             "search_rect": list(res["rect"]), "candidates_per_search": res["candidates"],
@@ -736,7 +751,8 @@ def main():
         },
         "ms_per_removal": round(ms_per_step, 3),
         # the same removal from host buffers: create, upload and read-back included
-        "ms_per_removal_end_to_end": end_to_end_removal(job, a.form, a.iters_per_check, a.tile_rows, a.path),
+        "ms_per_removal_end_to_end": (None if a.no_end_to_end else
+                                      end_to_end_removal(job, a.form, checks(a, a.form), a.tile_rows, a.path)),
         "iterations_per_s": round(sum(res["iters"]) / res["seconds"], 1),
         # Eq. 4's terms (3 channels x known offsets) and the dense equivalent
         # (3 x P^2 per candidate), per second over the timed removals
@@ -749,7 +765,7 @@ def main():
             "kernel": kernel,
             "achieved": round(OPS_PER_TERM * achieved / 1e12, 3), "peak": round(OPS_PER_TERM * peak / 1e12, 2),
             "unit": "TOP/s", "frac": round(achieved / peak, 5),
-            "traffic": traffic_for(kernel, job.name),
+            "traffic": traffic_for(kernel, job.name, checks(a, a.form)) if persistent else None,
             "avg_launch_us": round(1000 * avg_kernel_ms, 3), "launches_timed": res["searches"],
             "terms_per_launch": round(terms_per_launch),
             "min_hbm_bytes_per_launch": bytes_per_launch,

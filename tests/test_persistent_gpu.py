@@ -135,6 +135,24 @@ def test_hd_full_run_matches_stored_oracle(key, path):
         assert g.run_form() == "persistent"
 
 
+@pytest.mark.parametrize("dispatch_iters", [1024, 4096])
+def test_hd_long_dispatches_match_stored_oracle(dispatch_iters):
+    # The 1080p removal in the launch configuration the benchmark times:
+    # 1024 iterations per persistent dispatch (4 dispatches, the last one
+    # partial), and the whole removal in one dispatch.
+    gold = load_golden("hd9")
+    if gold is None:
+        pytest.skip("stored oracle result for hd9 not generated")
+    job = synth.hd(patch=9)
+    assert job.sha256() == gold["input_sha256"]
+    g = B.Inpainter(job.rgb, job.mask, job.patch_radius, form="persistent", iters_per_check=dispatch_iters,
+                    path=B.PATH_MFMA)
+    assert g.run_form() == "persistent"
+    st, n, log = g.run(log_cap=gold["iterations"] + 8)
+    assert st == B.DONE and n == gold["iterations"]
+    assert_matches_golden(gold, log, g.read_image(), f"hd9 persistent mfma, {dispatch_iters} per dispatch")
+
+
 @pytest.mark.parametrize("path", ["mfma", "simt"])
 def test_persistent_above_coresident_tiles_matches_stored_oracle(path):
     # 1992x1221, 7x7 patch: more search tiles (640 MFMA / 1248 SIMT) than
