@@ -98,3 +98,38 @@ def test_step_record_layout():
     assert STEP_DTYPE.itemsize == 64
     assert ctypes.sizeof(inpaint_params) == 4 * 16
     assert oracle.STEP_DTYPE.names == STEP_DTYPE.names
+
+
+def test_create_rejects_empty_and_full_masks_before_device_work(so):
+    # The caller's mask is counted on the host first: an empty or full mask
+    # is an argument error, returned before any upload or kernel (the
+    # workspace pointer below is host memory and is never used).
+    import numpy as np
+    from paper_1403_4238_amd.binding import inpaint_image, inpaint_params
+    L = ctypes.CDLL(so)
+    L.inpaint_create.argtypes = [ctypes.POINTER(inpaint_image), ctypes.c_void_p, ctypes.c_int32,
+                                 ctypes.POINTER(inpaint_params), ctypes.c_void_p, ctypes.c_uint64,
+                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    L.inpaint_last_error.restype = ctypes.c_char_p
+    L.inpaint_last_error.argtypes = [ctypes.c_void_p]
+    W, H = 40, 30
+    rgb = np.zeros((H, W, 3), np.uint8)
+    img = inpaint_image()
+    img.data = rgb.ctypes.data
+    img.width, img.height, img.channels, img.stride_bytes = W, H, 3, 3 * W
+    p = inpaint_params()
+    p.patch_radius = 2
+    p.alpha_den = 1
+    need = ctypes.c_uint64()
+    L.inpaint_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(inpaint_params),
+                                          ctypes.POINTER(ctypes.c_uint64)]
+    assert L.inpaint_workspace_bytes(W, H, ctypes.byref(p), ctypes.byref(need)) == 0
+    host = np.zeros(int(need.value) + 256, np.uint8)
+    ws = (host.ctypes.data + 255) // 256 * 256
+    out = ctypes.c_void_p()
+    for fill, why in ((0, b"mask is empty"), (1, b"mask covers the whole image")):
+        mask = np.full((H, W), fill, np.uint8)
+        st = L.inpaint_create(ctypes.byref(img), mask.ctypes.data, W, ctypes.byref(p), ws, need.value, None,
+                              ctypes.byref(out))
+        assert st == -1 and out.value is None
+        assert L.inpaint_last_error(None) == why
