@@ -880,7 +880,8 @@ int32_t inpaint_run(inpaint_ctx *ctx, int64_t max_iters, int64_t *iters_done, in
         if (ctx->prof) return ctx->fail(INPAINT_INVALID_ARGUMENT, "search timing is not available in the graph form");
         HIP_OR_FAIL(ctx, ensure_graph(ctx, G), "graph capture");
     } else if (ctx->prof) {
-        HIP_OR_FAIL(ctx, ensure_events(ctx, G), "events");
+        // (a persistent dispatch is timed as a whole: one pair)
+        HIP_OR_FAIL(ctx, ensure_events(ctx, form == INPAINT_FORM_PERSISTENT ? 1 : G), "events");
     }
     for (;;) {
         const int64_t before = ctx->h_state->iter;
