@@ -9,8 +9,10 @@ HBM when timing starts).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
                     [--form persistent|stream|plain] [--path mfma|simt]
-                    [--workload hd|vga|small|batch|serve|sweep|copy]
+                    [--workload hd|vga|small|big|batch|serve|sweep|copy|resume]
                     [--patch 9|13|17] [--window]
+                    [--dispatch-iters 1024] [--iters-per-check 128]
+                    [--no-other-form] [--no-cpu-baseline] [--no-end-to-end]
 
 Prints one JSON line.  Besides the headline it reports the other forms
 (stream = search and commit launches enqueued ahead, checked every few
