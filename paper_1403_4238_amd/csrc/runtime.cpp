@@ -82,6 +82,14 @@ bool sealed(const InitInfo &info, uint32_t nonce, uint32_t blocks) {
     return info.nonce == nonce && info.seal == nonce && (blocks == 0 || info.blocks == blocks);
 }
 
+// Host rows to a packed device buffer.  A 2D copy from pageable memory moves
+// every row separately (one transfer per row), so packed rows go as one copy.
+static hipError_t upload_rows(void *dst, size_t row_bytes, const void *src, size_t stride, int rows,
+                              hipStream_t s) {
+    if (stride == row_bytes) return hipMemcpyAsync(dst, src, row_bytes * rows, hipMemcpyHostToDevice, s);
+    return hipMemcpy2DAsync(dst, row_bytes, src, stride, row_bytes, rows, hipMemcpyHostToDevice, s);
+}
+
 // The nonzero bytes of a caller's W x H mask and their bounding box
 // (half-open).  Create and import compare the device's count (and box) of
 // the uploaded mask with these, so a pass that read anything but the
@@ -590,10 +598,8 @@ int32_t inpaint_create(const inpaint_image *img, const uint8_t *mask, int32_t ma
     uint8_t *stage_mask = stage_rgb + 4 * n;
     uint8_t *hdist = d.hdist ? d.hdist : stage_mask + n;
     hipStream_t s = c->stream;
-    hipError_t e = hipMemcpy2DAsync(stage_rgb, (size_t)W * ch, img->data, img->stride_bytes, (size_t)W * ch, H,
-                                    hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpy2DAsync(stage_mask, W, mask, mask_stride, W, H, hipMemcpyHostToDevice, s);
+    hipError_t e = upload_rows(stage_rgb, (size_t)W * ch, img->data, img->stride_bytes, H, s);
+    if (e == hipSuccess) e = upload_rows(stage_mask, W, mask, mask_stride, H, s);
     const uint32_t nonce = next_nonce();
     if (e == hipSuccess) e = launch_init(d, stage_rgb, ch, stage_mask, hdist, nonce, s);
     if (e == hipSuccess && d.mfma) e = launch_mfma_planes(d, s);
@@ -1008,9 +1014,8 @@ int32_t inpaint_import_state(inpaint_ctx *ctx, const uint8_t *rgb, int32_t rgb_s
     uint8_t *stage = (uint8_t *)d.pcd;
     uint8_t *s_rgb = stage, *s_hole = stage + 4 * n, *s_hdist = stage + 5 * n;
     double *s_conf = (double *)(stage + 8 * n);
-    HIP_OR_FAIL(ctx, hipMemcpy2DAsync(s_rgb, (size_t)W * channels, rgb, rgb_stride, (size_t)W * channels, H,
-                                      hipMemcpyHostToDevice, s), "upload");
-    HIP_OR_FAIL(ctx, hipMemcpy2DAsync(s_hole, W, hole, hole_stride, W, H, hipMemcpyHostToDevice, s), "upload");
+    HIP_OR_FAIL(ctx, upload_rows(s_rgb, (size_t)W * channels, rgb, rgb_stride, H, s), "upload");
+    HIP_OR_FAIL(ctx, upload_rows(s_hole, W, hole, hole_stride, H, s), "upload");
     HIP_OR_FAIL(ctx, hipMemcpyAsync(s_conf, conf, 8 * n, hipMemcpyHostToDevice, s), "upload");
     const uint32_t nonce = next_nonce();
     HIP_OR_FAIL(ctx, launch_import_check(d, s_hole, s_conf, nonce, s), "check");

@@ -458,3 +458,43 @@ def test_direct_vga_full_run_matches_stored_oracle():
     st, n, log = g.run(log_cap=gold["iterations"] + 8)
     assert st == B.DONE
     assert_matches_golden(gold, log, g.read_image(), "vga direct")
+
+
+def test_create_from_padded_rows_equals_packed_rows():
+    # Rows with padding between them go through the strided upload; packed
+    # rows (what the binding passes) through one copy.  Both must initialise
+    # the same state: the whole removal and its final image are identical,
+    # and both equal the oracle.
+    import ctypes
+    import torch
+    job = synth.small()
+    H, W, _ = job.rgb.shape
+    want = oracle.Oracle(job.rgb, job.mask, job.patch_radius).run()
+    ref = B.Inpainter(job.rgb, job.mask, job.patch_radius, form="persistent", iters_per_check=64)
+    st, n, log_ref = ref.run(log_cap=len(want) + 4)
+    assert st == B.DONE
+    assert_logs_equal(log_ref, want, "packed rows")
+    rgb_pad = np.zeros((H, 3 * W + 13), np.uint8)
+    rgb_pad[:, :3 * W] = job.rgb.reshape(H, 3 * W)
+    rgb_pad[:, 3 * W:] = 77            # padding bytes must be ignored
+    mask_pad = np.full((H, W + 7), 1, np.uint8)
+    mask_pad[:, :W] = job.mask
+    g = B.Inpainter.__new__(B.Inpainter)
+    g.params = B.make_params(job.patch_radius, B.SEARCH_FULL, (0, 1), (0, 0, 0, 0), B.PATH_AUTO, "persistent",
+                             64, int(job.mask.sum()), 0, B.SOURCE_ORIGINAL, B.SCORE_WHOLE)
+    g.width, g.height = W, H
+    g.ws_bytes = B.inpaint_workspace_bytes(W, H, g.params)
+    g.workspace = torch.empty(g.ws_bytes, dtype=torch.uint8, device="cuda")
+    g.stream = torch.cuda.current_stream()
+    img = B.inpaint_image(rgb_pad.ctypes.data, W, H, rgb_pad.shape[1], 3)
+    h = ctypes.c_void_p()
+    st = B.lib().inpaint_create(ctypes.byref(img), mask_pad.ctypes.data, mask_pad.shape[1], ctypes.byref(g.params),
+                                g.workspace.data_ptr(), g.ws_bytes, g.stream.cuda_stream, ctypes.byref(h))
+    assert st == B.OK, B.inpaint_last_error(None)
+    g.ctx = h
+    st, n2, log_pad = g.run(log_cap=len(want) + 4)
+    assert st == B.DONE and n2 == n
+    assert_logs_equal(log_pad, want, "padded rows")
+    assert (g.read_image() == ref.read_image()).all()
+    g.close()
+    ref.close()
